@@ -1,0 +1,173 @@
+/*
+ * libgks: the gas-kinetic scheme (GKS) time step for Maxwell's equations on one AMD MI355X GPU.
+ *
+ * The method is the discrete-velocity GKS of "A Gas-Kinetic Scheme for Maxwell Equations"
+ * (Pu, Long, Xu): a finite-volume update of cell averages (Sec. 3.1, cell-average update)
+ * whose interface fluxes are the time averages over one step of the integral solution of the
+ * vector BGK model (Sec. 3.1, numerical flux with coefficients C1..C5), built from the
+ * D2Q4 / D3Q4 lattice equilibria (Sec. 2.2) in the face-local frame.
+ *
+ * Conventions for every entry point
+ *   - Plain C ABI: pointers and sizes only.  Every call returns a gks_status; 0 is success,
+ *     a negative value an error whose text gks_last_error() returns.  No call throws, exits
+ *     or aborts.
+ *   - Pointers documented as "device" must be device memory of the GPU the context was
+ *     created on; "host" pointers are ordinary CPU memory.
+ *   - Field arrays are structure-of-arrays, [batch][field][cell], x fastest on Cartesian
+ *     grids (cell = ix + nx*(iy + ny*iz)).  Fields: TM2D (Ez, Hx, Hy); EM3D (Ex, Ey, Ez, Hx,
+ *     Hy, Hz).  Units have c = eps0 = mu0 = 1 (Sec. 5), so H and B coincide in vacuum.
+ *   - The element type is double for GKS_FP64 contexts and float for GKS_FP32 contexts
+ *     (in FP32 the flux arithmetic is single precision and the per-cell sum of face fluxes
+ *     and its addition to the old value are double precision, rounded once on store).
+ *   - All GPU work is enqueued on the stream given to gks_init_mesh and runs asynchronously,
+ *     except the calls that return host values (gks_energy, gks_probe_energy, gks_run with an
+ *     energy buffer), which synchronise that stream.
+ *   - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef GKS_H
+#define GKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gks_ctx gks_ctx;
+
+typedef enum {
+    GKS_OK = 0,
+    GKS_EINVAL = -1,      /* bad argument (checked on the host before any launch) */
+    GKS_ENOMEM = -2,      /* device or host allocation failed */
+    GKS_EDEVICE = -3,     /* a HIP call failed */
+    GKS_EUNSTABLE = -4,   /* energy grew beyond the stability threshold */
+    GKS_ENONFINITE = -5,  /* energy is NaN or infinite */
+    GKS_ESTATE = -6       /* call not valid in the context's state */
+} gks_status;
+
+typedef enum { GKS_CART2D = 0, GKS_CART3D = 1, GKS_TRI2D = 2 } gks_mesh_kind;
+typedef enum { GKS_TM2D = 0, GKS_EM3D = 1 } gks_model;
+typedef enum { GKS_BC_PERIODIC = 0, GKS_BC_NONREFLECT = 1, GKS_BC_PEC = 2 } gks_bc;
+typedef enum { GKS_FP64 = 0, GKS_FP32 = 1 } gks_precision;
+
+/*
+ * Mesh description (host memory; copied by gks_init_mesh, not retained).
+ *   Cartesian (GKS_CART2D with GKS_TM2D, GKS_CART3D with GKS_EM3D): n[3] cells per axis
+ *   (n[2] = 1 in 2D), box [lo, hi], bc[6] = x-, x+, y-, y+, z-, z+ sides (the z entries are
+ *   ignored in 2D).  A periodic axis must be periodic on both sides.
+ *   Triangles (GKS_TRI2D with GKS_TM2D): nverts vertices vert_xy[2*v], ncells triangles
+ *   cell_verts[3*c], nfaces edges face_cells[2*s] = (owner, neighbour) with neighbour < 0
+ *   meaning a boundary edge of type -(1 + gks_bc) (non-reflecting or PEC), and
+ *   face_verts[2*s] = the edge's two vertices.
+ *   batch: number of independent problems sharing the mesh (fields and materials carry a
+ *   leading batch axis).
+ */
+typedef struct {
+    int32_t kind, model, precision;
+    int64_t batch;
+    int64_t n[3];
+    double lo[3], hi[3];
+    int32_t bc[6];
+    int64_t ncells, nfaces, nverts;
+    const double *vert_xy;
+    const int32_t *cell_verts;
+    const int32_t *face_cells;
+    const int32_t *face_verts;
+} gks_mesh_desc;
+
+/*
+ * Scheme parameters (host memory, copied).
+ *   c:            lattice speed = speed of light (> 0).
+ *   cfl, dt:      dt > 0 is used as given; otherwise dt = cfl * h / c with h the smallest
+ *                 cell width (Cartesian) or the smallest 2|Omega|/perimeter (triangles).
+ *   tau_over_dt:  collision time tau = tau_over_dt * dt (>= 0; +INFINITY = collisionless).
+ *   energy_every: gks_run records the energy every this many steps (0 = never).
+ *   unstable_growth: gks_run fails with GKS_EUNSTABLE when a recorded energy exceeds this
+ *                 factor times the first recorded one (0 = no check).
+ */
+typedef struct {
+    double c;
+    double cfl;
+    double dt;
+    double tau_over_dt;
+    int32_t energy_every;
+    double unstable_growth;
+} gks_params;
+
+/* Creates a context on the current HIP device.  hip_stream: a hipStream_t (NULL = the null
+ * stream) on which every later call enqueues its work.  *out receives the context; on error
+ * *out is NULL. */
+gks_status gks_init_mesh(const gks_mesh_desc *mesh, const gks_params *params, void *hip_stream,
+                         gks_ctx **out);
+
+/* Releases the context and everything it owns (NULL is accepted). */
+gks_status gks_destroy(gks_ctx *ctx);
+
+/* Text of the last error on this context (or of the last failed gks_init_mesh when ctx is
+ * NULL).  Owned by the library, valid until the next call on the context. */
+const char *gks_last_error(const gks_ctx *ctx);
+
+/* The time step in use and the five coefficients C1..C5 of the time-integrated flux
+ * (Sec. 3.1) as computed in double precision on the host. */
+gks_status gks_get_dt(const gks_ctx *ctx, double *dt_out);
+gks_status gks_flux_coefficients(double dt, double tau, double C_out[5]);
+
+/*
+ * Per-cell material maps (device, element type of the context, [batch][ncells]):
+ * epsinv = 1/eps, muinv = 1/mu; NULL means 1 (vacuum).  The pointers are retained and read
+ * by every later step until the next call: the caller keeps the memory alive.
+ * Materials are absent from the paper; the library scales the cell update by 1/eps, 1/mu
+ * and the equilibrium time derivative at a face by the face average of 1/eps, 1/mu.
+ */
+gks_status gks_set_material(gks_ctx *ctx, const void *epsinv, const void *muinv);
+
+/*
+ * Point current source (Sec. 2.1 source term S = (-J, 0)): on each listed cell (host
+ * arrays cells[n], weight[n]) J_z(t) = weight * J0 * exp(-((t - t0)/sigma_t)^2), applied
+ * explicitly at t^n in every batch item.  n = 0 removes the source.  At most 4096 cells.
+ */
+gks_status gks_set_point_source(gks_ctx *ctx, int64_t n, const int64_t *cells, const double *weight,
+                                double J0, double t0, double sigma_t);
+
+/*
+ * One explicit step from time t_n (Sec. 3.1): U_out = Phi(U_in).  U_in, U_out: device,
+ * [batch][nfields][ncells], must not overlap (GKS_EINVAL otherwise).
+ */
+gks_status gks_step(gks_ctx *ctx, const void *U_in, void *U_out, double t_n);
+
+/*
+ * nsteps steps in place on U (device) starting at t0 (t^n = t0 + n dt), ping-ponging with a
+ * library-owned buffer.  energy_host: NULL, or host memory for (nsteps / energy_every) x batch
+ * doubles receiving W = 1/2 sum |Omega| (eps |E|^2 + mu |H|^2) after every energy_every-th
+ * step; when given, a NaN/Inf energy returns GKS_ENONFINITE and growth beyond
+ * unstable_growth returns GKS_EUNSTABLE (U then holds the state at that check).
+ */
+gks_status gks_run(gks_ctx *ctx, void *U, int64_t nsteps, double t0, double *energy_host);
+
+/*
+ * Reverse-mode adjoint of one gks_step (the step is linear in U for fixed materials):
+ *   lam_n   = (dPhi/dU)^T lam_np1                  (device, field type, [batch][nf][ncells])
+ *   g_epsinv += (dPhi/d epsinv)^T lam_np1           (device, double, [batch][ncells]; nullable)
+ *   g_muinv  += (dPhi/d muinv)^T lam_np1            (device, double, [batch][ncells]; nullable)
+ * U_n is the state the forward step started from (device, field type).  lam_n must not
+ * overlap lam_np1 or U_n.  Cartesian 2D TM contexts only (GKS_ESTATE otherwise).
+ */
+gks_status gks_adjoint_step(gks_ctx *ctx, const void *U_n, const void *lam_np1, void *lam_n,
+                            double *g_epsinv, double *g_muinv, double t_n);
+
+/* Energy W = 1/2 sum_i |Omega_i| (eps_i |E_i|^2 + mu_i |H_i|^2) of each batch item, summed in
+ * double precision in a fixed order; out_host: host, [batch].  Synchronises the stream. */
+gks_status gks_energy(gks_ctx *ctx, const void *U, double *out_host);
+
+/* Probe-box field energy sum_{cells in box} |Omega| Ez^2 of each batch item (Cartesian only;
+ * box = [i0, i1) x [j0, j1) x [k0, k1) cell indices, host int64[6]); out_host: host, [batch]. */
+gks_status gks_probe_energy(gks_ctx *ctx, const void *U, const int64_t *box, double *out_host);
+
+/* Gradient of gks_probe_energy with respect to U: lam = 2 |Omega| Ez on the box cells, 0
+ * elsewhere (device, field type, [batch][nf][ncells]); the seed of an adjoint sweep. */
+gks_status gks_probe_energy_grad(gks_ctx *ctx, const void *U, const int64_t *box, void *lam);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GKS_H */

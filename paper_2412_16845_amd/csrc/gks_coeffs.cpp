@@ -1,0 +1,273 @@
+// Host-side coefficient algebra of the GKS interface flux.
+//
+// The kernels never evaluate the kinetic moments.  The interface flux of Sec. 3.1 is linear in
+// the left/right face states and slopes for a fixed face material, so for a Cartesian face it
+// is a sparse linear form of the stencil values:
+//     Phi = K0 w + (1/eps_s) KE w + (1/mu_s) KH w,      Phi = (dt/h_n) * F~   (local frame)
+// with w the left/right cell values and their central half-differences along the local axes
+// (TM: 18 inputs, EM: 48 inputs).  This file evaluates the closed-form moments of the D2Q4 /
+// D3Q4 lattices in double precision and probes them with unit vectors to obtain K0, KE, KH.
+// The kernels carry only the structurally non-zero entries (the tables in gks_pattern.h); the
+// probe checks that every other entry is exactly zero, so a wrong table cannot go unnoticed.
+#include "gks_internal.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+namespace gks {
+
+// ------------------------------------------------------------------ C1..C5 (Sec. 3.1)
+// C1 = dt - tau(1-e), C2 = tau(-dt + 2 tau (1-e) - dt e), C3 = dt^2/2 - tau dt + tau^2 (1-e),
+// C4 = tau (1-e), C5 = tau^2 (1-e) - tau dt e, e = exp(-dt/tau).  For x = dt/tau < 1 the
+// closed forms cancel badly, so their power series in x are summed instead.
+void flux_coefficients(double dt, double tau, double C[5])
+{
+    if (tau == 0.0) {
+        C[0] = dt; C[1] = 0.0; C[2] = 0.5 * dt * dt; C[3] = 0.0; C[4] = 0.0;
+        return;
+    }
+    if (std::isinf(tau)) {
+        C[0] = 0.0; C[1] = 0.0; C[2] = 0.0; C[3] = dt; C[4] = 0.5 * dt * dt;
+        return;
+    }
+    const double x = dt / tau, d2 = dt * dt;
+    if (x >= 1.0) {
+        const double em1 = -std::expm1(-x), e = std::exp(-x);
+        C[0] = dt * (1.0 - em1 / x);
+        C[1] = d2 * ((2.0 * em1 - x * (1.0 + e)) / (x * x));
+        C[2] = d2 * (0.5 - 1.0 / x + em1 / (x * x));
+        C[3] = dt * (em1 / x);
+        C[4] = d2 * ((em1 - x * e) / (x * x));
+        return;
+    }
+    // series in x (m >= 0, f1 = (m+1)!, f2 = (m+2)!):
+    //   C1/dt  = sum_{m>=1} (-1)^{m+1} x^m / f1     C4/dt  = sum_{m>=0} (-1)^m x^m / f1
+    //   C3/dt2 = sum_{m>=1} (-1)^{m+1} x^m / f2     C5/dt2 = sum_{m>=0} (-1)^m (m+1) x^m / f2
+    //   C2/dt2 = sum_{m>=1} (-1)^m m x^m / f2
+    double s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0;
+    double xm = 1.0, f1 = 1.0, f2 = 2.0;
+    for (int m = 0; m <= 40; ++m) {
+        if (m > 0) { xm *= x; f1 *= (m + 1); f2 *= (m + 2); }
+        const double sg = (m % 2 == 0) ? 1.0 : -1.0;
+        s4 += sg * xm / f1;
+        s5 += sg * (m + 1) * xm / f2;
+        if (m >= 1) {
+            s1 -= sg * xm / f1;
+            s3 -= sg * xm / f2;
+            s2 += sg * m * xm / f2;
+        }
+    }
+    C[0] = dt * s1; C[1] = d2 * s2; C[2] = d2 * s3; C[3] = dt * s4; C[4] = d2 * s5;
+}
+
+// ------------------------------------------------------------------ closed-form moments
+// Directional fluxes of the Maxwell system with chi = gamma = 0 (Sec. 2.1), six components.
+static void F1(const double *V, double c, double *o)
+{
+    const double c2 = c * c;
+    o[0] = 0; o[1] = c2 * V[5]; o[2] = -c2 * V[4]; o[3] = 0; o[4] = -V[2]; o[5] = V[1];
+}
+static void F2(const double *V, double c, double *o)
+{
+    const double c2 = c * c;
+    o[0] = -c2 * V[5]; o[1] = 0; o[2] = c2 * V[3]; o[3] = V[2]; o[4] = 0; o[5] = -V[0];
+}
+static void F3(const double *V, double c, double *o)
+{
+    const double c2 = c * c;
+    o[0] = c2 * V[4]; o[1] = -c2 * V[3]; o[2] = 0; o[3] = -V[1]; o[4] = V[0]; o[5] = 0;
+}
+
+// Closed-form GKS flux dt*F~ in the face frame (normal = local axis 1) from the reconstructed
+// states Ul, Ur and the physical slopes sl[j], sr[j] along the local axes, for the D2Q4
+// (dim 2; sl[2], sr[2] ignored) or D3Q4 (dim 3) lattice:
+//   half moments      <g(V)>_{+-} = V/2 +- F1(V)/(2c),   <u1 g(V)>_{+-} = +-cV/2 + F1(V)/2
+//   slope moments     Q(s)  = <u1 u.grad g> = c^2 s1 (+ c [F3(s2) + F2(s3)] on D3Q4)
+//                     Q+-(s) = c^2 s1/2 +- c F1(s1)/2 +- c F2(s2)/2           (D2Q4)
+//                     Q+(s) = c^2 s1/2 + c F1(s1)/2 + c [F2(s2)+F3(s2)+F2(s3)+F3(s3)]/2
+//                     Q-(s) = c^2 s1/2 - c F1(s1)/2 + c [F3(s2)-F2(s2)+F2(s3)-F3(s3)]/2   (D3Q4)
+//   dt F~ = C1 F1(U0) + C2 Q(grad U0) + C3 F1(U_t) + C4 [<u1 g^l>_+ + <u1 g^r>_-]
+//           - C5 [Q+(grad U^l) + Q-(grad U^r)]
+// with U0 = <g^l>_+ + <g^r>_-, grad U0 likewise, U_t = -M_s^{-1} sum_j F_j(d_j U0).
+static void closed_flux(int dim, double c, const double C[5], const double *Ul, const double *Ur,
+                        const double sl[3][6], const double sr[3][6], double mE, double mH, double *out)
+{
+    double a[6], b[6], t[6], U0[6], s0[3][6];
+    F1(Ul, c, a);
+    F1(Ur, c, b);
+    for (int f = 0; f < 6; ++f) U0[f] = 0.5 * (Ul[f] + Ur[f]) + (a[f] - b[f]) / (2 * c);
+    const int nd = dim;
+    for (int j = 0; j < 3; ++j) {
+        if (j >= nd) { std::memset(s0[j], 0, sizeof s0[j]); continue; }
+        F1(sl[j], c, a);
+        F1(sr[j], c, b);
+        for (int f = 0; f < 6; ++f) s0[j][f] = 0.5 * (sl[j][f] + sr[j][f]) + (a[f] - b[f]) / (2 * c);
+    }
+    auto Q = [&](const double s[3][6], int half, double *o) {
+        double p1[6], p2[6], p3[6], q2[6], q3[6];
+        F1(s[0], c, p1);
+        F2(s[1], c, p2);
+        F3(s[1], c, p3);
+        F2(s[2], c, q2);
+        F3(s[2], c, q3);
+        for (int f = 0; f < 6; ++f) {
+            if (half == 0) {
+                o[f] = c * c * s[0][f] + (nd == 3 ? c * (p3[f] + q2[f]) : 0.0);
+            } else {
+                const double h = (half > 0) ? 1.0 : -1.0;
+                double v = 0.5 * c * c * s[0][f] + h * 0.5 * c * p1[f];
+                if (nd == 2) v += h * 0.5 * c * p2[f];
+                else if (half > 0) v += 0.5 * c * (p2[f] + p3[f] + q2[f] + q3[f]);
+                else v += 0.5 * c * (p3[f] - p2[f] + q2[f] - q3[f]);
+                o[f] = v;
+            }
+        }
+    };
+    double Ut[6] = {0}, Fj[6];
+    F1(s0[0], c, Fj);
+    for (int f = 0; f < 6; ++f) Ut[f] -= Fj[f];
+    F2(s0[1], c, Fj);
+    for (int f = 0; f < 6; ++f) Ut[f] -= Fj[f];
+    if (nd == 3) {
+        F3(s0[2], c, Fj);
+        for (int f = 0; f < 6; ++f) Ut[f] -= Fj[f];
+    }
+    for (int f = 0; f < 3; ++f) Ut[f] *= mE;
+    for (int f = 3; f < 6; ++f) Ut[f] *= mH;
+
+    double m1[6], m2[6], m3[6], ql[6], qr[6];
+    F1(U0, c, m1);
+    Q(s0, 0, m2);
+    F1(Ut, c, m3);
+    Q(sl, +1, ql);
+    Q(sr, -1, qr);
+    F1(Ul, c, a);
+    F1(Ur, c, b);
+    for (int f = 0; f < 6; ++f) {
+        const double m4 = 0.5 * c * (Ul[f] - Ur[f]) + 0.5 * (a[f] + b[f]);
+        out[f] = C[0] * m1[f] + C[1] * m2[f] + C[2] * m3[f] + C[3] * m4 - C[4] * (ql[f] + qr[f]);
+    }
+}
+
+// ------------------------------------------------------------------ Cartesian face operators
+// Inputs w (local frame): TM2D (E,X,Y) = components (2,3,4):
+//   [UL(3) UR(3) d1L(3) d2L(3) d1R(3) d2R(3)]          d_j = h_j * (central slope along j)
+// EM3D: [UL(6) UR(6) d1L(6) d2L(6) d3L(6) d1R(6) d2R(6) d3R(6)]
+// Reconstruction on a Cartesian grid: U^l = UL + d1L/2, U^r = UR - d1R/2 (Sec. 3.1, linear
+// reconstruction with the Green-Gauss = central-difference gradient).
+static void cart_flux_eval(int model, double c, const double C[5], double dt, const double h[3],
+                           const double *w, double mE, double mH, double *phi)
+{
+    const int nf = (model == GKS_TM2D) ? 3 : 6;
+    const int nd = (model == GKS_TM2D) ? 2 : 3;
+    static const int tm[3] = {2, 3, 4};
+    double UL[6] = {0}, UR[6] = {0}, dL[3][6] = {{0}}, dR[3][6] = {{0}};
+    for (int q = 0; q < nf; ++q) {
+        const int f = (nf == 3) ? tm[q] : q;
+        UL[f] = w[q];
+        UR[f] = w[nf + q];
+        for (int j = 0; j < nd; ++j) {
+            dL[j][f] = w[2 * nf + j * nf + q];
+            dR[j][f] = w[2 * nf + nd * nf + j * nf + q];
+        }
+    }
+    double Ul[6], Ur[6], sl[3][6] = {{0}}, sr[3][6] = {{0}};
+    for (int f = 0; f < 6; ++f) {
+        Ul[f] = UL[f] + 0.5 * dL[0][f];
+        Ur[f] = UR[f] - 0.5 * dR[0][f];
+        for (int j = 0; j < nd; ++j) {
+            sl[j][f] = dL[j][f] / h[j];
+            sr[j][f] = dR[j][f] / h[j];
+        }
+    }
+    double out[6];
+    closed_flux(nd, c, C, Ul, Ur, sl, sr, mE, mH, out);
+    for (int q = 0; q < nf; ++q) {
+        const int f = (nf == 3) ? tm[q] : q;
+        phi[q] = out[f] / h[0];     // (dt/h_n) F~ = (dt F~)/h_n
+    }
+}
+
+// Face operator on reconstructed states (triangles): inputs [Ul(3) Ur(3) s1l s2l s1r s2r] with
+// physical slopes; output dt * F~ (the caller scales by |l_s|/|Omega_i|).
+static void face_flux_eval(double c, const double C[5], const double *w, double mE, double mH, double *phi)
+{
+    static const int tm[3] = {2, 3, 4};
+    double Ul[6] = {0}, Ur[6] = {0}, sl[3][6] = {{0}}, sr[3][6] = {{0}};
+    for (int q = 0; q < 3; ++q) {
+        const int f = tm[q];
+        Ul[f] = w[q];
+        Ur[f] = w[3 + q];
+        sl[0][f] = w[6 + q];
+        sl[1][f] = w[9 + q];
+        sr[0][f] = w[12 + q];
+        sr[1][f] = w[15 + q];
+    }
+    double out[6];
+    closed_flux(2, c, C, Ul, Ur, sl, sr, mE, mH, out);
+    for (int q = 0; q < 3; ++q) phi[q] = out[tm[q]];
+}
+
+// Probe a linear evaluator into dense K0/KE/KH and compress to the pattern tables.
+template <typename Eval>
+static bool probe(int nout, int nin, Eval ev, const Pattern &pat, double *k0, double *ke, double *kh,
+                  char *err, size_t errlen)
+{
+    std::vector<double> D0(nout * nin), DE(nout * nin), DH(nout * nin);
+    std::vector<double> w(nin, 0.0), phi(nout);
+    for (int i = 0; i < nin; ++i) {
+        w.assign(nin, 0.0);
+        w[i] = 1.0;
+        ev(w.data(), 0.0, 0.0, phi.data());
+        for (int r = 0; r < nout; ++r) D0[r * nin + i] = phi[r];
+        ev(w.data(), 1.0, 0.0, phi.data());
+        for (int r = 0; r < nout; ++r) DE[r * nin + i] = phi[r] - D0[r * nin + i];
+        ev(w.data(), 0.0, 1.0, phi.data());
+        for (int r = 0; r < nout; ++r) DH[r * nin + i] = phi[r] - D0[r * nin + i];
+    }
+    auto compress = [&](std::vector<double> &D, int nnz, const uint8_t *row, const uint8_t *col,
+                        double *k, const char *name) {
+        for (int q = 0; q < nnz; ++q) {
+            k[q] = D[row[q] * nin + col[q]];
+            D[row[q] * nin + col[q]] = 0.0;
+        }
+        for (int e = 0; e < nout * nin; ++e)
+            if (D[e] != 0.0) {
+                std::snprintf(err, errlen, "internal: %s entry (%d,%d) = %g outside the sparsity table",
+                              name, e / nin, e % nin, D[e]);
+                return false;
+            }
+        return true;
+    };
+    return compress(D0, pat.n0, pat.r0, pat.c0, k0, "K0") && compress(DE, pat.nE, pat.rE, pat.cE, ke, "KE") &&
+           compress(DH, pat.nH, pat.rH, pat.cH, kh, "KH");
+}
+
+bool cart_face_operator(int model, double c, const double C[5], double dt, const double h[3], double *k0,
+                        double *ke, double *kh, char *err, size_t errlen)
+{
+    const int nf = (model == GKS_TM2D) ? 3 : 6;
+    const int nin = (model == GKS_TM2D) ? 18 : 48;
+    const Pattern &pat = (model == GKS_TM2D) ? pattern_tm() : pattern_em();
+    auto ev = [&](const double *w, double mE, double mH, double *phi) {
+        cart_flux_eval(model, c, C, dt, h, w, mE, mH, phi);
+    };
+    return probe(nf, nin, ev, pat, k0, ke, kh, err, errlen);
+}
+
+bool tri_face_operator(double c, const double C[5], double *k0, double *ke, double *kh, char *err, size_t errlen)
+{
+    auto ev = [&](const double *w, double mE, double mH, double *phi) { face_flux_eval(c, C, w, mE, mH, phi); };
+    return probe(3, 18, ev, pattern_tm(), k0, ke, kh, err, errlen);
+}
+
+}  // namespace gks
+
+extern "C" gks_status gks_flux_coefficients(double dt, double tau, double C_out[5])
+{
+    if (!C_out || !(dt > 0.0) || !std::isfinite(dt) || !(tau >= 0.0)) return GKS_EINVAL;
+    gks::flux_coefficients(dt, tau, C_out);
+    return GKS_OK;
+}

@@ -1,0 +1,504 @@
+// Host runtime of libgks: the C ABI of include/gks.h.
+//
+// Responsibilities: argument validation before any launch, the time step, the coefficients
+// C1..C5 of the time-integrated flux (Sec. 3.1) and the sparse face operators derived from
+// them, device buffers owned by a context (ping-pong state for gks_run, reduction scratch,
+// source lists), kernel launches on the caller's stream, and error reporting.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "gks_internal.h"
+
+using namespace gks;
+
+struct gks_ctx {
+    int32_t kind = 0, model = 0, prec = 0;
+    int64_t batch = 1;
+    int64_t n[3] = {1, 1, 1};
+    double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1}, h[3] = {1, 1, 1};
+    int32_t bc[6] = {0, 0, 0, 0, 0, 0};
+    int64_t ncell = 0;
+    int32_t nfields = 3;
+    double c = 1, dt = 0, tau = 0, C[5] = {0, 0, 0, 0, 0};
+    int32_t energy_every = 0;
+    double unstable_growth = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    const void *epsinv = nullptr, *muinv = nullptr;
+
+    // face operators in double precision: [orientation][...]
+    double k0[3][EM_N0], ke[3][EM_NE], kh[3][EM_NH];
+
+    // point sources
+    std::vector<int64_t> src_cells;
+    std::vector<double> src_w;
+    double J0 = 0, t0 = 0, sigma_t = 1;
+    int64_t *d_src_cells = nullptr;
+    double *d_src_w = nullptr;
+
+    // owned device buffers
+    void *pingpong = nullptr;
+    size_t pingpong_bytes = 0;
+    double *d_partial = nullptr;
+    int32_t nblk = 0;
+    double *d_out = nullptr;        // energy records
+    size_t d_out_count = 0;
+    double *h_out = nullptr;        // pinned host mirror
+    size_t h_out_count = 0;
+
+    std::string err;
+};
+
+static thread_local std::string g_init_error;
+
+namespace {
+
+gks_status fail(gks_ctx *ctx, gks_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_init_error = buf;
+    return st;
+}
+
+gks_status hip_fail(gks_ctx *ctx, int e, const char *what)
+{
+    return fail(ctx, GKS_EDEVICE, "%s: %s", what, hipGetErrorString((hipError_t)e));
+}
+
+size_t elem_size(const gks_ctx *x) { return x->prec == GKS_FP64 ? sizeof(double) : sizeof(float); }
+size_t state_bytes(const gks_ctx *x) { return (size_t)x->batch * x->nfields * x->ncell * elem_size(x); }
+
+gks_status check_device(gks_ctx *ctx)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(ctx, GKS_EDEVICE, "hipGetDevice failed");
+    if (dev != ctx->device)
+        return fail(ctx, GKS_ESTATE, "the current HIP device (%d) is not the context's device (%d)", dev, ctx->device);
+    return GKS_OK;
+}
+
+bool ranges_overlap(const void *a, const void *b, size_t n)
+{
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + n && pb < pa + n;
+}
+
+template <typename T>
+void fill_op(FaceOpTM<T> &o, const double *k0, const double *ke, const double *kh)
+{
+    for (int q = 0; q < TM_N0; ++q) o.k0[q] = (T)k0[q];
+    for (int q = 0; q < TM_NE; ++q) o.ke[q] = (T)ke[q];
+    for (int q = 0; q < TM_NH; ++q) o.kh[q] = (T)kh[q];
+}
+
+double source_pulse(const gks_ctx *x, double t)
+{
+    const double z = (t - x->t0) / x->sigma_t;
+    return x->J0 * std::exp(-z * z);
+}
+
+template <typename T>
+gks_status step_cart2d(gks_ctx *x, const void *Uin, void *Uout, double tn)
+{
+    Cart2DArgs<T> a;
+    std::memset(&a, 0, sizeof a);
+    a.U = (const T *)Uin;
+    a.Unew = (T *)Uout;
+    a.epsinv = (const T *)x->epsinv;
+    a.muinv = (const T *)x->muinv;
+    a.nx = (int32_t)x->n[0];
+    a.ny = (int32_t)x->n[1];
+    a.batch = (int32_t)x->batch;
+    for (int i = 0; i < 4; ++i) a.bc[i] = x->bc[i];
+    a.ntx = (a.nx + cart2d_tile_x() - 1) / cart2d_tile_x();
+    a.nty = (a.ny + cart2d_tile_y() - 1) / cart2d_tile_y();
+    fill_op(a.fx, x->k0[0], x->ke[0], x->kh[0]);
+    fill_op(a.fy, x->k0[1], x->ke[1], x->kh[1]);
+    const int64_t ns = (int64_t)x->src_cells.size();
+    const double amp = ns ? -x->dt * source_pulse(x, tn) : 0.0;   // dt * S_z = -dt J_z
+    if (ns > 0 && ns <= MAX_FUSED_SRC) {
+        a.nsrc = (int32_t)ns;
+        for (int s = 0; s < ns; ++s) {
+            a.src_cell[s] = (int32_t)x->src_cells[s];
+            a.src_amp[s] = amp * x->src_w[s];
+        }
+    }
+    int e = launch_cart2d_step<T>(a, x->stream);
+    if (e) return hip_fail(x, e, "GKS step launch");
+    if (ns > MAX_FUSED_SRC) {
+        e = launch_source_scatter<T>((T *)Uout, (const T *)x->epsinv, x->ncell, (int64_t)x->nfields * x->ncell,
+                                     (int32_t)x->batch, 0, x->d_src_cells, x->d_src_w, amp, (int32_t)ns, x->stream);
+        if (e) return hip_fail(x, e, "source launch");
+    }
+    return GKS_OK;
+}
+
+gks_status do_step(gks_ctx *x, const void *Uin, void *Uout, double tn)
+{
+    if (x->kind == GKS_CART2D)
+        return x->prec == GKS_FP64 ? step_cart2d<double>(x, Uin, Uout, tn) : step_cart2d<float>(x, Uin, Uout, tn);
+    return fail(x, GKS_ESTATE, "this mesh kind has no step kernel");
+}
+
+gks_status ensure_out(gks_ctx *x, size_t count)
+{
+    if (x->d_out_count < count) {
+        if (x->d_out) hipFree(x->d_out);
+        x->d_out = nullptr;
+        x->d_out_count = 0;
+        if (hipMalloc((void **)&x->d_out, count * sizeof(double)) != hipSuccess)
+            return fail(x, GKS_ENOMEM, "cannot allocate %zu doubles of device memory", count);
+        x->d_out_count = count;
+    }
+    if (x->h_out_count < count) {
+        if (x->h_out) hipHostFree(x->h_out);
+        x->h_out = nullptr;
+        x->h_out_count = 0;
+        if (hipHostMalloc((void **)&x->h_out, count * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            return fail(x, GKS_ENOMEM, "cannot allocate %zu doubles of pinned host memory", count);
+        x->h_out_count = count;
+    }
+    return GKS_OK;
+}
+
+gks_status launch_energy_into(gks_ctx *x, const void *U, double *dst)
+{
+    const double vol = x->h[0] * x->h[1] * (x->kind == GKS_CART3D ? x->h[2] : 1.0);
+    int e;
+    if (x->prec == GKS_FP64)
+        e = launch_energy<double>((const double *)U, (const double *)x->epsinv, (const double *)x->muinv, x->ncell,
+                                  x->nfields, (int32_t)x->batch, nullptr, vol, x->d_partial, x->nblk, dst, x->stream);
+    else
+        e = launch_energy<float>((const float *)U, (const float *)x->epsinv, (const float *)x->muinv, x->ncell,
+                                 x->nfields, (int32_t)x->batch, nullptr, vol, x->d_partial, x->nblk, dst, x->stream);
+    if (e) return hip_fail(x, e, "energy launch");
+    return GKS_OK;
+}
+
+gks_status validate_box(gks_ctx *x, const int64_t *box)
+{
+    if (!box) return fail(x, GKS_EINVAL, "box is NULL");
+    if (x->kind == GKS_TRI2D) return fail(x, GKS_ESTATE, "probe boxes need a Cartesian mesh");
+    for (int d = 0; d < 3; ++d) {
+        const int64_t a = box[2 * d], b = box[2 * d + 1];
+        if (a < 0 || b > x->n[d] || a >= b) return fail(x, GKS_EINVAL, "box axis %d [%lld, %lld) outside [0, %lld)", d,
+                                                          (long long)a, (long long)b, (long long)x->n[d]);
+    }
+    return GKS_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" const char *gks_last_error(const gks_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p, void *hip_stream, gks_ctx **out)
+{
+    if (!out) return fail(nullptr, GKS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!m || !p) return fail(nullptr, GKS_EINVAL, "mesh or params is NULL");
+    if (m->precision != GKS_FP64 && m->precision != GKS_FP32) return fail(nullptr, GKS_EINVAL, "bad precision %d", m->precision);
+    if (m->batch < 1 || m->batch > 4096) return fail(nullptr, GKS_EINVAL, "batch %lld not in [1, 4096]", (long long)m->batch);
+    if (!(p->c > 0) || !std::isfinite(p->c)) return fail(nullptr, GKS_EINVAL, "c must be positive and finite");
+    if (!(p->tau_over_dt >= 0)) return fail(nullptr, GKS_EINVAL, "tau_over_dt must be >= 0");
+    if (p->energy_every < 0) return fail(nullptr, GKS_EINVAL, "energy_every must be >= 0");
+    if (!(p->unstable_growth >= 0)) return fail(nullptr, GKS_EINVAL, "unstable_growth must be >= 0");
+
+    gks_ctx *x = new (std::nothrow) gks_ctx();
+    if (!x) return fail(nullptr, GKS_ENOMEM, "cannot allocate the context");
+    x->kind = m->kind;
+    x->model = m->model;
+    x->prec = m->precision;
+    x->batch = m->batch;
+    x->c = p->c;
+    x->energy_every = p->energy_every;
+    x->unstable_growth = p->unstable_growth;
+    x->stream = (hipStream_t)hip_stream;
+    auto bail = [&](gks_status st) {
+        g_init_error = x->err;
+        gks_destroy(x);
+        return st;
+    };
+
+    if (m->kind == GKS_CART2D || m->kind == GKS_CART3D) {
+        const int nd = (m->kind == GKS_CART2D) ? 2 : 3;
+        if ((m->kind == GKS_CART2D && m->model != GKS_TM2D) || (m->kind == GKS_CART3D && m->model != GKS_EM3D))
+            return bail(fail(x, GKS_EINVAL, "Cartesian 2D grids carry TM2D fields and 3D grids EM3D fields"));
+        for (int d = 0; d < 3; ++d) {
+            const int64_t nn = (d < nd) ? m->n[d] : 1;
+            if (d < nd && (nn < 2 || nn > (1 << 30)))
+                return bail(fail(x, GKS_EINVAL, "n[%d] = %lld must be in [2, 2^30]", d, (long long)m->n[d]));
+            if (d < nd && !(m->hi[d] > m->lo[d]))
+                return bail(fail(x, GKS_EINVAL, "hi[%d] must exceed lo[%d]", d, d));
+            x->n[d] = nn;
+            x->lo[d] = (d < nd) ? m->lo[d] : 0.0;
+            x->hi[d] = (d < nd) ? m->hi[d] : 1.0;
+            x->h[d] = (x->hi[d] - x->lo[d]) / (double)nn;
+        }
+        for (int s = 0; s < 2 * nd; ++s) {
+            if (m->bc[s] < GKS_BC_PERIODIC || m->bc[s] > GKS_BC_PEC)
+                return bail(fail(x, GKS_EINVAL, "bc[%d] = %d is not a boundary type", s, m->bc[s]));
+            x->bc[s] = m->bc[s];
+        }
+        for (int d = 0; d < nd; ++d)
+            if ((x->bc[2 * d] == GKS_BC_PERIODIC) != (x->bc[2 * d + 1] == GKS_BC_PERIODIC))
+                return bail(fail(x, GKS_EINVAL, "axis %d is periodic on one side only", d));
+        x->ncell = x->n[0] * x->n[1] * x->n[2];
+        x->nfields = (m->model == GKS_TM2D) ? 3 : 6;
+        if ((int64_t)x->nfields * x->ncell > ((int64_t)1 << 31) - 1)
+            return bail(fail(x, GKS_EINVAL, "grid too large for 32-bit field indexing"));
+        const double hmin = (nd == 2) ? std::min(x->h[0], x->h[1]) : std::min(x->h[0], std::min(x->h[1], x->h[2]));
+        x->dt = (p->dt > 0) ? p->dt : p->cfl * hmin / p->c;
+        if (!(x->dt > 0) || !std::isfinite(x->dt)) return bail(fail(x, GKS_EINVAL, "dt must be positive (set dt or cfl)"));
+        const double nu = p->c * x->dt / hmin;
+        if (nu > 0.5 * (1 + 1e-12))
+            return bail(fail(x, GKS_EINVAL, "Courant number c dt / h = %g exceeds the stability limit 0.5", nu));
+    } else if (m->kind == GKS_TRI2D) {
+        return bail(fail(x, GKS_ESTATE, "triangle meshes are not available in this build"));
+    } else {
+        return bail(fail(x, GKS_EINVAL, "bad mesh kind %d", m->kind));
+    }
+
+    x->tau = p->tau_over_dt * x->dt;
+    flux_coefficients(x->dt, x->tau, x->C);
+
+    // face operators: local frames of the x-, y- (and z-) faces
+    char err[256];
+    if (x->kind == GKS_CART2D) {
+        const double hx[3] = {x->h[0], x->h[1], 1.0}, hy[3] = {x->h[1], x->h[0], 1.0};
+        if (!cart_face_operator(GKS_TM2D, x->c, x->C, x->dt, hx, x->k0[0], x->ke[0], x->kh[0], err, sizeof err) ||
+            !cart_face_operator(GKS_TM2D, x->c, x->C, x->dt, hy, x->k0[1], x->ke[1], x->kh[1], err, sizeof err))
+            return bail(fail(x, GKS_EINVAL, "%s", err));
+    }
+
+    if (hipGetDevice(&x->device) != hipSuccess) return bail(fail(x, GKS_EDEVICE, "no HIP device"));
+    x->nblk = 1024;
+    if (hipMalloc((void **)&x->d_partial, sizeof(double) * x->nblk * x->batch) != hipSuccess)
+        return bail(fail(x, GKS_ENOMEM, "cannot allocate reduction scratch"));
+    *out = x;
+    return GKS_OK;
+}
+
+extern "C" gks_status gks_destroy(gks_ctx *ctx)
+{
+    if (!ctx) return GKS_OK;
+    if (ctx->pingpong) hipFree(ctx->pingpong);
+    if (ctx->d_partial) hipFree(ctx->d_partial);
+    if (ctx->d_out) hipFree(ctx->d_out);
+    if (ctx->h_out) hipHostFree(ctx->h_out);
+    if (ctx->d_src_cells) hipFree(ctx->d_src_cells);
+    if (ctx->d_src_w) hipFree(ctx->d_src_w);
+    delete ctx;
+    return GKS_OK;
+}
+
+extern "C" gks_status gks_get_dt(const gks_ctx *ctx, double *dt_out)
+{
+    if (!ctx || !dt_out) return GKS_EINVAL;
+    *dt_out = ctx->dt;
+    return GKS_OK;
+}
+
+extern "C" gks_status gks_set_material(gks_ctx *ctx, const void *epsinv, const void *muinv)
+{
+    if (!ctx) return GKS_EINVAL;
+    ctx->epsinv = epsinv;
+    ctx->muinv = muinv;
+    return GKS_OK;
+}
+
+extern "C" gks_status gks_set_point_source(gks_ctx *ctx, int64_t n, const int64_t *cells, const double *weight,
+                                           double J0, double t0, double sigma_t)
+{
+    if (!ctx) return GKS_EINVAL;
+    if (n < 0 || n > 4096) return fail(ctx, GKS_EINVAL, "source count %lld not in [0, 4096]", (long long)n);
+    if (n > 0 && (!cells || !weight)) return fail(ctx, GKS_EINVAL, "cells or weight is NULL");
+    if (n > 0 && !(sigma_t > 0)) return fail(ctx, GKS_EINVAL, "sigma_t must be positive");
+    // merge repeated cells (the scatter kernel writes each cell once)
+    std::map<int64_t, double> merged;
+    for (int64_t s = 0; s < n; ++s) {
+        if (cells[s] < 0 || cells[s] >= ctx->ncell)
+            return fail(ctx, GKS_EINVAL, "source cell %lld outside [0, %lld)", (long long)cells[s], (long long)ctx->ncell);
+        merged[cells[s]] += weight[s];
+    }
+    ctx->src_cells.clear();
+    ctx->src_w.clear();
+    for (auto &kv : merged) {
+        ctx->src_cells.push_back(kv.first);
+        ctx->src_w.push_back(kv.second);
+    }
+    ctx->J0 = J0;
+    ctx->t0 = t0;
+    ctx->sigma_t = (n > 0) ? sigma_t : 1.0;
+    if (ctx->d_src_cells) hipFree(ctx->d_src_cells);
+    if (ctx->d_src_w) hipFree(ctx->d_src_w);
+    ctx->d_src_cells = nullptr;
+    ctx->d_src_w = nullptr;
+    const size_t m = ctx->src_cells.size();
+    if (m > (size_t)MAX_FUSED_SRC) {
+        if (hipMalloc((void **)&ctx->d_src_cells, m * sizeof(int64_t)) != hipSuccess ||
+            hipMalloc((void **)&ctx->d_src_w, m * sizeof(double)) != hipSuccess)
+            return fail(ctx, GKS_ENOMEM, "cannot allocate the source list");
+        int e = hipMemcpy(ctx->d_src_cells, ctx->src_cells.data(), m * sizeof(int64_t), hipMemcpyHostToDevice);
+        if (!e) e = hipMemcpy(ctx->d_src_w, ctx->src_w.data(), m * sizeof(double), hipMemcpyHostToDevice);
+        if (e) return hip_fail(ctx, e, "source upload");
+    }
+    return GKS_OK;
+}
+
+extern "C" gks_status gks_step(gks_ctx *ctx, const void *U_in, void *U_out, double t_n)
+{
+    if (!ctx) return GKS_EINVAL;
+    if (!U_in || !U_out) return fail(ctx, GKS_EINVAL, "U_in or U_out is NULL");
+    if (ranges_overlap(U_in, U_out, state_bytes(ctx)))
+        return fail(ctx, GKS_EINVAL, "U_in and U_out overlap (the step is out of place)");
+    if (!std::isfinite(t_n)) return fail(ctx, GKS_EINVAL, "t_n is not finite");
+    gks_status st = check_device(ctx);
+    if (st) return st;
+    return do_step(ctx, U_in, U_out, t_n);
+}
+
+extern "C" gks_status gks_run(gks_ctx *ctx, void *U, int64_t nsteps, double t0, double *energy_host)
+{
+    if (!ctx) return GKS_EINVAL;
+    if (!U) return fail(ctx, GKS_EINVAL, "U is NULL");
+    if (nsteps < 0) return fail(ctx, GKS_EINVAL, "nsteps must be >= 0");
+    if (!std::isfinite(t0)) return fail(ctx, GKS_EINVAL, "t0 is not finite");
+    gks_status st = check_device(ctx);
+    if (st) return st;
+    const size_t bytes = state_bytes(ctx);
+    if (ctx->pingpong_bytes < bytes) {
+        if (ctx->pingpong) hipFree(ctx->pingpong);
+        ctx->pingpong = nullptr;
+        ctx->pingpong_bytes = 0;
+        if (hipMalloc(&ctx->pingpong, bytes) != hipSuccess)
+            return fail(ctx, GKS_ENOMEM, "cannot allocate the %zu-byte ping-pong state", bytes);
+        ctx->pingpong_bytes = bytes;
+    }
+    const int64_t every = (energy_host && ctx->energy_every > 0) ? ctx->energy_every : 0;
+    const int64_t nrec = every ? nsteps / every : 0;
+    if (nrec) {
+        st = ensure_out(ctx, (size_t)nrec * ctx->batch);
+        if (st) return st;
+    }
+    void *cur = U, *nxt = ctx->pingpong;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        st = do_step(ctx, cur, nxt, t0 + (double)k * ctx->dt);
+        if (st) return st;
+        std::swap(cur, nxt);
+        if (every && (k + 1) % every == 0) {
+            st = launch_energy_into(ctx, cur, ctx->d_out + ((k + 1) / every - 1) * ctx->batch);
+            if (st) return st;
+        }
+    }
+    if (cur != U) {
+        int e = hipMemcpyAsync(U, cur, bytes, hipMemcpyDeviceToDevice, ctx->stream);
+        if (e) return hip_fail(ctx, e, "state copy");
+    }
+    if (nrec) {
+        const size_t cnt = (size_t)nrec * ctx->batch;
+        int e = hipMemcpyAsync(ctx->h_out, ctx->d_out, cnt * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+        if (!e) e = hipStreamSynchronize(ctx->stream);
+        if (e) return hip_fail(ctx, e, "energy readback");
+        std::memcpy(energy_host, ctx->h_out, cnt * sizeof(double));
+        for (int64_t r = 0; r < nrec; ++r)
+            for (int64_t b = 0; b < ctx->batch; ++b) {
+                const double w = energy_host[r * ctx->batch + b];
+                if (!std::isfinite(w))
+                    return fail(ctx, GKS_ENONFINITE, "energy of batch item %lld is not finite after step %lld",
+                                (long long)b, (long long)((r + 1) * every));
+                if (ctx->unstable_growth > 0 && w > ctx->unstable_growth * energy_host[b])
+                    return fail(ctx, GKS_EUNSTABLE, "energy of batch item %lld grew by %g after step %lld", (long long)b,
+                                w / energy_host[b], (long long)((r + 1) * every));
+            }
+    }
+    return GKS_OK;
+}
+
+extern "C" gks_status gks_energy(gks_ctx *ctx, const void *U, double *out_host)
+{
+    if (!ctx) return GKS_EINVAL;
+    if (!U || !out_host) return fail(ctx, GKS_EINVAL, "U or out_host is NULL");
+    gks_status st = check_device(ctx);
+    if (st) return st;
+    st = ensure_out(ctx, (size_t)ctx->batch);
+    if (st) return st;
+    st = launch_energy_into(ctx, U, ctx->d_out);
+    if (st) return st;
+    int e = hipMemcpyAsync(ctx->h_out, ctx->d_out, ctx->batch * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (!e) e = hipStreamSynchronize(ctx->stream);
+    if (e) return hip_fail(ctx, e, "energy readback");
+    std::memcpy(out_host, ctx->h_out, ctx->batch * sizeof(double));
+    return GKS_OK;
+}
+
+extern "C" gks_status gks_probe_energy(gks_ctx *ctx, const void *U, const int64_t *box, double *out_host)
+{
+    if (!ctx) return GKS_EINVAL;
+    if (!U || !out_host) return fail(ctx, GKS_EINVAL, "U or out_host is NULL");
+    gks_status st = validate_box(ctx, box);
+    if (st) return st;
+    st = check_device(ctx);
+    if (st) return st;
+    st = ensure_out(ctx, (size_t)ctx->batch);
+    if (st) return st;
+    const double vol = ctx->h[0] * ctx->h[1] * (ctx->kind == GKS_CART3D ? ctx->h[2] : 1.0);
+    const int ezf = (ctx->model == GKS_TM2D) ? 0 : 2;
+    int e = (ctx->prec == GKS_FP64)
+                ? launch_probe_energy<double>((const double *)U, ctx->n[0], ctx->n[1], ctx->n[2], ctx->nfields, ezf,
+                                              (int32_t)ctx->batch, box, vol, ctx->d_partial, ctx->nblk, ctx->d_out,
+                                              ctx->stream)
+                : launch_probe_energy<float>((const float *)U, ctx->n[0], ctx->n[1], ctx->n[2], ctx->nfields, ezf,
+                                             (int32_t)ctx->batch, box, vol, ctx->d_partial, ctx->nblk, ctx->d_out,
+                                             ctx->stream);
+    if (!e) e = hipMemcpyAsync(ctx->h_out, ctx->d_out, ctx->batch * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (!e) e = hipStreamSynchronize(ctx->stream);
+    if (e) return hip_fail(ctx, e, "probe energy");
+    std::memcpy(out_host, ctx->h_out, ctx->batch * sizeof(double));
+    return GKS_OK;
+}
+
+extern "C" gks_status gks_probe_energy_grad(gks_ctx *ctx, const void *U, const int64_t *box, void *lam)
+{
+    if (!ctx) return GKS_EINVAL;
+    if (!U || !lam) return fail(ctx, GKS_EINVAL, "U or lam is NULL");
+    if (ranges_overlap(U, lam, state_bytes(ctx))) return fail(ctx, GKS_EINVAL, "U and lam overlap");
+    gks_status st = validate_box(ctx, box);
+    if (st) return st;
+    st = check_device(ctx);
+    if (st) return st;
+    const double vol = ctx->h[0] * ctx->h[1] * (ctx->kind == GKS_CART3D ? ctx->h[2] : 1.0);
+    const int ezf = (ctx->model == GKS_TM2D) ? 0 : 2;
+    int e = (ctx->prec == GKS_FP64)
+                ? launch_probe_grad<double>((const double *)U, (double *)lam, ctx->n[0], ctx->n[1], ctx->n[2],
+                                            ctx->nfields, ezf, (int32_t)ctx->batch, box, vol, ctx->stream)
+                : launch_probe_grad<float>((const float *)U, (float *)lam, ctx->n[0], ctx->n[1], ctx->n[2],
+                                           ctx->nfields, ezf, (int32_t)ctx->batch, box, vol, ctx->stream);
+    if (e) return hip_fail(ctx, e, "probe gradient");
+    return GKS_OK;
+}
+
+extern "C" gks_status gks_adjoint_step(gks_ctx *ctx, const void *U_n, const void *lam_np1, void *lam_n,
+                                       double *g_epsinv, double *g_muinv, double t_n)
+{
+    if (!ctx) return GKS_EINVAL;
+    (void)U_n; (void)lam_np1; (void)lam_n; (void)g_epsinv; (void)g_muinv; (void)t_n;
+    return fail(ctx, GKS_ESTATE, "the adjoint step is not available in this build");
+}

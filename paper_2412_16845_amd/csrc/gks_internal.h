@@ -1,0 +1,101 @@
+// Internal declarations shared by the host runtime and the kernels of libgks.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/gks.h"
+
+namespace gks {
+
+// ------------------------------------------------------------------ sparse face operators
+// Structurally non-zero entries (row = output component, col = input index) of the face
+// operators K0 (material independent), KE (times 1/eps_s) and KH (times 1/mu_s).
+struct Pattern {
+    int n0, nE, nH;
+    const uint8_t *r0, *c0, *rE, *cE, *rH, *cH;
+};
+const Pattern &pattern_tm();
+const Pattern &pattern_em();
+
+constexpr int TM_N0 = 24, TM_NE = 6, TM_NH = 4;
+constexpr int EM_N0 = 80, EM_NE = 12, EM_NH = 12;
+
+void flux_coefficients(double dt, double tau, double C[5]);
+bool cart_face_operator(int model, double c, const double C[5], double dt, const double h[3], double *k0,
+                        double *ke, double *kh, char *err, size_t errlen);
+bool tri_face_operator(double c, const double C[5], double *k0, double *ke, double *kh, char *err,
+                       size_t errlen);
+
+// Coefficients of one face orientation, in the storage precision T.
+template <typename T, int N0, int NE, int NH>
+struct FaceOp {
+    T k0[N0];
+    T ke[NE];
+    T kh[NH];
+};
+template <typename T> using FaceOpTM = FaceOp<T, TM_N0, TM_NE, TM_NH>;
+template <typename T> using FaceOpEM = FaceOp<T, EM_N0, EM_NE, EM_NH>;
+
+constexpr int MAX_FUSED_SRC = 4;
+
+// Arguments of the Cartesian 2D TM step kernel.
+template <typename T>
+struct Cart2DArgs {
+    const T *U;
+    T *Unew;
+    const T *epsinv;      // nullable: vacuum
+    const T *muinv;       // nullable: vacuum
+    int32_t nx, ny;
+    int32_t batch;
+    int32_t bc[4];        // x-, x+, y-, y+
+    int32_t ntx, nty;     // tiles per row / column
+    FaceOpTM<T> fx, fy;   // x-face and y-face operators (local frame of each)
+    int32_t nsrc;         // fused point sources (<= MAX_FUSED_SRC)
+    int32_t src_cell[MAX_FUSED_SRC];
+    double src_amp[MAX_FUSED_SRC];   // dt * S_z = -dt * J_z(t^n) (before the 1/eps factor)
+};
+
+// Arguments of the Cartesian 2D TM adjoint kernel.
+template <typename T>
+struct Cart2DAdjArgs {
+    const T *U;           // state the forward step started from
+    const T *lam;         // lambda^{n+1}
+    T *lam_out;           // lambda^n
+    double *g_epsinv;     // nullable, accumulated
+    double *g_muinv;      // nullable, accumulated
+    const T *epsinv;
+    const T *muinv;
+    int32_t nx, ny, batch;
+    int32_t bc[4];
+    int32_t ntx, nty;
+    FaceOpTM<T> fx, fy;
+    int32_t nsrc;
+    int32_t src_cell[MAX_FUSED_SRC];
+    double src_amp[MAX_FUSED_SRC];
+};
+
+// Launchers (defined in the .hip files).  Return a hipError_t as int.
+template <typename T> int launch_cart2d_step(const Cart2DArgs<T> &a, void *stream);
+template <typename T> int launch_cart2d_adjoint(const Cart2DAdjArgs<T> &a, void *stream);
+// U[b][field][cells[s]] += (1/eps) * amp * weight[s]  (explicit source, long source lists)
+template <typename T> int launch_source_scatter(T *U, const T *epsinv, int64_t ncell, int64_t fstride,
+                                                int32_t batch, int32_t field, const int64_t *cells,
+                                                const double *weight, double amp, int32_t n, void *stream);
+int cart2d_tile_x();
+int cart2d_tile_y();
+
+// Energy: partial sums per (batch, block) then a fixed-order final sum; all FP64.
+template <typename T>
+int launch_energy(const T *U, const T *epsinv, const T *muinv, int64_t ncell, int32_t nfields, int32_t batch,
+                  const double *vol /*nullable: uniform*/, double uniform_vol, double *partial, int32_t nblk,
+                  double *out, void *stream);
+template <typename T>
+int launch_probe_energy(const T *U, int64_t nx, int64_t ny, int64_t nz, int32_t nfields, int32_t ez_field,
+                        int32_t batch, const int64_t box[6], double vol, double *partial, int32_t nblk, double *out,
+                        void *stream);
+template <typename T>
+int launch_probe_grad(const T *U, T *lam, int64_t nx, int64_t ny, int64_t nz, int32_t nfields, int32_t ez_field,
+                      int32_t batch, const int64_t box[6], double vol, void *stream);
+
+}  // namespace gks

@@ -1,0 +1,178 @@
+"""Seeded synthetic inputs for the GKS workloads (shared by the tests, the benchmark and the
+oracle checks).  Pure NumPy; none of the scheme's arithmetic lives here.
+
+All arrays are float64, structure-of-arrays: fields (batch, nfields, *grid) with grid =
+(ny, nx) or (nz, ny, nx), material maps (batch, *grid).  Random draws use
+numpy.random.default_rng(seed).
+
+Workloads (names used across the repository):
+  tm_gaussian_periodic  2D TM, periodic unit square, vacuum, periodic Gaussian Ez pulse
+  tm_dielectric_nr      2D TM, non-reflecting sides, circular dielectric inclusions, Gaussian
+                        point current source (and optionally an initial Gaussian pulse)
+  em_blocks_pec         3D six-component, random dielectric blocks, PEC z walls, non-reflecting
+                        x/y sides, Ez pulse uniform in z
+  tm_batch_probe        2D TM batch of dielectric maps with a probe box (differentiable workload)
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+PERIODIC, NONREFLECT, PEC = "periodic", "nonreflecting", "pec"
+
+
+@dataclass
+class Workload:
+    name: str
+    kind: str                       # 'cart2d' | 'cart3d' | 'tri2d'
+    n: tuple                        # cells per axis (x, y[, z]) or (ncells,)
+    lo: tuple
+    hi: tuple
+    bc: tuple                       # per side, x-, x+, y-, y+[, z-, z+]
+    U0: np.ndarray                  # (batch, nfields, *grid)
+    epsinv: Optional[np.ndarray]    # (batch, *grid) or None
+    muinv: Optional[np.ndarray]
+    cfl: float
+    tau_over_dt: float
+    nsteps: int
+    source: Optional[dict] = None   # cells, weights, J0, t0, sigma_t
+    probe: Optional[tuple] = None   # (i0, i1, j0, j1) cell box
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def batch(self) -> int:
+        return int(self.U0.shape[0])
+
+    @property
+    def ncell(self) -> int:
+        return int(np.prod(self.n))
+
+
+def centres_2d(nx, ny, lo=(0.0, 0.0), hi=(1.0, 1.0)):
+    """Cell-centre coordinates, arrays of shape (ny, nx)."""
+    x = lo[0] + (np.arange(nx) + 0.5) * (hi[0] - lo[0]) / nx
+    y = lo[1] + (np.arange(ny) + 0.5) * (hi[1] - lo[1]) / ny
+    return np.meshgrid(x, y, indexing="xy")
+
+
+def centres_3d(nx, ny, nz, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+    """Cell-centre coordinates, arrays of shape (nz, ny, nx)."""
+    ax = [lo[d] + (np.arange(m) + 0.5) * (hi[d] - lo[d]) / m for d, m in enumerate((nx, ny, nz))]
+    z, y, x = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return x, y, z
+
+
+def gaussian(x, y, xc, yc, w, periodic=False):
+    """exp(-|x - x_c|^2 / (2 w^2)); with periodic=True summed over the 3 x 3 unit-square images."""
+    if not periodic:
+        return np.exp(-((x - xc) ** 2 + (y - yc) ** 2) / (2 * w * w))
+    out = np.zeros_like(x)
+    for sx in (-1, 0, 1):
+        for sy in (-1, 0, 1):
+            out += np.exp(-((x - xc - sx) ** 2 + (y - yc - sy) ** 2) / (2 * w * w))
+    return out
+
+
+def circles_eps(x, y, rng, count, r_range, eps_range):
+    """Background eps = 1 with `count` discs painted in order at the cell centres."""
+    eps = np.ones_like(x)
+    cx = rng.uniform(0.05, 0.95, count)
+    cy = rng.uniform(0.05, 0.95, count)
+    r = rng.uniform(r_range[0], r_range[1], count)
+    ev = rng.uniform(eps_range[0], eps_range[1], count)
+    for i in range(count):
+        eps[(x - cx[i]) ** 2 + (y - cy[i]) ** 2 <= r[i] ** 2] = ev[i]
+    return eps
+
+
+def boxes_eps(x, y, z, rng, count, side_range, eps_range):
+    """Background eps = 1 with `count` axis-aligned boxes inside the unit cube, painted in order."""
+    eps = np.ones_like(x)
+    for _ in range(count):
+        s = rng.uniform(side_range[0], side_range[1], 3)
+        a = rng.uniform(0.0, 1.0 - s)
+        e = rng.uniform(eps_range[0], eps_range[1])
+        m = (x >= a[0]) & (x < a[0] + s[0]) & (y >= a[1]) & (y < a[1] + s[1]) & (z >= a[2]) & (z < a[2] + s[2])
+        eps[m] = e
+    return eps
+
+
+def cell_containing(nx, ny, p, lo=(0.0, 0.0), hi=(1.0, 1.0)) -> int:
+    ix = min(int((p[0] - lo[0]) / (hi[0] - lo[0]) * nx), nx - 1)
+    iy = min(int((p[1] - lo[1]) / (hi[1] - lo[1]) * ny), ny - 1)
+    return iy * nx + ix
+
+
+# ----------------------------------------------------------------------------- workloads
+def tm_gaussian_periodic(n=64, seed=0, nsteps=200, cfl=0.5, tau_over_dt=0.01, w=0.05) -> Workload:
+    rng = np.random.default_rng(seed)
+    xc, yc = rng.uniform(0.25, 0.75, 2)
+    x, y = centres_2d(n, n)
+    U = np.zeros((1, 3, n, n))
+    U[0, 0] = gaussian(x, y, xc, yc, w, periodic=True)
+    return Workload("tm_gaussian_periodic", "cart2d", (n, n), (0.0, 0.0), (1.0, 1.0), (PERIODIC,) * 4, U,
+                    None, None, cfl, tau_over_dt, nsteps, extra={"centre": (xc, yc), "w": w})
+
+
+def tm_dielectric_nr(nx=4096, ny=None, seed=0, nsteps=1000, cfl=0.5, tau_over_dt=0.01, ncircles=64,
+                     pulse: Optional[float] = None, bc=(NONREFLECT,) * 4) -> Workload:
+    """Non-reflecting box with circular inclusions (radii in [0.01, 0.04], eps in [1, 4]) and a
+    Gaussian point source J_z = exp(-((t - 0.02)/0.005)^2) in the cell holding (0.5, 0.5).
+    pulse: optional amplitude of an initial Ez Gaussian (w = 0.05 at (0.35, 0.6))."""
+    ny = nx if ny is None else ny
+    rng = np.random.default_rng(seed)
+    x, y = centres_2d(nx, ny)
+    eps = circles_eps(x, y, rng, ncircles, (0.01, 0.04), (1.0, 4.0))
+    U = np.zeros((1, 3, ny, nx))
+    if pulse:
+        U[0, 0] = pulse * gaussian(x, y, 0.35, 0.6, 0.05)
+    src = {"cells": [cell_containing(nx, ny, (0.5, 0.5))], "weights": [1.0], "J0": 1.0, "t0": 0.02,
+           "sigma_t": 0.005}
+    return Workload("tm_dielectric_nr", "cart2d", (nx, ny), (0.0, 0.0), (1.0, 1.0), tuple(bc), U,
+                    (1.0 / eps)[None], None, cfl, tau_over_dt, nsteps, source=src)
+
+
+def em_blocks_pec(n=384, seed=0, nsteps=500, cfl=1.0 / 3.0, tau_over_dt=0.01, nboxes=32, w=0.05) -> Workload:
+    """384^3 style 3D workload: dielectric blocks (sides in [0.05, 0.25], eps in [1, 6]), PEC on
+    z = 0, 1, non-reflecting x, y sides; Ez = Gaussian in (x, y), uniform in z; H = 0."""
+    nx = ny = nz = n if np.isscalar(n) else None
+    if not np.isscalar(n):
+        nx, ny, nz = n
+    rng = np.random.default_rng(seed)
+    x, y, z = centres_3d(nx, ny, nz)
+    eps = boxes_eps(x, y, z, rng, nboxes, (0.05, 0.25), (1.0, 6.0))
+    xc, yc = rng.uniform(0.3, 0.7, 2)
+    U = np.zeros((1, 6, nz, ny, nx))
+    U[0, 2] = np.exp(-((x - xc) ** 2 + (y - yc) ** 2) / (2 * w * w))
+    bc = (NONREFLECT, NONREFLECT, NONREFLECT, NONREFLECT, PEC, PEC)
+    return Workload("em_blocks_pec", "cart3d", (nx, ny, nz), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), bc, U,
+                    (1.0 / eps)[None], None, cfl, tau_over_dt, nsteps)
+
+
+def tm_batch_probe(n=1024, batch=8, seed=0, nsteps=800, cfl=0.5, tau_over_dt=0.01, ncircles=16,
+                   w=0.05) -> Workload:
+    """Batch of dielectric maps (16 discs, radii [0.03, 0.1], eps [1, 4]); Ez Gaussian at
+    (0.3, 0.5); probe box [0.55, 0.65] x [0.45, 0.55]; non-reflecting sides."""
+    rng = np.random.default_rng(seed)
+    x, y = centres_2d(n, n)
+    eps = np.stack([circles_eps(x, y, rng, ncircles, (0.03, 0.1), (1.0, 4.0)) for _ in range(batch)])
+    U = np.zeros((batch, 3, n, n))
+    U[:, 0] = gaussian(x, y, 0.3, 0.5, w)[None]
+    box = (int(0.55 * n), int(0.65 * n), int(0.45 * n), int(0.55 * n))
+    return Workload("tm_batch_probe", "cart2d", (n, n), (0.0, 0.0), (1.0, 1.0), (NONREFLECT,) * 4, U,
+                    1.0 / eps, None, cfl, tau_over_dt, nsteps, probe=box)
+
+
+def random_smooth_tm(nx, ny, seed, modes=4, batch=1):
+    """Sum of a few random Fourier modes per field (for symmetry and parity tests)."""
+    rng = np.random.default_rng(seed)
+    x, y = centres_2d(nx, ny)
+    U = np.zeros((batch, 3, ny, nx))
+    for b in range(batch):
+        for f in range(3):
+            for _ in range(modes):
+                kx, ky = rng.integers(-3, 4, size=2)
+                U[b, f] += rng.normal() * np.cos(2 * np.pi * (kx * x + ky * y) + rng.uniform(0, 2 * np.pi))
+    return U

@@ -1,0 +1,96 @@
+"""CPU checks of the C ABI library: it loads, exports every entry point of include/gks.h,
+computes C1..C5 like the oracle, and rejects bad arguments on the host before touching a GPU."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def gks():
+    from paper_2412_16845_amd import gks as G
+    G.lib()
+    return G
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "gks.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gks_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_entry_point(gks):
+    names = declared_functions()
+    assert len(names) >= 13
+    assert set(names) == set(gks.EXPORTS)
+    L = ctypes.CDLL(gks.LIBPATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+@pytest.mark.parametrize("tau_hat", [0.0, 1e-6, 1e-3, 0.01, 0.3, 0.99, 1.0, 1.01, 5.0, 100.0, 1e4, 1e9, math.inf])
+def test_flux_coefficients_match_oracle(gks, oracle, tau_hat):
+    dt = 0.5 / 4096
+    got = np.array(gks.flux_coefficients(dt, tau_hat * dt))
+    ref = np.array(oracle.coefficients(dt, tau_hat * dt))
+    scale = np.array([dt, dt * dt, dt * dt, dt, dt * dt])
+    assert np.allclose(got / scale, ref / scale, rtol=0, atol=2e-15), (got, ref)
+
+
+def _init(gks, **over):
+    d = gks.MeshDesc()
+    d.kind, d.model, d.precision, d.batch = 0, 0, 0, 1
+    for i, v in enumerate((16, 16, 1)):
+        d.n[i] = v
+    for i in range(3):
+        d.lo[i], d.hi[i] = 0.0, 1.0
+    p = gks.Params(1.0, 0.5, 0.0, 0.01, 0, 0.0)
+    for k, v in over.items():
+        if k in ("c", "cfl", "dt", "tau_over_dt", "energy_every", "unstable_growth"):
+            setattr(p, k, v)
+        elif k == "n":
+            for i, x in enumerate(v):
+                d.n[i] = x
+        elif k == "bc":
+            for i, x in enumerate(v):
+                d.bc[i] = x
+        else:
+            setattr(d, k, v)
+    h = ctypes.c_void_p()
+    st = gks.lib().gks_init_mesh(ctypes.byref(d), ctypes.byref(p), None, ctypes.byref(h))
+    msg = gks.lib().gks_last_error(None).decode()
+    if h.value:
+        gks.lib().gks_destroy(h)
+    return st, msg
+
+
+@pytest.mark.parametrize("over,needle", [
+    ({"precision": 7}, "precision"),
+    ({"batch": 0}, "batch"),
+    ({"n": (1, 16, 1)}, "n[0]"),
+    ({"bc": (0, 1, 0, 0)}, "periodic on one side"),
+    ({"bc": (5, 5, 0, 0)}, "boundary type"),
+    ({"cfl": 0.6}, "stability"),
+    ({"c": -1.0}, "c must"),
+    ({"tau_over_dt": -1.0}, "tau_over_dt"),
+    ({"kind": 1}, "Cartesian"),
+    ({"kind": 9}, "kind"),
+])
+def test_init_rejects_bad_arguments(gks, over, needle):
+    st, msg = _init(gks, **over)
+    assert st == -1, (st, msg)
+    assert needle in msg
+
+
+def test_null_arguments(gks):
+    L = gks.lib()
+    assert L.gks_init_mesh(None, None, None, None) == -1
+    assert L.gks_destroy(None) == 0
+    assert L.gks_step(None, None, None, 0.0) == -1
+    out = (ctypes.c_double * 5)()
+    assert L.gks_flux_coefficients(-1.0, 0.0, out) == -1
