@@ -1,0 +1,242 @@
+"""Benchmark of the GKS step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload: 2D TM fields on a 4096 x 4096 Cartesian grid of the unit square, kinetic
+non-reflecting sides, eps map of 64 seeded circular inclusions (eps in [1, 4]), Gaussian point
+current source at the centre, CFL 0.5, collision time 0.01 dt.  A step is one full GKS time step
+(load, gradients, face reconstruction, interface flux, accumulation, boundaries and source)
+over the whole grid, with the FP64 energy diagnostic every 100 steps, as in a production run.
+Inputs are resident in HBM before timing starts.
+
+One JSON line on stdout:
+  value          FP32-mode cell-updates/s (FP32 storage/flux, FP64 accumulation)
+  fp64           the same run in FP64
+  roofline       achieved algorithmic HBM bandwidth of the step kernel (HIP events around each
+                 launch) against the 8 TB/s peak; traffic = HBM bytes per launch from the
+                 committed rocprofv3 counter summary (null when the kernel source changed since)
+  cpu_baseline   the FP64 oracle on the host cores, on a bounded sample of the same workload
+  adjoint        forward + adjoint step time of the differentiable workload (when built)
+
+Helper modes for the profiles: --profile-kernel PREC runs only step kernels (for rocprofv3);
+--copy-calibration runs a plain device copy of known size (counter scale factor).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GKS cell-updates/s (FP32 vs FP64) + % HBM roofline; fwd+adjoint step time"
+PEAK_GBS = 8000.0
+N = 4096
+ENERGY_EVERY = 100
+KERNEL_SRC = os.path.join(ROOT, "paper_2412_16845_amd", "csrc", "k_cart2d.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cart2d_step_4096_traffic.txt")
+# algorithmic bytes per cell-update: read Ez,Hx,Hy and 1/eps, write Ez,Hx,Hy
+BYTES_PER_CELL = {"fp32": 7 * 4, "fp64": 7 * 8}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload():
+    from paper_2412_16845_amd import inputs as I
+    return I.tm_dielectric_nr(nx=N, seed=0, nsteps=1000)
+
+
+def make(torch, wl, precision, energy_every=0):
+    from paper_2412_16845_amd.gks import Solver
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    s = Solver("cart2d", n=wl.n, bc=wl.bc, precision=precision, cfl=wl.cfl, tau_over_dt=wl.tau_over_dt,
+               energy_every=energy_every)
+    ei = torch.tensor(wl.epsinv, dtype=dtype, device="cuda")
+    s.set_material(ei)
+    src = wl.source
+    s.set_point_source(src["cells"], src["weights"], src["J0"], src["t0"], src["sigma_t"])
+    U = torch.tensor(wl.U0, dtype=dtype, device="cuda")
+    return s, U, ei
+
+
+def time_run(torch, s, U, steps, warmup):
+    """Whole-job time of `steps` GKS steps (gks_run with the energy diagnostic)."""
+    s.run(U, warmup, t0=0.0, energy=True)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(s.stream)
+    s.run(U, steps, t0=warmup * s.dt, energy=True)
+    end.record(s.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(end) / 1e3, wall
+
+
+def time_kernel(torch, s, U, launches=200):
+    """Average duration of one step-kernel launch: a HIP event pair around each launch on the
+    stream the kernel runs on."""
+    A, B = U, torch.empty_like(U)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(launches)]
+    for i in range(10):
+        s.step(A, B, t=i * s.dt)
+        A, B = B, A
+    torch.cuda.synchronize()
+    for i, (e0, e1) in enumerate(evs):
+        e0.record(s.stream)
+        s.step(A, B, t=i * s.dt)
+        e1.record(s.stream)
+        A, B = B, A
+    torch.cuda.synchronize()
+    d = np.array([e0.elapsed_time(e1) for e0, e1 in evs]) / 1e3
+    return float(np.mean(d)), float(np.median(d))
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(precision):
+    """HBM bytes per launch from the committed counter summary, if it matches this kernel."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        line = line.strip()
+        if line.startswith("#") or "=" not in line:
+            continue
+        k, v = line.split("=", 1)
+        kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_sha():
+        return None
+    key = f"traffic_bytes_per_launch_{precision}"
+    return float(kv[key]) if key in kv else None
+
+
+def roofline(precision, t_launch):
+    ncell = N * N
+    alg = BYTES_PER_CELL[precision] * ncell
+    achieved = alg / t_launch / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_GBS, 4), "traffic": read_traffic(precision),
+            "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch}
+
+
+def cpu_baseline(wl, dt):
+    """The FP64 oracle (OpenMP over all host cores) on a 1024 x 1024 window of the workload
+    (its centre, with the source and inclusions; cut sides non-reflecting) for a few steps."""
+    from oracle import gks_oracle as O
+    O.build()
+    x0 = y0 = (N - 1024) // 2
+    mesh = O.cart_window((N, N, 1), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), [1, 1, 1, 1], (x0, y0, 0),
+                         (x0 + 1024, y0 + 1024, 1), 2)
+    ei = np.ascontiguousarray(wl.epsinv[0][y0:y0 + 1024, x0:x0 + 1024]).reshape(-1)
+    U = O.from_soa(wl.U0[0][:, y0:y0 + 1024, x0:x0 + 1024].reshape(3, -1), "tm2d")
+    c = wl.source["cells"][0]
+    src = (np.array([(c // N - y0) * 1024 + (c % N - x0)]), np.array([1.0]), 1.0, 0.02, 0.005)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        U = O.run(mesh, U, 1, dt, wl.tau_over_dt * dt, epsinv=ei, source=src, t0=steps * dt)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > 12.0 or steps >= 40:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(1024 * 1024 * steps / el, 1), "unit": "cell-updates/s", "cores": cores,
+            "kind": "oracle", "sample": f"1024x1024 centre window of the 4096x4096 workload, {steps} steps, "
+                                        f"{el:.1f} s, FP64 literal per-face lattice sums"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-kernel", choices=["fp32", "fp64"])
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the GKS step is measured on one "
+              "MI355X and multi-GPU domain decomposition is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        n = 1 << 28   # 1 GiB of float32 read, 1 GiB written
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+        return
+
+    wl = workload()
+    if args.profile_kernel:
+        s, U, _ = make(torch, wl, args.profile_kernel)
+        B = torch.empty_like(U)
+        for i in range(20):
+            s.step(U, B, t=i * s.dt)
+            U, B = B, U
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled": args.profile_kernel, "launches": 20}))
+        return
+
+    res = {}
+    for prec in ("fp32", "fp64"):
+        log(f"[bench] {prec}: 4096x4096 dielectric box, warmup {args.warmup}, {args.steps} timed steps")
+        s, U, ei = make(torch, wl, prec, energy_every=ENERGY_EVERY)
+        el, wall = time_run(torch, s, U, args.steps, args.warmup)
+        if not torch.isfinite(U).all():
+            raise RuntimeError(f"{prec} run produced non-finite values")
+        t_launch, t_med = time_kernel(torch, s, U)
+        res[prec] = {"seconds": el, "wall": wall, "t_launch": t_launch, "t_launch_median": t_med, "dt": s.dt}
+        log(f"[bench] {prec}: {el * 1e3 / args.steps:.4f} ms/step, kernel {t_launch * 1e6:.1f} us/launch")
+        del s, U, ei
+        torch.cuda.empty_cache()
+
+    ncell = N * N
+    f32, f64 = res["fp32"], res["fp64"]
+    out = {
+        "metric": METRIC,
+        "value": round(ncell * args.steps / f32["seconds"], 1),
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f32["seconds"] * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 accumulation)",
+        "data": "synthetic",
+        "config": {"workload": "tm_dielectric_nr: 2D TM 4096x4096, non-reflecting sides, 64 dielectric discs "
+                               "(eps in [1,4]), Gaussian point source, CFL 0.5, tau = 0.01 dt, energy every 100 steps",
+                   "cells": ncell, "precision": "fp32"},
+        "roofline": roofline("fp32", f32["t_launch"]),
+        "fp64": {"value": round(ncell * args.steps / f64["seconds"], 1), "unit": "cell-updates/s",
+                 "ms_per_step": round(f64["seconds"] * 1e3 / args.steps, 5), "dtype": "f64",
+                 "roofline": roofline("fp64", f64["t_launch"])},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline: oracle on a 1024x1024 window")
+        out["cpu_baseline"] = cpu_baseline(wl, f64["dt"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -152,41 +152,85 @@ static void closed_flux(int dim, double c, const double C[5], const double *Ul, 
 }
 
 // ------------------------------------------------------------------ Cartesian face operators
-// Inputs w (local frame): TM2D (E,X,Y) = components (2,3,4):
-//   [UL(3) UR(3) d1L(3) d2L(3) d1R(3) d2R(3)]          d_j = h_j * (central slope along j)
-// EM3D: [UL(6) UR(6) d1L(6) d2L(6) d3L(6) d1R(6) d2R(6) d3R(6)]
-// Reconstruction on a Cartesian grid: U^l = UL + d1L/2, U^r = UR - d1R/2 (Sec. 3.1, linear
-// reconstruction with the Green-Gauss = central-difference gradient).
-static void cart_flux_eval(int model, double c, const double C[5], double dt, const double h[3],
+// Rotation T' of Sec. 3.1 for a unit normal n: its rows are the local axes in global
+// coordinates (local x along n), with T' = diag(-1, -1, 1) when n1 = -1.
+static void face_rotation(const double n[3], double T[3][3])
+{
+    if (n[0] == -1.0) {
+        std::memset(T, 0, 9 * sizeof(double));
+        T[0][0] = -1.0; T[1][1] = -1.0; T[2][2] = 1.0;
+        return;
+    }
+    const double q = 1.0 + n[0];
+    T[0][0] = n[0];  T[0][1] = n[1];                      T[0][2] = n[2];
+    T[1][0] = -n[1]; T[1][1] = n[0] + n[2] * n[2] / q;    T[1][2] = -n[1] * n[2] / q;
+    T[2][0] = -n[2]; T[2][1] = -n[1] * n[2] / q;          T[2][2] = 1.0 - n[2] * n[2] / q;
+}
+
+static void rotate_fields(const double T[3][3], const double *a, double *b, bool inverse)
+{
+    for (int blk = 0; blk < 2; ++blk)
+        for (int r = 0; r < 3; ++r) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += (inverse ? T[k][r] : T[r][k]) * a[3 * blk + k];
+            b[3 * blk + r] = s;
+        }
+}
+
+static int tm_component(int q) { return 2 + q; }   // (Ez, Hx, Hy) inside (Ex, Ey, Ez, Hx, Hy, Hz)
+
+// Axis-aligned Cartesian face with normal +e_ax; inputs and outputs in the global frame:
+//   w = [UL UR dnL dt1L (dt2L) dnR dt1R (dt2R)] x fields,
+// d = dfac * h * (central slope) along the face normal (dn) and the remaining axes in increasing
+// order (dt1, dt2).  Reconstruction (Sec. 3.1): U^l = U_L + (h_n/2) dU_L/dn, U^r = U_R - (h_n/2)
+// dU_R/dn; states and slopes are rotated into the face frame (d~_j U~ = sum_i T'_ji T d_i U),
+// the closed-form flux is evaluated there and rotated back.  Output phi = (dt/h_n) F (global).
+static void cart_flux_eval(int model, int ax, double c, const double C[5], const double h[3], double dfac,
                            const double *w, double mE, double mH, double *phi)
 {
     const int nf = (model == GKS_TM2D) ? 3 : 6;
     const int nd = (model == GKS_TM2D) ? 2 : 3;
-    static const int tm[3] = {2, 3, 4};
-    double UL[6] = {0}, UR[6] = {0}, dL[3][6] = {{0}}, dR[3][6] = {{0}};
+    int axes[3] = {ax, 0, 0};
+    for (int i = 0, k = 1; i < nd; ++i)
+        if (i != ax) axes[k++] = i;
+    double UL[6] = {0}, UR[6] = {0}, gL[3][6] = {{0}}, gR[3][6] = {{0}};
     for (int q = 0; q < nf; ++q) {
-        const int f = (nf == 3) ? tm[q] : q;
+        const int f = (nf == 3) ? tm_component(q) : q;
         UL[f] = w[q];
         UR[f] = w[nf + q];
         for (int j = 0; j < nd; ++j) {
-            dL[j][f] = w[2 * nf + j * nf + q];
-            dR[j][f] = w[2 * nf + nd * nf + j * nf + q];
+            const int i = axes[j];
+            gL[i][f] = w[2 * nf + j * nf + q] / (dfac * h[i]);
+            gR[i][f] = w[2 * nf + nd * nf + j * nf + q] / (dfac * h[i]);
         }
     }
-    double Ul[6], Ur[6], sl[3][6] = {{0}}, sr[3][6] = {{0}};
+    double n[3] = {0, 0, 0};
+    n[ax] = 1.0;
+    double T[3][3];
+    face_rotation(n, T);
+    double Ugl[6], Ugr[6], Ul[6], Ur[6], sl[3][6], sr[3][6];
     for (int f = 0; f < 6; ++f) {
-        Ul[f] = UL[f] + 0.5 * dL[0][f];
-        Ur[f] = UR[f] - 0.5 * dR[0][f];
-        for (int j = 0; j < nd; ++j) {
-            sl[j][f] = dL[j][f] / h[j];
-            sr[j][f] = dR[j][f] / h[j];
-        }
+        Ugl[f] = UL[f] + 0.5 * h[ax] * gL[ax][f];
+        Ugr[f] = UR[f] - 0.5 * h[ax] * gR[ax][f];
     }
-    double out[6];
+    rotate_fields(T, Ugl, Ul, false);
+    rotate_fields(T, Ugr, Ur, false);
+    for (int j = 0; j < 3; ++j) {
+        double al[6] = {0}, ar[6] = {0};
+        for (int i = 0; i < 3; ++i)
+            for (int f = 0; f < 6; ++f) {
+                al[f] += T[j][i] * gL[i][f];
+                ar[f] += T[j][i] * gR[i][f];
+            }
+        rotate_fields(T, al, sl[j], false);
+        rotate_fields(T, ar, sr[j], false);
+    }
+    double out[6], Fg[6];
     closed_flux(nd, c, C, Ul, Ur, sl, sr, mE, mH, out);
+    rotate_fields(T, out, Fg, true);
     for (int q = 0; q < nf; ++q) {
-        const int f = (nf == 3) ? tm[q] : q;
-        phi[q] = out[f] / h[0];     // (dt/h_n) F~ = (dt F~)/h_n
+        const int f = (nf == 3) ? tm_component(q) : q;
+        phi[q] = Fg[f] / h[ax];
     }
 }
 
@@ -245,22 +289,21 @@ static bool probe(int nout, int nin, Eval ev, const Pattern &pat, double *k0, do
            compress(DH, pat.nH, pat.rH, pat.cH, kh, "KH");
 }
 
-bool cart_face_operator(int model, double c, const double C[5], double dt, const double h[3], double *k0,
-                        double *ke, double *kh, char *err, size_t errlen)
+bool cart_face_operator(int model, int axis, double c, const double C[5], const double h[3], double dfac,
+                        double *k0, double *ke, double *kh, char *err, size_t errlen)
 {
     const int nf = (model == GKS_TM2D) ? 3 : 6;
     const int nin = (model == GKS_TM2D) ? 18 : 48;
-    const Pattern &pat = (model == GKS_TM2D) ? pattern_tm() : pattern_em();
     auto ev = [&](const double *w, double mE, double mH, double *phi) {
-        cart_flux_eval(model, c, C, dt, h, w, mE, mH, phi);
+        cart_flux_eval(model, axis, c, C, h, dfac, w, mE, mH, phi);
     };
-    return probe(nf, nin, ev, pat, k0, ke, kh, err, errlen);
+    return probe(nf, nin, ev, pattern_cart(model, axis), k0, ke, kh, err, errlen);
 }
 
 bool tri_face_operator(double c, const double C[5], double *k0, double *ke, double *kh, char *err, size_t errlen)
 {
     auto ev = [&](const double *w, double mE, double mH, double *phi) { face_flux_eval(c, C, w, mE, mH, phi); };
-    return probe(3, 18, ev, pattern_tm(), k0, ke, kh, err, errlen);
+    return probe(3, 18, ev, pattern_tri(), k0, ke, kh, err, errlen);
 }
 
 }  // namespace gks

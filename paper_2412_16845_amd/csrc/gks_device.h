@@ -12,28 +12,80 @@ constexpr int WAVE = 64;
 
 // ------------------------------------------------------------------ cross-lane moves (DPP)
 // from_right(v): lane i receives lane i+1 (wave_shl:1); from_left(v): lane i receives lane i-1
-// (wave_shr:1).  The end lanes receive 0 (only halo lanes read them).
+// (wave_shr:1).  bound_ctrl makes the end lane (which has no source) receive 0; only halo lanes
+// read it.
+__device__ __forceinline__ int dpp_shl1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_shr1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true); }
+
 __device__ __forceinline__ float from_right(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, dpp_shl1(__builtin_bit_cast(int, v)));
 }
 __device__ __forceinline__ float from_left(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, dpp_shr1(__builtin_bit_cast(int, v)));
 }
 __device__ __forceinline__ double from_right(double v)
 {
     const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x130, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, false);
+    const int lo = dpp_shl1((int)(b & 0xffffffffll));
+    const int hi = dpp_shl1((int)(b >> 32));
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ double from_left(double v)
 {
     const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x138, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, false);
+    const int lo = dpp_shr1((int)(b & 0xffffffffll));
+    const int hi = dpp_shr1((int)(b >> 32));
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// ------------------------------------------------------------------ buffer memory access
+// Raw buffer loads/stores: a 128-bit resource (base, size) in scalar registers, a per-lane
+// 32-bit byte offset in a vector register and a uniform 32-bit byte offset in a scalar
+// register, so the per-row address arithmetic runs on the scalar unit.  Accesses at or beyond
+// the resource size read 0 / are dropped by the hardware.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int RSRC_DWORD3 = 0x00020000;   // 32-bit data format, raw (stride 0) buffer
+
+__device__ __forceinline__ Rsrc make_rsrc(const void *p, uint64_t bytes)
+{
+    const uint32_t n = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)n, RSRC_DWORD3);
+}
+
+template <typename T> __device__ __forceinline__ T buf_load(Rsrc r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ float buf_load<float>(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ double buf_load<double>(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+// Two adjacent floats (one 8-byte access per lane).
+__device__ __forceinline__ float2 buf_load_f2(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+#ifndef GKS_STORE_AUX
+#define GKS_STORE_AUX 0
+#endif
+__device__ __forceinline__ void buf_store(float v, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, voff, soff, GKS_STORE_AUX);
+}
+__device__ __forceinline__ void buf_store(double v, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    using v2u = __attribute__((ext_vector_type(2))) unsigned int;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, voff, soff, GKS_STORE_AUX);
+}
+
+__device__ __forceinline__ void buf_store_f2(float2 v, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    using v2u = __attribute__((ext_vector_type(2))) unsigned int;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, voff, soff, GKS_STORE_AUX);
 }
 
 // ------------------------------------------------------------------ boundary index maps
@@ -60,58 +112,87 @@ __device__ __forceinline__ int map_axis(int g, int n, int bclo, int bchi, bool &
     return g;
 }
 
-// ------------------------------------------------------------------ sparse face operators
-// phi = K0 w + mE KE w + mH KH w using the compile-time sparsity tables.
-template <typename T>
-__device__ __forceinline__ void apply_tm(const T (&w)[18], T mE, T mH, const FaceOpTM<T> &K, T (&phi)[3])
+// ------------------------------------------------------------------ coefficient access
+// Face-operator coefficients live in a small device buffer of the context.  They are read
+// through the constant address space (scalar loads into SGPRs, served by the scalar cache)
+// right where a face is evaluated: the empty asm hides the pointer's loop invariance so the
+// loads are not hoisted into a register set that would not fit the SGPR file.
+template <typename Op>
+using ConstPtr = const __attribute__((address_space(4))) Op *;
+
+template <typename Op>
+__device__ __forceinline__ ConstPtr<Op> scalar_ptr(const Op *p)
 {
-    T a[3] = {T(0), T(0), T(0)}, e[3] = {T(0), T(0), T(0)}, h[3] = {T(0), T(0), T(0)};
+    ConstPtr<Op> q = (ConstPtr<Op>)p;
+    asm volatile("" : "+s"(q));
+    return q;
+}
+
+// ------------------------------------------------------------------ sparse face operators
+// phi = K0 w + mE KE w + mH KH w for the face orientation described by the table struct P
+// (callers pass mE, mH as the SUM of the two cells' 1/eps, 1/mu: the host halves KE, KH)
+// (gks_pattern.h); the loops unroll into straight-line FMAs on the structural non-zeros.
+// K points to the coefficients (a ConstPtr from scalar_ptr).
+template <typename P, typename T, int NF, int NIN, typename Op>
+__device__ __forceinline__ void apply_op(const T (&w)[NIN], T mE, T mH, Op K, T (&phi)[NF])
+{
+    T a[NF], e[NF], h[NF];
 #pragma unroll
-    for (int q = 0; q < TM_N0; ++q) a[TM_R0[q]] = fma(K.k0[q], w[TM_C0[q]], a[TM_R0[q]]);
+    for (int r = 0; r < NF; ++r) a[r] = e[r] = h[r] = T(0);
 #pragma unroll
-    for (int q = 0; q < TM_NE; ++q) e[TM_RE[q]] = fma(K.ke[q], w[TM_CE[q]], e[TM_RE[q]]);
+    for (int q = 0; q < P::N0; ++q) a[P::R0[q]] = fma(K->k0[q], w[P::C0[q]], a[P::R0[q]]);
 #pragma unroll
-    for (int q = 0; q < TM_NH; ++q) h[TM_RH[q]] = fma(K.kh[q], w[TM_CH[q]], h[TM_RH[q]]);
+    for (int q = 0; q < P::NE; ++q) e[P::RE[q]] = fma(K->ke[q], w[P::CE[q]], e[P::RE[q]]);
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
+    for (int q = 0; q < P::NH; ++q) h[P::RH[q]] = fma(K->kh[q], w[P::CH[q]], h[P::RH[q]]);
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
         T v = a[r];
-        if (TM_EROWS >> r & 1u) v = fma(mE, e[r], v);
-        if (TM_HROWS >> r & 1u) v = fma(mH, h[r], v);
+        if ((P::EROWS >> r) & 1u) v = fma(mE, e[r], v);
+        if ((P::HROWS >> r) & 1u) v = fma(mH, h[r], v);
         phi[r] = v;
     }
 }
 
 // Transpose: wbar += K(mE, mH)^T abar.
-template <typename T>
-__device__ __forceinline__ void apply_tm_transpose(const T (&abar)[3], T mE, T mH, const FaceOpTM<T> &K,
-                                                   T (&wbar)[18])
+template <typename P, typename T, int NF, int NIN, typename Op>
+__device__ __forceinline__ void apply_op_transpose(const T (&abar)[NF], T mE, T mH, Op K, T (&wbar)[NIN])
 {
-    T ae[3], ah[3];
+    T ae[NF], ah[NF];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
+    for (int r = 0; r < NF; ++r) {
         ae[r] = mE * abar[r];
         ah[r] = mH * abar[r];
     }
 #pragma unroll
-    for (int q = 0; q < TM_N0; ++q) wbar[TM_C0[q]] = fma(K.k0[q], abar[TM_R0[q]], wbar[TM_C0[q]]);
+    for (int q = 0; q < P::N0; ++q) wbar[P::C0[q]] = fma(K->k0[q], abar[P::R0[q]], wbar[P::C0[q]]);
 #pragma unroll
-    for (int q = 0; q < TM_NE; ++q) wbar[TM_CE[q]] = fma(K.ke[q], ae[TM_RE[q]], wbar[TM_CE[q]]);
+    for (int q = 0; q < P::NE; ++q) wbar[P::CE[q]] = fma(K->ke[q], ae[P::RE[q]], wbar[P::CE[q]]);
 #pragma unroll
-    for (int q = 0; q < TM_NH; ++q) wbar[TM_CH[q]] = fma(K.kh[q], ah[TM_RH[q]], wbar[TM_CH[q]]);
+    for (int q = 0; q < P::NH; ++q) wbar[P::CH[q]] = fma(K->kh[q], ah[P::RH[q]], wbar[P::CH[q]]);
 }
 
-// abar . (KE w) and abar . (KH w): the derivatives of abar . phi with respect to mE and mH.
-template <typename T>
-__device__ __forceinline__ void material_sens_tm(const T (&abar)[3], const T (&w)[18], const FaceOpTM<T> &K,
-                                                 T &dE, T &dH)
+// abar . (KE w) and abar . (KH w): derivatives of abar . phi with respect to mE and mH.
+template <typename P, typename T, int NF, int NIN, typename Op>
+__device__ __forceinline__ void material_sens(const T (&abar)[NF], const T (&w)[NIN], Op K, T &dE, T &dH)
 {
     T e = T(0), h = T(0);
 #pragma unroll
-    for (int q = 0; q < TM_NE; ++q) e = fma(K.ke[q] * abar[TM_RE[q]], w[TM_CE[q]], e);
+    for (int q = 0; q < P::NE; ++q) e = fma(K->ke[q] * abar[P::RE[q]], w[P::CE[q]], e);
 #pragma unroll
-    for (int q = 0; q < TM_NH; ++q) h = fma(K.kh[q] * abar[TM_RH[q]], w[TM_CH[q]], h);
+    for (int q = 0; q < P::NH; ++q) h = fma(K->kh[q] * abar[P::RH[q]], w[P::CH[q]], h);
     dE = e;
     dH = h;
+}
+
+// Work distribution: workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Renumber them so that every XCD receives one contiguous range of logical workgroups,
+// i.e. a contiguous band of tiles whose shared halo rows and columns stay in that XCD's L2.
+__device__ __forceinline__ int xcd_logical_block()
+{
+    const int nb = gridDim.x, bid = blockIdx.x;
+    const int x = bid % 8, per = nb / 8, rem = nb % 8;
+    return x * per + min(x, rem) + bid / 8;
 }
 
 }  // namespace gks

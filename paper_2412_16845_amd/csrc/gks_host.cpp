@@ -32,6 +32,8 @@ struct gks_ctx {
     double unstable_growth = 0;
     hipStream_t stream = nullptr;
     int device = 0;
+    int ncu = 256;                  // compute units of the device
+    int32_t tile_y = 64;            // rows per wave tile (Cartesian 2D)
     const void *epsinv = nullptr, *muinv = nullptr;
 
     // face operators in double precision: [orientation][...]
@@ -45,6 +47,7 @@ struct gks_ctx {
     double *d_src_w = nullptr;
 
     // owned device buffers
+    void *d_ops = nullptr;          // face operators in the context's precision
     void *pingpong = nullptr;
     size_t pingpong_bytes = 0;
     double *d_partial = nullptr;
@@ -96,13 +99,68 @@ bool ranges_overlap(const void *a, const void *b, size_t n)
     return pa < pb + n && pb < pa + n;
 }
 
-template <typename T>
-void fill_op(FaceOpTM<T> &o, const double *k0, const double *ke, const double *kh)
+// Device form of a face operator: the kernels pass the sum of the two cells' 1/eps (1/mu)
+// instead of their mean, so KE and KH are stored halved.
+template <typename T, int N0, int NE, int NH>
+void fill_op(FaceOp<T, N0, NE, NH> &o, const double *k0, const double *ke, const double *kh)
 {
-    for (int q = 0; q < TM_N0; ++q) o.k0[q] = (T)k0[q];
-    for (int q = 0; q < TM_NE; ++q) o.ke[q] = (T)ke[q];
-    for (int q = 0; q < TM_NH; ++q) o.kh[q] = (T)kh[q];
+    for (int q = 0; q < N0; ++q) o.k0[q] = (T)k0[q];
+    for (int q = 0; q < NE; ++q) o.ke[q] = (T)(0.5 * ke[q]);
+    for (int q = 0; q < NH; ++q) o.kh[q] = (T)(0.5 * kh[q]);
 }
+
+template <typename T>
+void pack_ops(const gks_ctx *x, std::vector<char> &buf)
+{
+    if (x->model == GKS_TM2D) {
+        std::vector<FaceOpTM<T>> ops(2);
+        for (int ax = 0; ax < 2; ++ax) fill_op(ops[ax], x->k0[ax], x->ke[ax], x->kh[ax]);
+        buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
+    } else {
+        std::vector<FaceOpEM<T>> ops(3);
+        for (int ax = 0; ax < 3; ++ax) fill_op(ops[ax], x->k0[ax], x->ke[ax], x->kh[ax]);
+        buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
+    }
+}
+
+// Copies the face operators, rounded once to the storage precision, to device memory.
+gks_status upload_ops(gks_ctx *x)
+{
+    std::vector<char> buf;
+    if (x->prec == GKS_FP64) pack_ops<double>(x, buf);
+    else pack_ops<float>(x, buf);
+    if (hipMalloc(&x->d_ops, buf.size()) != hipSuccess) return fail(x, GKS_ENOMEM, "cannot allocate face operators");
+    int e = hipMemcpy(x->d_ops, buf.data(), buf.size(), hipMemcpyHostToDevice);
+    if (e) return hip_fail(x, e, "face operator upload");
+    return GKS_OK;
+}
+
+}  // namespace
+
+int gks::cart2d_pick_tile_y(int nx, int ny, int batch, int ncu)
+{
+#ifdef GKS_FORCE_TILE_Y
+    return GKS_FORCE_TILE_Y;   // build-time override for tuning sweeps
+#endif
+    const int64_t ntx = (nx + cart2d_tile_x() - 1) / cart2d_tile_x();
+    int best = 64;
+    double best_cost = 1e300;
+    for (int ty = 16; ty <= 256; ++ty) {
+        const int64_t nty = (ny + ty - 1) / ty;
+        const int64_t wgs = (ntx * nty * batch + 3) / 4;
+        const int64_t per_cu = (wgs + ncu - 1) / ncu;
+        const int rows = std::min(ty, ny);
+        const double cost = (double)per_cu * (rows + 4);
+        if (cost < best_cost - 1e-9) {
+            best_cost = cost;
+            best = ty;
+        }
+        if (ty >= ny) break;
+    }
+    return best;
+}
+
+namespace {
 
 double source_pulse(const gks_ctx *x, double t)
 {
@@ -124,9 +182,9 @@ gks_status step_cart2d(gks_ctx *x, const void *Uin, void *Uout, double tn)
     a.batch = (int32_t)x->batch;
     for (int i = 0; i < 4; ++i) a.bc[i] = x->bc[i];
     a.ntx = (a.nx + cart2d_tile_x() - 1) / cart2d_tile_x();
-    a.nty = (a.ny + cart2d_tile_y() - 1) / cart2d_tile_y();
-    fill_op(a.fx, x->k0[0], x->ke[0], x->kh[0]);
-    fill_op(a.fy, x->k0[1], x->ke[1], x->kh[1]);
+    a.tile_y = x->tile_y;
+    a.nty = (a.ny + a.tile_y - 1) / a.tile_y;
+    a.ops = (const FaceOpTM<T> *)x->d_ops;
     const int64_t ns = (int64_t)x->src_cells.size();
     const double amp = ns ? -x->dt * source_pulse(x, tn) : 0.0;   // dt * S_z = -dt J_z
     if (ns > 0 && ns <= MAX_FUSED_SRC) {
@@ -264,6 +322,10 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
         x->nfields = (m->model == GKS_TM2D) ? 3 : 6;
         if ((int64_t)x->nfields * x->ncell > ((int64_t)1 << 31) - 1)
             return bail(fail(x, GKS_EINVAL, "grid too large for 32-bit field indexing"));
+        // the kernels address one batch item's fields with 32-bit byte offsets
+        const int64_t esz = (m->precision == GKS_FP64) ? 8 : 4;
+        if ((int64_t)x->nfields * x->ncell * esz > (int64_t)0xFFFFFFFF)
+            return bail(fail(x, GKS_EINVAL, "grid too large: one batch item's fields exceed 4 GiB"));
         const double hmin = (nd == 2) ? std::min(x->h[0], x->h[1]) : std::min(x->h[0], std::min(x->h[1], x->h[2]));
         x->dt = (p->dt > 0) ? p->dt : p->cfl * hmin / p->c;
         if (!(x->dt > 0) || !std::isfinite(x->dt)) return bail(fail(x, GKS_EINVAL, "dt must be positive (set dt or cfl)"));
@@ -281,14 +343,27 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
 
     // face operators: local frames of the x-, y- (and z-) faces
     char err[256];
-    if (x->kind == GKS_CART2D) {
-        const double hx[3] = {x->h[0], x->h[1], 1.0}, hy[3] = {x->h[1], x->h[0], 1.0};
-        if (!cart_face_operator(GKS_TM2D, x->c, x->C, x->dt, hx, x->k0[0], x->ke[0], x->kh[0], err, sizeof err) ||
-            !cart_face_operator(GKS_TM2D, x->c, x->C, x->dt, hy, x->k0[1], x->ke[1], x->kh[1], err, sizeof err))
-            return bail(fail(x, GKS_EINVAL, "%s", err));
+    if (x->kind == GKS_CART2D || x->kind == GKS_CART3D) {
+        // the kernels feed full central differences U(i+1) - U(i-1) = 2 h dU/dx
+        const int nax = (x->kind == GKS_CART2D) ? 2 : 3;
+        for (int ax = 0; ax < nax; ++ax)
+            if (!cart_face_operator(x->model, ax, x->c, x->C, x->h, 2.0, x->k0[ax], x->ke[ax], x->kh[ax], err,
+                                    sizeof err))
+                return bail(fail(x, GKS_EINVAL, "%s", err));
     }
 
     if (hipGetDevice(&x->device) != hipSuccess) return bail(fail(x, GKS_EDEVICE, "no HIP device"));
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, x->device) == hipSuccess && ncu > 0)
+            x->ncu = ncu;
+    }
+    if (x->kind == GKS_CART2D)
+        x->tile_y = cart2d_pick_tile_y((int)x->n[0], (int)x->n[1], (int)x->batch, x->ncu);
+    {
+        gks_status st = upload_ops(x);
+        if (st) return bail(st);
+    }
     x->nblk = 1024;
     if (hipMalloc((void **)&x->d_partial, sizeof(double) * x->nblk * x->batch) != hipSuccess)
         return bail(fail(x, GKS_ENOMEM, "cannot allocate reduction scratch"));
@@ -299,6 +374,7 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
 extern "C" gks_status gks_destroy(gks_ctx *ctx)
 {
     if (!ctx) return GKS_OK;
+    if (ctx->d_ops) hipFree(ctx->d_ops);
     if (ctx->pingpong) hipFree(ctx->pingpong);
     if (ctx->d_partial) hipFree(ctx->d_partial);
     if (ctx->d_out) hipFree(ctx->d_out);

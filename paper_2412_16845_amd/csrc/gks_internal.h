@@ -15,15 +15,17 @@ struct Pattern {
     int n0, nE, nH;
     const uint8_t *r0, *c0, *rE, *cE, *rH, *cH;
 };
-const Pattern &pattern_tm();
-const Pattern &pattern_em();
+const Pattern &pattern_cart(int model, int axis);
+const Pattern &pattern_tri();
 
 constexpr int TM_N0 = 24, TM_NE = 6, TM_NH = 4;
 constexpr int EM_N0 = 80, EM_NE = 12, EM_NH = 12;
 
 void flux_coefficients(double dt, double tau, double C[5]);
-bool cart_face_operator(int model, double c, const double C[5], double dt, const double h[3], double *k0,
-                        double *ke, double *kh, char *err, size_t errlen);
+// Face operator of an axis-aligned Cartesian face (normal +e_axis), global-frame inputs whose
+// differences are dfac * h * slope; output (dt/h_axis) * F.
+bool cart_face_operator(int model, int axis, double c, const double C[5], const double h[3], double dfac,
+                        double *k0, double *ke, double *kh, char *err, size_t errlen);
 bool tri_face_operator(double c, const double C[5], double *k0, double *ke, double *kh, char *err,
                        size_t errlen);
 
@@ -50,7 +52,8 @@ struct Cart2DArgs {
     int32_t batch;
     int32_t bc[4];        // x-, x+, y-, y+
     int32_t ntx, nty;     // tiles per row / column
-    FaceOpTM<T> fx, fy;   // x-face and y-face operators (local frame of each)
+    int32_t tile_y;       // rows per tile
+    const FaceOpTM<T> *ops;   // device: x-face and y-face operators
     int32_t nsrc;         // fused point sources (<= MAX_FUSED_SRC)
     int32_t src_cell[MAX_FUSED_SRC];
     double src_amp[MAX_FUSED_SRC];   // dt * S_z = -dt * J_z(t^n) (before the 1/eps factor)
@@ -69,7 +72,8 @@ struct Cart2DAdjArgs {
     int32_t nx, ny, batch;
     int32_t bc[4];
     int32_t ntx, nty;
-    FaceOpTM<T> fx, fy;
+    int32_t tile_y;
+    const FaceOpTM<T> *ops;   // device: x-face and y-face operators
     int32_t nsrc;
     int32_t src_cell[MAX_FUSED_SRC];
     double src_amp[MAX_FUSED_SRC];
@@ -83,7 +87,10 @@ template <typename T> int launch_source_scatter(T *U, const T *epsinv, int64_t n
                                                 int32_t batch, int32_t field, const int64_t *cells,
                                                 const double *weight, double amp, int32_t n, void *stream);
 int cart2d_tile_x();
-int cart2d_tile_y();
+// Rows per wave tile for an nx x ny x batch grid on a device with ncu compute units: the
+// kernel is throughput bound per compute unit, so the step time follows the largest number of
+// 4-wave workgroups any unit receives times the rows each wave marches (plus its 4 halo rows).
+int cart2d_pick_tile_y(int nx, int ny, int batch, int ncu);
 
 // Energy: partial sums per (batch, block) then a fixed-order final sum; all FP64.
 template <typename T>

@@ -3,15 +3,19 @@
 
 namespace gks {
 
-const Pattern &pattern_tm()
+template <typename P>
+static const Pattern &make()
 {
-    static const Pattern p{TM_N0, TM_NE, TM_NH, TM_R0, TM_C0, TM_RE, TM_CE, TM_RH, TM_CH};
+    static const Pattern p{P::N0, P::NE, P::NH, P::R0, P::C0, P::RE, P::CE, P::RH, P::CH};
     return p;
 }
-const Pattern &pattern_em()
+
+const Pattern &pattern_cart(int model, int axis)
 {
-    static const Pattern p{EM_N0, EM_NE, EM_NH, EM_R0, EM_C0, EM_RE, EM_CE, EM_RH, EM_CH};
-    return p;
+    if (model == GKS_TM2D) return axis == 0 ? make<PatTMx>() : make<PatTMy>();
+    return axis == 0 ? make<PatEMx>() : (axis == 1 ? make<PatEMy>() : make<PatEMz>());
 }
+
+const Pattern &pattern_tri() { return make<PatTri>(); }
 
 }  // namespace gks

@@ -1,9 +1,12 @@
-// Sparsity tables of the Cartesian face operators (host and device).  Inputs, local frame:
-//   TM2D (18): [UL UR d1L d2L d1R d2R] x (Ez, Hx, Hy)
-//   EM3D (48): [UL UR d1L d2L d3L d1R d2R d3R] x (Ex, Ey, Ez, Hx, Hy, Hz)
-// Rows are the output components.  The same TM tables serve the triangle face operator
-// (inputs [Ul Ur s1l s2l s1r s2r]).  Context creation verifies that every entry of the probed
-// operators outside these tables is exactly zero.
+// Sparsity tables of the face operators (host and device), one struct per face orientation.
+// Cartesian faces take global-frame inputs
+//   TM (18): [UL UR dnL dtL dnR dtR] x (Ez, Hx, Hy)
+//   EM (48): [UL UR dnL dt1L dt2L dnR dt1R dt2R] x (Ex, Ey, Ez, Hx, Hy, Hz)
+// with dn the central difference along the face normal and dt1, dt2 along the other axes in
+// increasing order; rows are the global output components.  PatTri takes face-frame inputs
+// [Ul Ur s1l s2l s1r s2r] x (Ez, Hn, Ht) (triangle faces).  N0/NE/NH count the entries of K0,
+// KE (times 1/eps) and KH (times 1/mu); EROWS/HROWS flag the rows KE/KH reach.  Context
+// creation probes the closed-form flux and verifies that every other entry is exactly zero.
 #pragma once
 #include <cstdint>
 
@@ -11,27 +14,95 @@
 
 namespace gks {
 
-constexpr uint8_t TM_R0[TM_N0] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2};
-constexpr uint8_t TM_C0[TM_N0] = {0, 2, 3, 5, 6, 8, 10, 12, 14, 16, 1, 4, 7, 9, 13, 15, 0, 2, 3, 5, 6, 8, 12, 14};
-constexpr uint8_t TM_RE[TM_NE] = {2, 2, 2, 2, 2, 2};
-constexpr uint8_t TM_CE[TM_NE] = {6, 8, 10, 12, 14, 16};
-constexpr uint8_t TM_RH[TM_NH] = {0, 0, 0, 0};
-constexpr uint8_t TM_CH[TM_NH] = {6, 8, 12, 14};
+struct PatTMx {
+    static constexpr int N0 = 24;
+    static constexpr uint8_t R0[24] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2};
+    static constexpr uint8_t C0[24] = {0, 2, 3, 5, 6, 8, 10, 12, 14, 16, 1, 4, 7, 9, 13, 15, 0, 2, 3, 5, 6, 8, 12, 14};
+    static constexpr int NE = 6;
+    static constexpr uint8_t RE[6] = {2, 2, 2, 2, 2, 2};
+    static constexpr uint8_t CE[6] = {6, 8, 10, 12, 14, 16};
+    static constexpr uint32_t EROWS = 0x4u;
+    static constexpr int NH = 4;
+    static constexpr uint8_t RH[4] = {0, 0, 0, 0};
+    static constexpr uint8_t CH[4] = {6, 8, 12, 14};
+    static constexpr uint32_t HROWS = 0x1u;
+};
 
-constexpr uint8_t EM_R0[EM_N0] = {
-    0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2,
-    3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5};
-constexpr uint8_t EM_C0[EM_N0] = {
-    0,  6,  12, 20, 22, 23, 25, 28, 29, 30, 38, 40, 41, 43, 46, 47, 1,  5,  7,  11, 13, 17, 21, 27, 31, 35, 39, 45,
-    2,  4,  8,  10, 14, 16, 21, 27, 32, 34, 39, 45, 3,  9,  15, 19, 20, 23, 25, 26, 28, 33, 37, 38, 41, 43, 44, 46,
-    2,  4,  8,  10, 14, 16, 18, 24, 32, 34, 36, 42, 1,  5,  7,  11, 13, 17, 18, 24, 31, 35, 36, 42};
-constexpr uint8_t EM_RE[EM_NE] = {4, 4, 4, 4, 4, 4, 5, 5, 5, 5, 5, 5};
-constexpr uint8_t EM_CE[EM_NE] = {14, 16, 21, 32, 34, 39, 13, 17, 27, 31, 35, 45};
-constexpr uint8_t EM_RH[EM_NH] = {1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2};
-constexpr uint8_t EM_CH[EM_NH] = {13, 17, 18, 31, 35, 36, 14, 16, 24, 32, 34, 42};
+struct PatTMy {
+    static constexpr int N0 = 24;
+    static constexpr uint8_t R0[24] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2};
+    static constexpr uint8_t C0[24] = {0, 1, 3, 4, 6, 7, 11, 12, 13, 17, 0, 1, 3, 4, 6, 7, 12, 13, 2, 5, 8, 9, 14, 15};
+    static constexpr int NE = 6;
+    static constexpr uint8_t RE[6] = {1, 1, 1, 1, 1, 1};
+    static constexpr uint8_t CE[6] = {6, 7, 11, 12, 13, 17};
+    static constexpr uint32_t EROWS = 0x2u;
+    static constexpr int NH = 4;
+    static constexpr uint8_t RH[4] = {0, 0, 0, 0};
+    static constexpr uint8_t CH[4] = {6, 7, 12, 13};
+    static constexpr uint32_t HROWS = 0x1u;
+};
 
-// Output rows reached by KE / KH (bit r set = row r has entries).
-constexpr uint32_t TM_EROWS = 1u << 2, TM_HROWS = 1u << 0;
-constexpr uint32_t EM_EROWS = (1u << 4) | (1u << 5), EM_HROWS = (1u << 1) | (1u << 2);
+struct PatEMx {
+    static constexpr int N0 = 80;
+    static constexpr uint8_t R0[80] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5};
+    static constexpr uint8_t C0[80] = {0, 6, 12, 20, 22, 23, 25, 28, 29, 30, 38, 40, 41, 43, 46, 47, 1, 5, 7, 11, 13, 17, 21, 27, 31, 35, 39, 45, 2, 4, 8, 10, 14, 16, 21, 27, 32, 34, 39, 45, 3, 9, 15, 19, 20, 23, 25, 26, 28, 33, 37, 38, 41, 43, 44, 46, 2, 4, 8, 10, 14, 16, 18, 24, 32, 34, 36, 42, 1, 5, 7, 11, 13, 17, 18, 24, 31, 35, 36, 42};
+    static constexpr int NE = 12;
+    static constexpr uint8_t RE[12] = {4, 4, 4, 4, 4, 4, 5, 5, 5, 5, 5, 5};
+    static constexpr uint8_t CE[12] = {14, 16, 21, 32, 34, 39, 13, 17, 27, 31, 35, 45};
+    static constexpr uint32_t EROWS = 0x30u;
+    static constexpr int NH = 12;
+    static constexpr uint8_t RH[12] = {1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2};
+    static constexpr uint8_t CH[12] = {13, 17, 18, 31, 35, 36, 14, 16, 24, 32, 34, 42};
+    static constexpr uint32_t HROWS = 0x6u;
+};
+
+struct PatEMy {
+    static constexpr int N0 = 80;
+    static constexpr uint8_t R0[80] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5};
+    static constexpr uint8_t C0[80] = {0, 5, 6, 11, 12, 17, 22, 28, 30, 35, 40, 46, 1, 7, 13, 20, 21, 23, 24, 27, 29, 31, 38, 39, 41, 42, 45, 47, 2, 3, 8, 9, 14, 15, 22, 28, 32, 33, 40, 46, 2, 3, 8, 9, 14, 15, 19, 25, 32, 33, 37, 43, 4, 10, 16, 18, 20, 23, 24, 26, 27, 34, 36, 38, 41, 42, 44, 45, 0, 5, 6, 11, 12, 17, 19, 25, 30, 35, 37, 43};
+    static constexpr int NE = 12;
+    static constexpr uint8_t RE[12] = {3, 3, 3, 3, 3, 3, 5, 5, 5, 5, 5, 5};
+    static constexpr uint8_t CE[12] = {14, 15, 22, 32, 33, 40, 12, 17, 28, 30, 35, 46};
+    static constexpr uint32_t EROWS = 0x28u;
+    static constexpr int NH = 12;
+    static constexpr uint8_t RH[12] = {0, 0, 0, 0, 0, 0, 2, 2, 2, 2, 2, 2};
+    static constexpr uint8_t CH[12] = {12, 17, 19, 30, 35, 37, 14, 15, 25, 32, 33, 43};
+    static constexpr uint32_t HROWS = 0x5u;
+};
+
+struct PatEMz {
+    static constexpr int N0 = 80;
+    static constexpr uint8_t R0[80] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5};
+    static constexpr uint8_t C0[80] = {0, 4, 6, 10, 12, 16, 23, 29, 30, 34, 41, 47, 1, 3, 7, 9, 13, 15, 23, 29, 31, 33, 41, 47, 2, 8, 14, 19, 21, 22, 24, 27, 28, 32, 37, 39, 40, 42, 45, 46, 1, 3, 7, 9, 13, 15, 20, 26, 31, 33, 38, 44, 0, 4, 6, 10, 12, 16, 20, 26, 30, 34, 38, 44, 5, 11, 17, 18, 19, 22, 24, 25, 27, 35, 36, 37, 40, 42, 43, 45};
+    static constexpr int NE = 12;
+    static constexpr uint8_t RE[12] = {3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4};
+    static constexpr uint8_t CE[12] = {13, 15, 23, 31, 33, 41, 12, 16, 29, 30, 34, 47};
+    static constexpr uint32_t EROWS = 0x18u;
+    static constexpr int NH = 12;
+    static constexpr uint8_t RH[12] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1};
+    static constexpr uint8_t CH[12] = {12, 16, 20, 30, 34, 38, 13, 15, 26, 31, 33, 44};
+    static constexpr uint32_t HROWS = 0x3u;
+};
+
+struct PatTri {
+    static constexpr int N0 = 24;
+    static constexpr uint8_t R0[24] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2};
+    static constexpr uint8_t C0[24] = {0, 2, 3, 5, 6, 8, 10, 12, 14, 16, 1, 4, 7, 9, 13, 15, 0, 2, 3, 5, 6, 8, 12, 14};
+    static constexpr int NE = 6;
+    static constexpr uint8_t RE[6] = {2, 2, 2, 2, 2, 2};
+    static constexpr uint8_t CE[6] = {6, 8, 10, 12, 14, 16};
+    static constexpr uint32_t EROWS = 0x4u;
+    static constexpr int NH = 4;
+    static constexpr uint8_t RH[4] = {0, 0, 0, 0};
+    static constexpr uint8_t CH[4] = {6, 8, 12, 14};
+    static constexpr uint32_t HROWS = 0x1u;
+};
+
+static_assert(PatTMx::N0 == TM_N0 && PatTMx::NE == TM_NE && PatTMx::NH == TM_NH, "TM table size");
+static_assert(PatTMy::N0 == TM_N0 && PatTMy::NE == TM_NE && PatTMy::NH == TM_NH, "TM table size");
+static_assert(PatTri::N0 == TM_N0 && PatTri::NE == TM_NE && PatTri::NH == TM_NH, "TM table size");
+static_assert(PatEMx::N0 == EM_N0 && PatEMx::NE == EM_NE && PatEMx::NH == EM_NH, "EM table size");
+static_assert(PatEMy::N0 == EM_N0 && PatEMy::NE == EM_NE && PatEMy::NH == EM_NH, "EM table size");
+static_assert(PatEMz::N0 == EM_N0 && PatEMz::NE == EM_NE && PatEMz::NH == EM_NH, "EM table size");
 
 }  // namespace gks

@@ -1,58 +1,192 @@
 // Fused GKS step on a 2D Cartesian grid, TM fields (Ez, Hx, Hy).
 //
 // One wavefront owns a strip of 64 columns (60 written, 2 halo columns on each side) and
-// marches TILE_Y rows upwards, keeping three rows of fields, two rows of gradients and the
-// previous horizontal-face flux in registers.  Each field value is loaded once per strip row;
-// neighbours along x come from the adjacent lanes through DPP moves, so no LDS and no
-// barriers are needed.  Per row the wave:
-//   1. loads the next row (structure-of-arrays, 64 consecutive values per field: coalesced),
-//      mapping ghost rows/columns through the boundary conditions;
-//   2. forms the Green-Gauss (central) half-differences of the middle row (Sec. 3.1);
+// marches a tile of rows upwards (the tile height is chosen by the host to balance the
+// workgroups over the compute units).  Each field value is loaded once per strip row; neighbours along
+// x come from the adjacent lanes through DPP moves, so no LDS and no barriers are needed.
+// Per row the wave:
+//   1. issues the loads of the row PF rows ahead (structure-of-arrays, 64 consecutive values
+//      per field: coalesced), so that several rows of loads are in flight while it computes;
+//   2. forms the Green-Gauss (central) differences of the middle row of its three-row window;
 //   3. evaluates the GKS flux of the horizontal face below the middle row and of the vertical
 //      face right of each lane, as sparse linear forms of the stencil values (the closed-form
 //      moments of Sec. 3.1 folded into coefficients on the host);
-//   4. sums the four face terms of the row it finishes in double precision, adds the old
-//      value and the explicit source, and stores once.
-// Non-reflecting sides: the ghost side of a boundary face carries no distribution (zero state
-// and slopes); the ghost value used by the Green-Gauss gradient is the cell's own.  PEC
-// sides: mirror ghosts (Ez and the normal H odd, the tangential H even).  Periodic sides wrap.
+//   4. sums the four face terms of the row it finishes in double precision, adds the old value
+//      and the explicit source, and stores once.
+// The row loop is unrolled six times so that the rotating window (six row slots, two gradient
+// slots, two flux slots) lives in fixed registers without copies.
+// Strips that touch no domain side take a path without index mapping.  On the others, ghost
+// rows/columns follow the boundary condition: non-reflecting sides give the ghost side of a
+// boundary face no distribution (zero state and slopes) and the Green-Gauss gradient the cell's
+// own value; PEC sides read mirror ghosts (Ez and the normal H odd, the tangential H even);
+// periodic sides wrap.
 #include "gks_device.h"
 
 namespace gks {
 
 constexpr int HALO = 2;
 constexpr int OUTX = WAVE - 2 * HALO;   // columns written per wave
-constexpr int TILE_Y = 64;              // rows written per wave
+constexpr int PF = 3;   // rows loaded ahead of use: with the three-row window, six row slots
 
 template <typename T>
 struct Row2D {
     T u[3];      // Ez, Hx, Hy (mirror signs applied)
     T mE, mH;    // 1/eps, 1/mu of the cell read
-    bool nr;     // non-reflecting ghost
+    bool nr;     // non-reflecting ghost (boundary strips only)
 };
 
-template <typename T, bool HAS_EPS, bool HAS_MU>
-__device__ __forceinline__ void load_row(const Cart2DArgs<T> &a, const T *Ub, const T *Eb, const T *Mb, int64_t ncell,
-                                         int sx, T sgx0, T sgx1, bool nrx, int gy, Row2D<T> &r)
-{
-    bool mir, nry;
-    const int sy = map_axis(gy, a.ny, a.bc[2], a.bc[3], mir, nry);
-    const int64_t c = (int64_t)sy * a.nx + sx;
-    // y-mirror signs: Ez odd, Hx (tangential) even, Hy (normal) odd
-    const T sy0 = mir ? T(-1) : T(1);
-    r.u[0] = Ub[c] * (sgx0 * sy0);
-    r.u[1] = Ub[ncell + c] * sgx0;
-    r.u[2] = Ub[2 * ncell + c] * (sgx1 * sy0);
-    r.mE = HAS_EPS ? Eb[c] : T(1);
-    r.mH = HAS_MU ? Mb[c] : T(1);
-    r.nr = nry || nrx;
-}
+template <typename T, bool HAS_EPS, bool HAS_MU, bool BND>
+struct Strip2D {
+    const Cart2DArgs<T> &a;
+    Rsrc rU, rE, rM, rO;   // this batch item's fields, 1/eps, 1/mu, output fields
+    uint32_t fbytes;       // bytes per field array
+    uint32_t vx;           // byte offset of this lane's column (mapped column on boundary strips)
+    uint32_t vlane;        // byte offset of this lane inside the strip
+    int x0;                // first column of the strip (uniform; -2 on the first strip)
+    int gx;                // column of this lane
+    T sgx;                 // x-mirror sign of Ez and Hx
+    bool nrx;
+    bool writer;
+    int y0, y1;
+
+    __device__ __forceinline__ void load(int gy, Row2D<T> &r) const
+    {
+        if constexpr (BND) {
+            bool mir, nry;
+            const int sy = map_axis(gy, a.ny, a.bc[2], a.bc[3], mir, nry);
+            const uint32_t so = (uint32_t)sy * (uint32_t)a.nx * (uint32_t)sizeof(T);
+            const T sgy = mir ? T(-1) : T(1);   // y mirror: Ez and Hy odd, Hx even
+            r.u[0] = buf_load<T>(rU, vx, so) * (sgx * sgy);
+            r.u[1] = buf_load<T>(rU, vx, so + fbytes) * sgx;
+            r.u[2] = buf_load<T>(rU, vx, so + 2 * fbytes) * sgy;
+            r.mE = HAS_EPS ? buf_load<T>(rE, vx, so) : T(1);
+            r.mH = HAS_MU ? buf_load<T>(rM, vx, so) : T(1);
+            r.nr = nry || nrx;
+        } else {
+            const uint32_t so = ((uint32_t)gy * (uint32_t)a.nx + (uint32_t)x0) * (uint32_t)sizeof(T);
+            r.u[0] = buf_load<T>(rU, vx, so);
+            r.u[1] = buf_load<T>(rU, vx, so + fbytes);
+            r.u[2] = buf_load<T>(rU, vx, so + 2 * fbytes);
+            r.mE = HAS_EPS ? buf_load<T>(rE, vx, so) : T(1);
+            r.mH = HAS_MU ? buf_load<T>(rM, vx, so) : T(1);
+            r.nr = false;
+        }
+    }
+
+    // One row step at index q: window rows q-2 (Rs), q-1 (Rc), q (Rn); Rp receives row q+PF.
+    __device__ __forceinline__ void body(int q, Row2D<T> &Rs, Row2D<T> &Rc, Row2D<T> &Rn, Row2D<T> &Rp,
+                                         T (&Ds)[6], T (&Dc)[6], T (&fyS)[3], T (&fyN)[3]) const
+    {
+        // rows beyond y1 + 1 are not needed: re-read row y1 + 1 instead (already cached), which
+        // keeps the load unconditional so the loads in flight are counted exactly
+        load(min(q + PF, y1 + 1), Rp);
+        // central differences of row q-1: [d/dx x (Ez,Hx,Hy), d/dy x (Ez,Hx,Hy)] times 2h
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            Dc[f] = from_right(Rc.u[f]) - from_left(Rc.u[f]);
+            Dc[3 + f] = Rn.u[f] - Rs.u[f];
+        }
+        if (q < y0 + 1) return;
+
+        // horizontal face between rows q-2 and q-1: inputs [UL UR dyL dxL dyR dxR]
+        {
+            const bool zl = BND && Rs.nr, zr = BND && Rc.nr;
+            T w[18];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                w[f] = zl ? T(0) : Rs.u[f];
+                w[3 + f] = zr ? T(0) : Rc.u[f];
+                w[6 + f] = zl ? T(0) : Ds[3 + f];
+                w[9 + f] = zl ? T(0) : Ds[f];
+                w[12 + f] = zr ? T(0) : Dc[3 + f];
+                w[15 + f] = zr ? T(0) : Dc[f];
+            }
+            // face material: the two cells' values (a ghost reads its interior cell); the
+            // operator applies their mean
+            apply_op<PatTMy>(w, Rs.mE + Rc.mE, Rs.mH + Rc.mH, scalar_ptr(a.ops + 1), fyN);
+        }
+        if (q < y0 + 2) return;
+
+        // vertical face right of this lane, row q-2: inputs [UL UR dxL dyL dxR dyR]
+        const bool me_nr = BND && Rs.nr;
+        T ul[3], dl[6];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) ul[f] = me_nr ? T(0) : Rs.u[f];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) dl[f] = me_nr ? T(0) : Ds[f];
+        T v[18];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            v[f] = ul[f];
+            v[3 + f] = from_right(ul[f]);
+            v[6 + f] = dl[f];
+            v[9 + f] = dl[3 + f];
+            v[12 + f] = from_right(dl[f]);
+            v[15 + f] = from_right(dl[3 + f]);
+        }
+        T fx[3];
+        apply_op<PatTMx>(v, Rs.mE + from_right(Rs.mE), Rs.mH + from_right(Rs.mH), scalar_ptr(a.ops), fx);
+        T fxl[3];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) fxl[f] = from_left(fx[f]);
+
+        if (writer) {
+            // per-cell flux divergence (FP32 in FP32 mode), then the old value and the source
+            // added in FP64 with a single rounding
+            // interior strips: uniform offset of the strip start + lane offset; boundary strips
+            // (whose first column may be a ghost): uniform row start + the lane's own column
+            const uint32_t rowc = (uint32_t)(q - 2) * (uint32_t)a.nx;
+            const uint32_t so = BND ? rowc * (uint32_t)sizeof(T) : (rowc + (uint32_t)x0) * (uint32_t)sizeof(T);
+            const uint32_t vo = BND ? (uint32_t)gx * (uint32_t)sizeof(T) : vlane;
+            const int c = (int)rowc + gx;
+            double src = 0.0;
+            for (int s = 0; s < a.nsrc; ++s)
+                if (c == a.src_cell[s]) src += a.src_amp[s];
+            const double mE = (double)Rs.mE, mH = (double)Rs.mH;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const T div = (fx[f] - fxl[f]) + (fyN[f] - fyS[f]);
+                const double m = (f == 0) ? mE : mH;
+                const double add = (f == 0) ? src : 0.0;
+                buf_store((T)((double)Rs.u[f] + m * (add - (double)div)), rO, vo, so + f * fbytes);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void run() const
+    {
+        Row2D<T> R0, R1, R2, R3, R4, R5;
+        T D0[6], D1[6];
+        T F0[3] = {T(0), T(0), T(0)}, F1[3] = {T(0), T(0), T(0)};
+        load(y0 - 2, R0);
+        load(y0 - 1, R1);
+        load(y0, R2);
+        load(y0 + 1, R3);
+        load(y0 + 2, R4);
+        const int qend = y1 + 1;
+        for (int q = y0; q <= qend; q += 6) {
+            body(q, R0, R1, R2, R5, D0, D1, F0, F1);
+            if (q + 1 > qend) break;
+            body(q + 1, R1, R2, R3, R0, D1, D0, F1, F0);
+            if (q + 2 > qend) break;
+            body(q + 2, R2, R3, R4, R1, D0, D1, F0, F1);
+            if (q + 3 > qend) break;
+            body(q + 3, R3, R4, R5, R2, D1, D0, F1, F0);
+            if (q + 4 > qend) break;
+            body(q + 4, R4, R5, R0, R3, D0, D1, F0, F1);
+            if (q + 5 > qend) break;
+            body(q + 5, R5, R0, R1, R4, D1, D0, F1, F0);
+        }
+    }
+};
 
 template <typename T, bool HAS_EPS, bool HAS_MU>
 __global__ __launch_bounds__(256) void cart2d_step_kernel(Cart2DArgs<T> a)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int wave = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+    // the wave's index inside the block is uniform: say so, so that everything derived from it
+    // (tile, batch item, buffer resources, row offsets) lives in scalar registers
+    const int wave = xcd_logical_block() * (256 / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int per_b = a.ntx * a.nty;
     const int b = wave / per_b;
     if (b >= a.batch) return;
@@ -61,115 +195,30 @@ __global__ __launch_bounds__(256) void cart2d_step_kernel(Cart2DArgs<T> a)
     const int tx = rem - ty * a.ntx;
 
     const int64_t ncell = (int64_t)a.nx * a.ny;
-    const T *Ub = a.U + (int64_t)b * 3 * ncell;
-    T *Ob = a.Unew + (int64_t)b * 3 * ncell;
-    const T *Eb = HAS_EPS ? a.epsinv + (int64_t)b * ncell : nullptr;
-    const T *Mb = HAS_MU ? a.muinv + (int64_t)b * ncell : nullptr;
+    const uint32_t fbytes = (uint32_t)(ncell * (int64_t)sizeof(T));
+    const Rsrc rU = make_rsrc(a.U + (int64_t)b * 3 * ncell, 3ull * fbytes);
+    const Rsrc rO = make_rsrc(a.Unew + (int64_t)b * 3 * ncell, 3ull * fbytes);
+    const Rsrc rE = make_rsrc(HAS_EPS ? a.epsinv + (int64_t)b * ncell : a.U, fbytes);
+    const Rsrc rM = make_rsrc(HAS_MU ? a.muinv + (int64_t)b * ncell : a.U, fbytes);
 
-    // column of this lane and its boundary mapping
-    const int gx = tx * OUTX - HALO + lane;
-    bool mirx, nrx;
-    const int sx = map_axis(gx, a.nx, a.bc[0], a.bc[1], mirx, nrx);
-    const T sgx0 = mirx ? T(-1) : T(1);   // Ez and Hx (normal to an x wall) are odd
-    const T sgx1 = T(1);                  // Hy is even
-    const bool writer = lane >= HALO && lane < WAVE - HALO && gx < a.nx;
+    const int x0 = tx * OUTX - HALO;
+    const int gx = x0 + lane;
+    const int y0 = ty * a.tile_y;
+    const int y1 = min(y0 + a.tile_y, a.ny);   // rows [y0, y1) are written
+    const uint32_t vlane = (uint32_t)lane * (uint32_t)sizeof(T);
 
-    const int y0 = ty * TILE_Y;
-    const int y1 = min(y0 + TILE_Y, a.ny);   // rows [y0, y1) are written
-
-    Row2D<T> rs, rc, rn;                      // rows q-2, q-1, q
-    load_row<T, HAS_EPS, HAS_MU>(a, Ub, Eb, Mb, ncell, sx, sgx0, sgx1, nrx, y0 - 2, rs);
-    load_row<T, HAS_EPS, HAS_MU>(a, Ub, Eb, Mb, ncell, sx, sgx0, sgx1, nrx, y0 - 1, rc);
-    T Ds[6], Dc[6];                           // half-differences (d/dx, d/dy) x (Ez,Hx,Hy)
-    T fyS[3] = {T(0), T(0), T(0)};            // flux of the horizontal face below row q-2
-
-    for (int q = y0; q <= y1 + 1; ++q) {
-        load_row<T, HAS_EPS, HAS_MU>(a, Ub, Eb, Mb, ncell, sx, sgx0, sgx1, nrx, q, rn);
-        // gradient of row q-1 (Green-Gauss on a uniform grid = central half-differences)
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            Dc[f] = T(0.5) * (from_right(rc.u[f]) - from_left(rc.u[f]));
-            Dc[3 + f] = T(0.5) * (rn.u[f] - rs.u[f]);
-        }
-        if (q >= y0 + 1) {
-            // horizontal face between rows q-2 (left) and q-1 (right), local frame
-            // (x~, y~) = (y, -x): (Ez, Hx, Hy) -> (Ez, Hy, -Hx), d1 = d/dy, d2 = -d/dx
-            T w[18];
-            const bool zl = rs.nr, zr = rc.nr;
-            w[0] = zl ? T(0) : rs.u[0];
-            w[1] = zl ? T(0) : rs.u[2];
-            w[2] = zl ? T(0) : -rs.u[1];
-            w[3] = zr ? T(0) : rc.u[0];
-            w[4] = zr ? T(0) : rc.u[2];
-            w[5] = zr ? T(0) : -rc.u[1];
-            w[6] = zl ? T(0) : Ds[3];
-            w[7] = zl ? T(0) : Ds[5];
-            w[8] = zl ? T(0) : -Ds[4];
-            w[9] = zl ? T(0) : -Ds[0];
-            w[10] = zl ? T(0) : -Ds[2];
-            w[11] = zl ? T(0) : Ds[1];
-            w[12] = zr ? T(0) : Dc[3];
-            w[13] = zr ? T(0) : Dc[5];
-            w[14] = zr ? T(0) : -Dc[4];
-            w[15] = zr ? T(0) : -Dc[0];
-            w[16] = zr ? T(0) : -Dc[2];
-            w[17] = zr ? T(0) : Dc[1];
-            // face material: mean of the two cells (a ghost reads its interior cell, so a
-            // boundary face gets the interior value)
-            const T mE = T(0.5) * (rs.mE + rc.mE);
-            const T mH = T(0.5) * (rs.mH + rc.mH);
-            T p[3];
-            apply_tm(w, mE, mH, a.fy, p);
-            T fyN[3] = {p[0], -p[2], p[1]};   // back to (Ez, Hx, Hy)
-
-            if (q >= y0 + 2) {
-                // vertical face right of this lane, row q-2 (local frame = global frame)
-                const bool me_nr = rs.nr;
-                T ul[3], dl[6];
-#pragma unroll
-                for (int f = 0; f < 3; ++f) ul[f] = me_nr ? T(0) : rs.u[f];
-#pragma unroll
-                for (int f = 0; f < 6; ++f) dl[f] = me_nr ? T(0) : Ds[f];
-                T v[18];
-#pragma unroll
-                for (int f = 0; f < 3; ++f) {
-                    v[f] = ul[f];
-                    v[3 + f] = from_right(ul[f]);
-                    v[6 + f] = dl[f];
-                    v[9 + f] = dl[3 + f];
-                    v[12 + f] = from_right(dl[f]);
-                    v[15 + f] = from_right(dl[3 + f]);
-                }
-                const T mEx = T(0.5) * (rs.mE + from_right(rs.mE));
-                const T mHx = T(0.5) * (rs.mH + from_right(rs.mH));
-                T fx[3];
-                apply_tm(v, mEx, mHx, a.fx, fx);
-                T fxl[3];
-#pragma unroll
-                for (int f = 0; f < 3; ++f) fxl[f] = from_left(fx[f]);
-
-                const int r = q - 2;
-                if (writer) {
-                    const int64_t c = (int64_t)r * a.nx + gx;
-                    double src = 0.0;
-                    for (int s = 0; s < a.nsrc; ++s)
-                        if (c == a.src_cell[s]) src += a.src_amp[s];
-                    const double m[3] = {(double)rs.mE, (double)rs.mH, (double)rs.mH};
-                    const double add[3] = {src, 0.0, 0.0};
-#pragma unroll
-                    for (int f = 0; f < 3; ++f) {
-                        const double div = ((double)fx[f] - (double)fxl[f]) + ((double)fyN[f] - (double)fyS[f]);
-                        Ob[(int64_t)f * ncell + c] = (T)((double)rs.u[f] + m[f] * (add[f] - div));
-                    }
-                }
-            }
-#pragma unroll
-            for (int f = 0; f < 3; ++f) fyS[f] = fyN[f];
-        }
-        rs = rc;
-        rc = rn;
-#pragma unroll
-        for (int f = 0; f < 6; ++f) Ds[f] = Dc[f];
+    const bool interior = x0 >= 0 && x0 + WAVE - 1 <= a.nx - 1 && y0 - 2 >= 0 && y1 + 1 <= a.ny - 1;
+    if (interior) {
+        Strip2D<T, HAS_EPS, HAS_MU, false> s{a, rU, rE, rM, rO, fbytes, vlane, vlane, x0, gx, T(1), false,
+                                             lane >= HALO && lane < WAVE - HALO, y0, y1};
+        s.run();
+    } else {
+        bool mirx, nrx;
+        const int sx = map_axis(gx, a.nx, a.bc[0], a.bc[1], mirx, nrx);
+        Strip2D<T, HAS_EPS, HAS_MU, true> s{a, rU, rE, rM, rO, fbytes, (uint32_t)sx * (uint32_t)sizeof(T), vlane, x0, gx,
+                                            mirx ? T(-1) : T(1), nrx,
+                                            lane >= HALO && lane < WAVE - HALO && gx < a.nx, y0, y1};
+        s.run();
     }
 }
 
@@ -191,6 +240,5 @@ template int launch_cart2d_step<float>(const Cart2DArgs<float> &, void *);
 template int launch_cart2d_step<double>(const Cart2DArgs<double> &, void *);
 
 int cart2d_tile_x() { return OUTX; }
-int cart2d_tile_y() { return TILE_Y; }
 
 }  // namespace gks
