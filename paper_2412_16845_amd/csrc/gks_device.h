@@ -128,6 +128,16 @@ __device__ __forceinline__ ConstPtr<Op> scalar_ptr(const Op *p)
     return q;
 }
 
+// The same, but the pointer (hence the coefficient loads) only becomes available once `after`
+// has been computed: keeps the coefficient sets of consecutive faces from being live together.
+template <typename Op, typename V>
+__device__ __forceinline__ ConstPtr<Op> scalar_ptr_after(const Op *p, V after)
+{
+    ConstPtr<Op> q = (ConstPtr<Op>)p;
+    asm volatile("" : "+s"(q) : "v"(after));
+    return q;
+}
+
 // ------------------------------------------------------------------ sparse face operators
 // phi = K0 w + mE KE w + mH KH w for the face orientation described by the table struct P
 // (callers pass mE, mH as the SUM of the two cells' 1/eps, 1/mu: the host halves KE, KH)
@@ -139,8 +149,16 @@ __device__ __forceinline__ void apply_op(const T (&w)[NIN], T mE, T mH, Op K, T 
     T a[NF], e[NF], h[NF];
 #pragma unroll
     for (int r = 0; r < NF; ++r) a[r] = e[r] = h[r] = T(0);
+    // K0 in chunks of CH entries; the coefficients of a chunk are loaded only once the previous
+    // chunk has started (at most two chunks' scalar registers are live)
+    constexpr int CH = 12;
 #pragma unroll
-    for (int q = 0; q < P::N0; ++q) a[P::R0[q]] = fma(K->k0[q], w[P::C0[q]], a[P::R0[q]]);
+    for (int q = 0; q < P::N0; ++q) {
+        if (q % CH == 1 && q + CH - 1 < P::N0) asm volatile("" : "+s"(K) : "v"(a[P::R0[q - 1]]));
+        a[P::R0[q]] = fma(K->k0[q], w[P::C0[q]], a[P::R0[q]]);
+    }
+    // the material parts' coefficients are loaded once K0's have been used
+    asm volatile("" : "+s"(K) : "v"(a[P::R0[P::N0 - 1]]));
 #pragma unroll
     for (int q = 0; q < P::NE; ++q) e[P::RE[q]] = fma(K->ke[q], w[P::CE[q]], e[P::RE[q]]);
 #pragma unroll

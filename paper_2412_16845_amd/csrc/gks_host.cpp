@@ -137,27 +137,17 @@ gks_status upload_ops(gks_ctx *x)
 
 }  // namespace
 
-int gks::cart2d_pick_tile_y(int nx, int ny, int batch, int ncu)
+int gks::cart2d_pick_tile_y(int nx, int ny, int batch, int ncu, int precision)
 {
 #ifdef GKS_FORCE_TILE_Y
     return GKS_FORCE_TILE_Y;   // build-time override for tuning sweeps
 #endif
-    const int64_t ntx = (nx + cart2d_tile_x() - 1) / cart2d_tile_x();
-    int best = 64;
-    double best_cost = 1e300;
-    for (int ty = 16; ty <= 256; ++ty) {
-        const int64_t nty = (ny + ty - 1) / ty;
-        const int64_t wgs = (ntx * nty * batch + 3) / 4;
-        const int64_t per_cu = (wgs + ncu - 1) / ncu;
-        const int rows = std::min(ty, ny);
-        const double cost = (double)per_cu * (rows + 4);
-        if (cost < best_cost - 1e-9) {
-            best_cost = cost;
-            best = ty;
-        }
-        if (ty >= ny) break;
-    }
-    return best;
+    // Short tiles give many waves per SIMD to hide memory latency; adjacent tiles march in
+    // opposite directions and share their halo rows through the L2, so the extra halo reads of
+    // short tiles mostly hit the cache.  16 rows measured best (12..24 within 2%) on 4096^2 in
+    // both precisions.
+    (void)nx; (void)batch; (void)ncu; (void)precision;
+    return std::max(1, std::min(16, ny));
 }
 
 namespace {
@@ -181,22 +171,16 @@ gks_status step_cart2d(gks_ctx *x, const void *Uin, void *Uout, double tn)
     a.ny = (int32_t)x->n[1];
     a.batch = (int32_t)x->batch;
     for (int i = 0; i < 4; ++i) a.bc[i] = x->bc[i];
-    a.ntx = (a.nx + cart2d_tile_x() - 1) / cart2d_tile_x();
+    a.ntx = (a.nx + cart2d_tile_x(x->prec) - 1) / cart2d_tile_x(x->prec);
     a.tile_y = x->tile_y;
     a.nty = (a.ny + a.tile_y - 1) / a.tile_y;
     a.ops = (const FaceOpTM<T> *)x->d_ops;
     const int64_t ns = (int64_t)x->src_cells.size();
-    const double amp = ns ? -x->dt * source_pulse(x, tn) : 0.0;   // dt * S_z = -dt J_z
-    if (ns > 0 && ns <= MAX_FUSED_SRC) {
-        a.nsrc = (int32_t)ns;
-        for (int s = 0; s < ns; ++s) {
-            a.src_cell[s] = (int32_t)x->src_cells[s];
-            a.src_amp[s] = amp * x->src_w[s];
-        }
-    }
     int e = launch_cart2d_step<T>(a, x->stream);
     if (e) return hip_fail(x, e, "GKS step launch");
-    if (ns > MAX_FUSED_SRC) {
+    if (ns > 0) {
+        // dt * S_z = -dt * J_z(t^n), scaled by 1/eps of the cell in the kernel
+        const double amp = -x->dt * source_pulse(x, tn);
         e = launch_source_scatter<T>((T *)Uout, (const T *)x->epsinv, x->ncell, (int64_t)x->nfields * x->ncell,
                                      (int32_t)x->batch, 0, x->d_src_cells, x->d_src_w, amp, (int32_t)ns, x->stream);
         if (e) return hip_fail(x, e, "source launch");
@@ -359,7 +343,7 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
             x->ncu = ncu;
     }
     if (x->kind == GKS_CART2D)
-        x->tile_y = cart2d_pick_tile_y((int)x->n[0], (int)x->n[1], (int)x->batch, x->ncu);
+        x->tile_y = cart2d_pick_tile_y((int)x->n[0], (int)x->n[1], (int)x->batch, x->ncu, x->prec);
     {
         gks_status st = upload_ops(x);
         if (st) return bail(st);
@@ -428,7 +412,7 @@ extern "C" gks_status gks_set_point_source(gks_ctx *ctx, int64_t n, const int64_
     ctx->d_src_cells = nullptr;
     ctx->d_src_w = nullptr;
     const size_t m = ctx->src_cells.size();
-    if (m > (size_t)MAX_FUSED_SRC) {
+    if (m > 0) {
         if (hipMalloc((void **)&ctx->d_src_cells, m * sizeof(int64_t)) != hipSuccess ||
             hipMalloc((void **)&ctx->d_src_w, m * sizeof(double)) != hipSuccess)
             return fail(ctx, GKS_ENOMEM, "cannot allocate the source list");

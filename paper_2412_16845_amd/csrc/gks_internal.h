@@ -39,7 +39,7 @@ struct FaceOp {
 template <typename T> using FaceOpTM = FaceOp<T, TM_N0, TM_NE, TM_NH>;
 template <typename T> using FaceOpEM = FaceOp<T, EM_N0, EM_NE, EM_NH>;
 
-constexpr int MAX_FUSED_SRC = 4;
+
 
 // Arguments of the Cartesian 2D TM step kernel.
 template <typename T>
@@ -54,9 +54,6 @@ struct Cart2DArgs {
     int32_t ntx, nty;     // tiles per row / column
     int32_t tile_y;       // rows per tile
     const FaceOpTM<T> *ops;   // device: x-face and y-face operators
-    int32_t nsrc;         // fused point sources (<= MAX_FUSED_SRC)
-    int32_t src_cell[MAX_FUSED_SRC];
-    double src_amp[MAX_FUSED_SRC];   // dt * S_z = -dt * J_z(t^n) (before the 1/eps factor)
 };
 
 // Arguments of the Cartesian 2D TM adjoint kernel.
@@ -74,23 +71,21 @@ struct Cart2DAdjArgs {
     int32_t ntx, nty;
     int32_t tile_y;
     const FaceOpTM<T> *ops;   // device: x-face and y-face operators
-    int32_t nsrc;
-    int32_t src_cell[MAX_FUSED_SRC];
-    double src_amp[MAX_FUSED_SRC];
 };
 
 // Launchers (defined in the .hip files).  Return a hipError_t as int.
 template <typename T> int launch_cart2d_step(const Cart2DArgs<T> &a, void *stream);
 template <typename T> int launch_cart2d_adjoint(const Cart2DAdjArgs<T> &a, void *stream);
-// U[b][field][cells[s]] += (1/eps) * amp * weight[s]  (explicit source, long source lists)
+// U[b][field][cells[s]] += (1/eps) * amp * weight[s]  (explicit point source after a step)
 template <typename T> int launch_source_scatter(T *U, const T *epsinv, int64_t ncell, int64_t fstride,
                                                 int32_t batch, int32_t field, const int64_t *cells,
                                                 const double *weight, double amp, int32_t n, void *stream);
-int cart2d_tile_x();
+// Columns written per wave strip (depends on the element size).
+int cart2d_tile_x(int precision);
 // Rows per wave tile for an nx x ny x batch grid on a device with ncu compute units: the
 // kernel is throughput bound per compute unit, so the step time follows the largest number of
 // 4-wave workgroups any unit receives times the rows each wave marches (plus its 4 halo rows).
-int cart2d_pick_tile_y(int nx, int ny, int batch, int ncu);
+int cart2d_pick_tile_y(int nx, int ny, int batch, int ncu, int precision);
 
 // Energy: partial sums per (batch, block) then a fixed-order final sum; all FP64.
 template <typename T>

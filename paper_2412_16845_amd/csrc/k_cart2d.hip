@@ -1,18 +1,20 @@
 // Fused GKS step on a 2D Cartesian grid, TM fields (Ez, Hx, Hy).
 //
-// One wavefront owns a strip of 64 columns (60 written, 2 halo columns on each side) and
-// marches a tile of rows upwards (the tile height is chosen by the host to balance the
-// workgroups over the compute units).  Each field value is loaded once per strip row; neighbours along
-// x come from the adjacent lanes through DPP moves, so no LDS and no barriers are needed.
-// Per row the wave:
-//   1. issues the loads of the row PF rows ahead (structure-of-arrays, 64 consecutive values
+// One wavefront owns a strip of 64 lanes x NC adjacent columns (NC = 2 for FP32, 1 for FP64,
+// so that every lane moves 8 bytes per field and row); the two outermost columns on each side
+// are halo, the rest are written.  The wave marches a tile of rows upwards (the tile height is
+// chosen by the host to balance the workgroups over the compute units).  Each field value is
+// loaded once per strip row; neighbours along x come from the lane itself or from the adjacent
+// lanes through DPP moves, so no LDS and no barriers are needed.  Per row the wave:
+//   1. issues the loads of the row PF rows ahead (structure-of-arrays, 512 contiguous bytes
 //      per field: coalesced), so that several rows of loads are in flight while it computes;
 //   2. forms the Green-Gauss (central) differences of the middle row of its three-row window;
 //   3. evaluates the GKS flux of the horizontal face below the middle row and of the vertical
-//      face right of each lane, as sparse linear forms of the stencil values (the closed-form
-//      moments of Sec. 3.1 folded into coefficients on the host);
-//   4. sums the four face terms of the row it finishes in double precision, adds the old value
-//      and the explicit source, and stores once.
+//      face right of each column, as sparse linear forms of the stencil values (the
+//      closed-form moments of Sec. 3.1 folded into coefficients on the host);
+//   4. forms the flux divergence of each cell of the row it finishes, adds it to the old value
+//      in double precision and stores once.  (Explicit point sources are added afterwards by a
+//      small scatter kernel, which keeps the per-cell source test out of the marching loop.)
 // The row loop is unrolled six times so that the rotating window (six row slots, two gradient
 // slots, two flux slots) lives in fixed registers without copies.
 // Strips that touch no domain side take a path without index mapping.  On the others, ghost
@@ -25,164 +27,262 @@
 namespace gks {
 
 constexpr int HALO = 2;
-constexpr int OUTX = WAVE - 2 * HALO;   // columns written per wave
 constexpr int PF = 3;   // rows loaded ahead of use: with the three-row window, six row slots
 
+#ifndef GKS_FP32_COLS_PER_LANE
+#define GKS_FP32_COLS_PER_LANE 2
+#endif
 template <typename T>
+constexpr int cols_per_lane() { return sizeof(T) == 4 ? GKS_FP32_COLS_PER_LANE : 1; }
+template <typename T>
+constexpr int out_cols() { return WAVE * cols_per_lane<T>() - 2 * HALO; }
+
+template <typename T, int NC>
 struct Row2D {
-    T u[3];      // Ez, Hx, Hy (mirror signs applied)
-    T mE, mH;    // 1/eps, 1/mu of the cell read
-    bool nr;     // non-reflecting ghost (boundary strips only)
+    T u[NC][3];      // Ez, Hx, Hy per column (mirror signs applied)
+    T mE[NC], mH[NC];
+    bool nr[NC];     // non-reflecting ghost (boundary strips only)
 };
 
-template <typename T, bool HAS_EPS, bool HAS_MU, bool BND>
+// NC consecutive values at byte offsets (voff + soff): one 8-byte access.
+template <typename T, int NC>
+__device__ __forceinline__ void load_cols(Rsrc r, uint32_t voff, uint32_t soff, T (&out)[NC])
+{
+    if constexpr (NC == 2) {
+        const float2 v = buf_load_f2(r, voff, soff);
+        out[0] = v.x;
+        out[1] = v.y;
+    } else {
+        out[0] = buf_load<T>(r, voff, soff);
+    }
+}
+
+template <typename T, int NC, bool HAS_EPS, bool HAS_MU, bool BND>
 struct Strip2D {
     const Cart2DArgs<T> &a;
     Rsrc rU, rE, rM, rO;   // this batch item's fields, 1/eps, 1/mu, output fields
     uint32_t fbytes;       // bytes per field array
-    uint32_t vx;           // byte offset of this lane's column (mapped column on boundary strips)
-    uint32_t vlane;        // byte offset of this lane inside the strip
+    uint32_t vlane;        // byte offset of this lane's first column inside the strip
     int x0;                // first column of the strip (uniform; -2 on the first strip)
-    int gx;                // column of this lane
-    T sgx;                 // x-mirror sign of Ez and Hx
-    bool nrx;
-    bool writer;
+    int gx0;               // first column of this lane
+    uint32_t vx[NC];       // boundary strips: byte offset of the column each cell reads
+    T sgx[NC];             // boundary strips: x-mirror sign of Ez and Hx
+    bool nrx[NC];          // boundary strips: non-reflecting ghost column
+    bool writer[NC];
     int y0, y1;
 
-    __device__ __forceinline__ void load(int gy, Row2D<T> &r) const
+    __device__ __forceinline__ void load(int gy, Row2D<T, NC> &r) const
     {
         if constexpr (BND) {
             bool mir, nry;
             const int sy = map_axis(gy, a.ny, a.bc[2], a.bc[3], mir, nry);
             const uint32_t so = (uint32_t)sy * (uint32_t)a.nx * (uint32_t)sizeof(T);
             const T sgy = mir ? T(-1) : T(1);   // y mirror: Ez and Hy odd, Hx even
-            r.u[0] = buf_load<T>(rU, vx, so) * (sgx * sgy);
-            r.u[1] = buf_load<T>(rU, vx, so + fbytes) * sgx;
-            r.u[2] = buf_load<T>(rU, vx, so + 2 * fbytes) * sgy;
-            r.mE = HAS_EPS ? buf_load<T>(rE, vx, so) : T(1);
-            r.mH = HAS_MU ? buf_load<T>(rM, vx, so) : T(1);
-            r.nr = nry || nrx;
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                r.u[k][0] = buf_load<T>(rU, vx[k], so) * (sgx[k] * sgy);
+                r.u[k][1] = buf_load<T>(rU, vx[k], so + fbytes) * sgx[k];
+                r.u[k][2] = buf_load<T>(rU, vx[k], so + 2 * fbytes) * sgy;
+                r.mE[k] = HAS_EPS ? buf_load<T>(rE, vx[k], so) : T(1);
+                r.mH[k] = HAS_MU ? buf_load<T>(rM, vx[k], so) : T(1);
+                r.nr[k] = nry || nrx[k];
+            }
         } else {
             const uint32_t so = ((uint32_t)gy * (uint32_t)a.nx + (uint32_t)x0) * (uint32_t)sizeof(T);
-            r.u[0] = buf_load<T>(rU, vx, so);
-            r.u[1] = buf_load<T>(rU, vx, so + fbytes);
-            r.u[2] = buf_load<T>(rU, vx, so + 2 * fbytes);
-            r.mE = HAS_EPS ? buf_load<T>(rE, vx, so) : T(1);
-            r.mH = HAS_MU ? buf_load<T>(rM, vx, so) : T(1);
-            r.nr = false;
+            T v[NC];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                load_cols<T, NC>(rU, vlane, so + f * fbytes, v);
+#pragma unroll
+                for (int k = 0; k < NC; ++k) r.u[k][f] = v[k];
+            }
+            if (HAS_EPS) load_cols<T, NC>(rE, vlane, so, r.mE);
+            else
+#pragma unroll
+                for (int k = 0; k < NC; ++k) r.mE[k] = T(1);
+            if (HAS_MU) load_cols<T, NC>(rM, vlane, so, r.mH);
+            else
+#pragma unroll
+                for (int k = 0; k < NC; ++k) r.mH[k] = T(1);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) r.nr[k] = false;
         }
     }
 
-    // One row step at index q: window rows q-2 (Rs), q-1 (Rc), q (Rn); Rp receives row q+PF.
-    __device__ __forceinline__ void body(int q, Row2D<T> &Rs, Row2D<T> &Rc, Row2D<T> &Rn, Row2D<T> &Rp,
-                                         T (&Ds)[6], T (&Dc)[6], T (&fyS)[3], T (&fyN)[3]) const
+    // One row step number i of the march in direction s = +1 (upwards, DN false) or -1: the
+    // window holds rows q-2s (Rs), q-s (Rc), q (Rn) with q = qs + s i; Rp receives row q+PF s.
+    // fyP is the horizontal face computed one step earlier, fyN the one computed now.
+    template <bool DN>
+    __device__ __forceinline__ void body(int i, int qs, Row2D<T, NC> &Rs, Row2D<T, NC> &Rc, Row2D<T, NC> &Rn,
+                                         Row2D<T, NC> &Rp, T (&Ds)[NC][6], T (&Dc)[NC][6], T (&fyP)[NC][3],
+                                         T (&fyN)[NC][3]) const
     {
-        // rows beyond y1 + 1 are not needed: re-read row y1 + 1 instead (already cached), which
-        // keeps the load unconditional so the loads in flight are counted exactly
-        load(min(q + PF, y1 + 1), Rp);
+        constexpr int sd = DN ? -1 : 1;
+        const int q = qs + sd * i;
+        // coefficients of the horizontal faces: loaded after the previous row's divergence
+        const auto opy = scalar_ptr_after(a.ops + 1, fyP[0][0]);
+        // rows beyond the tile and its halo are not needed: re-read the last halo row instead
+        // (already cached), which keeps the load unconditional so the loads in flight are
+        // counted exactly
+        load(DN ? max(q - PF, y0 - 2) : min(q + PF, y1 + 1), Rp);
         // central differences of row q-1: [d/dx x (Ez,Hx,Hy), d/dy x (Ez,Hx,Hy)] times 2h
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            Dc[f] = from_right(Rc.u[f]) - from_left(Rc.u[f]);
-            Dc[3 + f] = Rn.u[f] - Rs.u[f];
+            const T rnext = from_right(Rc.u[0][f]);       // first column of the next lane
+            const T lprev = from_left(Rc.u[NC - 1][f]);   // last column of the previous lane
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                const T right = (k + 1 < NC) ? Rc.u[k + 1 < NC ? k + 1 : 0][f] : rnext;
+                const T left = (k > 0) ? Rc.u[k > 0 ? k - 1 : 0][f] : lprev;
+                Dc[k][f] = right - left;
+                Dc[k][3 + f] = DN ? Rs.u[k][f] - Rn.u[k][f] : Rn.u[k][f] - Rs.u[k][f];
+            }
         }
-        if (q < y0 + 1) return;
+        if (i < 1) return;
 
-        // horizontal face between rows q-2 and q-1: inputs [UL UR dyL dxL dyR dxR]
-        {
-            const bool zl = BND && Rs.nr, zr = BND && Rc.nr;
+        // horizontal face between rows q-2s and q-s: inputs [UL UR dyL dxL dyR dxR], L the
+        // lower row
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const Row2D<T, NC> &RL = DN ? Rc : Rs;
+            const Row2D<T, NC> &RR = DN ? Rs : Rc;
+            const T(&DL)[NC][6] = DN ? Dc : Ds;
+            const T(&DR)[NC][6] = DN ? Ds : Dc;
+            const bool zl = BND && RL.nr[k], zr = BND && RR.nr[k];
             T w[18];
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
-                w[f] = zl ? T(0) : Rs.u[f];
-                w[3 + f] = zr ? T(0) : Rc.u[f];
-                w[6 + f] = zl ? T(0) : Ds[3 + f];
-                w[9 + f] = zl ? T(0) : Ds[f];
-                w[12 + f] = zr ? T(0) : Dc[3 + f];
-                w[15 + f] = zr ? T(0) : Dc[f];
+                w[f] = zl ? T(0) : RL.u[k][f];
+                w[3 + f] = zr ? T(0) : RR.u[k][f];
+                w[6 + f] = zl ? T(0) : DL[k][3 + f];
+                w[9 + f] = zl ? T(0) : DL[k][f];
+                w[12 + f] = zr ? T(0) : DR[k][3 + f];
+                w[15 + f] = zr ? T(0) : DR[k][f];
             }
             // face material: the two cells' values (a ghost reads its interior cell); the
             // operator applies their mean
-            apply_op<PatTMy>(w, Rs.mE + Rc.mE, Rs.mH + Rc.mH, scalar_ptr(a.ops + 1), fyN);
+            apply_op<PatTMy>(w, RL.mE[k] + RR.mE[k], RL.mH[k] + RR.mH[k], opy, fyN[k]);
         }
-        if (q < y0 + 2) return;
+        if (i < 2) return;
+        // coefficients of the vertical faces: loaded once the horizontal faces are done
+        const auto opx = scalar_ptr_after(a.ops, fyN[NC - 1][2]);
 
-        // vertical face right of this lane, row q-2: inputs [UL UR dxL dyL dxR dyR]
-        const bool me_nr = BND && Rs.nr;
-        T ul[3], dl[6];
+        // vertical faces right of each column, row q-2s: inputs [UL UR dxL dyL dxR dyR]
+        T ul[NC][3], dl[NC][6];
 #pragma unroll
-        for (int f = 0; f < 3; ++f) ul[f] = me_nr ? T(0) : Rs.u[f];
+        for (int k = 0; k < NC; ++k) {
+            const bool z = BND && Rs.nr[k];
 #pragma unroll
-        for (int f = 0; f < 6; ++f) dl[f] = me_nr ? T(0) : Ds[f];
-        T v[18];
+            for (int f = 0; f < 3; ++f) ul[k][f] = z ? T(0) : Rs.u[k][f];
 #pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            v[f] = ul[f];
-            v[3 + f] = from_right(ul[f]);
-            v[6 + f] = dl[f];
-            v[9 + f] = dl[3 + f];
-            v[12 + f] = from_right(dl[f]);
-            v[15 + f] = from_right(dl[3 + f]);
+            for (int f = 0; f < 6; ++f) dl[k][f] = z ? T(0) : Ds[k][f];
         }
-        T fx[3];
-        apply_op<PatTMx>(v, Rs.mE + from_right(Rs.mE), Rs.mH + from_right(Rs.mH), scalar_ptr(a.ops), fx);
-        T fxl[3];
+        T fx[NC][3];
 #pragma unroll
-        for (int f = 0; f < 3; ++f) fxl[f] = from_left(fx[f]);
-
-        if (writer) {
-            // per-cell flux divergence (FP32 in FP32 mode), then the old value and the source
-            // added in FP64 with a single rounding
-            // interior strips: uniform offset of the strip start + lane offset; boundary strips
-            // (whose first column may be a ghost): uniform row start + the lane's own column
-            const uint32_t rowc = (uint32_t)(q - 2) * (uint32_t)a.nx;
-            const uint32_t so = BND ? rowc * (uint32_t)sizeof(T) : (rowc + (uint32_t)x0) * (uint32_t)sizeof(T);
-            const uint32_t vo = BND ? (uint32_t)gx * (uint32_t)sizeof(T) : vlane;
-            const int c = (int)rowc + gx;
-            double src = 0.0;
-            for (int s = 0; s < a.nsrc; ++s)
-                if (c == a.src_cell[s]) src += a.src_amp[s];
-            const double mE = (double)Rs.mE, mH = (double)Rs.mH;
+        for (int k = 0; k < NC; ++k) {
+            constexpr int last = NC - 1;
+            const int kr = (k + 1 < NC) ? k + 1 : 0;
+            T v[18];
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
-                const T div = (fx[f] - fxl[f]) + (fyN[f] - fyS[f]);
-                const double m = (f == 0) ? mE : mH;
-                const double add = (f == 0) ? src : 0.0;
-                buf_store((T)((double)Rs.u[f] + m * (add - (double)div)), rO, vo, so + f * fbytes);
+                v[f] = ul[k][f];
+                v[3 + f] = (k < last) ? ul[kr][f] : from_right(ul[0][f]);
+                v[6 + f] = dl[k][f];
+                v[9 + f] = dl[k][3 + f];
+                v[12 + f] = (k < last) ? dl[kr][f] : from_right(dl[0][f]);
+                v[15 + f] = (k < last) ? dl[kr][3 + f] : from_right(dl[0][3 + f]);
             }
+            const T mEr = (k < last) ? Rs.mE[kr] : from_right(Rs.mE[0]);
+            const T mHr = (k < last) ? Rs.mH[kr] : from_right(Rs.mH[0]);
+            apply_op<PatTMx>(v, Rs.mE[k] + mEr, Rs.mH[k] + mHr, opx, fx[k]);
+        }
+
+        // update: per-cell flux divergence (FP32 in FP32 mode), then the old value added in
+        // FP64 with a single rounding (point sources are added by a separate scatter kernel)
+        const uint32_t rowc = (uint32_t)(q - 2 * sd) * (uint32_t)a.nx;
+        T nv[NC][3];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const T fl = (k > 0) ? fx[k > 0 ? k - 1 : 0][f] : from_left(fx[NC - 1][f]);
+                const T dyf = DN ? fyP[k][f] - fyN[k][f] : fyN[k][f] - fyP[k][f];   // upper - lower face
+                const T div = (fx[k][f] - fl) + dyf;
+                const double m = (f == 0) ? (double)Rs.mE[k] : (double)Rs.mH[k];
+                nv[k][f] = (T)((double)Rs.u[k][f] - m * (double)div);
+            }
+        }
+        if constexpr (!BND) {
+            // interior strips: every lane but the two halo lanes writes all its columns
+            if (writer[0]) {
+                const uint32_t so = (rowc + (uint32_t)x0) * (uint32_t)sizeof(T);
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    if constexpr (NC == 2) buf_store_f2(make_float2(nv[0][f], nv[1][f]), rO, vlane, so + f * fbytes);
+                    else buf_store(nv[0][f], rO, vlane, so + f * fbytes);
+                }
+            }
+        } else {
+            // boundary strips (whose first columns may be ghosts): row start + own column
+            const uint32_t so = rowc * (uint32_t)sizeof(T);
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+                if (writer[k]) {
+                    const uint32_t vo = (uint32_t)(gx0 + k) * (uint32_t)sizeof(T);
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) buf_store(nv[k][f], rO, vo, so + f * fbytes);
+                }
         }
     }
 
+    // March the tile upwards (DN false: rows y0-2 .. y1+1) or downwards (rows y1+1 .. y0-2).
+    template <bool DN>
     __device__ __forceinline__ void run() const
     {
-        Row2D<T> R0, R1, R2, R3, R4, R5;
-        T D0[6], D1[6];
-        T F0[3] = {T(0), T(0), T(0)}, F1[3] = {T(0), T(0), T(0)};
-        load(y0 - 2, R0);
-        load(y0 - 1, R1);
-        load(y0, R2);
-        load(y0 + 1, R3);
-        load(y0 + 2, R4);
-        const int qend = y1 + 1;
-        for (int q = y0; q <= qend; q += 6) {
-            body(q, R0, R1, R2, R5, D0, D1, F0, F1);
-            if (q + 1 > qend) break;
-            body(q + 1, R1, R2, R3, R0, D1, D0, F1, F0);
-            if (q + 2 > qend) break;
-            body(q + 2, R2, R3, R4, R1, D0, D1, F0, F1);
-            if (q + 3 > qend) break;
-            body(q + 3, R3, R4, R5, R2, D1, D0, F1, F0);
-            if (q + 4 > qend) break;
-            body(q + 4, R4, R5, R0, R3, D0, D1, F0, F1);
-            if (q + 5 > qend) break;
-            body(q + 5, R5, R0, R1, R4, D1, D0, F1, F0);
+        constexpr int sd = DN ? -1 : 1;
+        Row2D<T, NC> R0, R1, R2, R3, R4, R5;
+        T D0[NC][6], D1[NC][6];
+        T F0[NC][3], F1[NC][3];
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+#pragma unroll
+            for (int f = 0; f < 3; ++f) F0[k][f] = F1[k][f] = T(0);
+        const int qs = DN ? y1 - 1 : y0;       // window head of the first step
+        load(qs - 2 * sd, R0);
+        load(qs - sd, R1);
+        load(qs, R2);
+        load(qs + sd, R3);
+        load(qs + 2 * sd, R4);
+        const int n = y1 - y0 + 2;             // steps: the head runs over y0..y1+1
+        for (int i = 0; i < n; i += 6) {
+            body<DN>(i, qs, R0, R1, R2, R5, D0, D1, F0, F1);
+            if (i + 1 >= n) break;
+            body<DN>(i + 1, qs, R1, R2, R3, R0, D1, D0, F1, F0);
+            if (i + 2 >= n) break;
+            body<DN>(i + 2, qs, R2, R3, R4, R1, D0, D1, F0, F1);
+            if (i + 3 >= n) break;
+            body<DN>(i + 3, qs, R3, R4, R5, R2, D1, D0, F1, F0);
+            if (i + 4 >= n) break;
+            body<DN>(i + 4, qs, R4, R5, R0, R3, D0, D1, F0, F1);
+            if (i + 5 >= n) break;
+            body<DN>(i + 5, qs, R5, R0, R1, R4, D1, D0, F1, F0);
         }
+    }
+
+    // Vertically adjacent tiles march in opposite directions, so that the two rows they share
+    // at a tile edge are read by both at the same time (both at the start or both at the end
+    // of their march) and the second read is served by the L2.
+    __device__ __forceinline__ void run(bool down) const
+    {
+        if (down) run<true>();
+        else run<false>();
     }
 };
 
 template <typename T, bool HAS_EPS, bool HAS_MU>
 __global__ __launch_bounds__(256) void cart2d_step_kernel(Cart2DArgs<T> a)
 {
+    constexpr int NC = cols_per_lane<T>();
     const int lane = threadIdx.x & (WAVE - 1);
     // the wave's index inside the block is uniform: say so, so that everything derived from it
     // (tile, batch item, buffer resources, row offsets) lives in scalar registers
@@ -201,24 +301,39 @@ __global__ __launch_bounds__(256) void cart2d_step_kernel(Cart2DArgs<T> a)
     const Rsrc rE = make_rsrc(HAS_EPS ? a.epsinv + (int64_t)b * ncell : a.U, fbytes);
     const Rsrc rM = make_rsrc(HAS_MU ? a.muinv + (int64_t)b * ncell : a.U, fbytes);
 
-    const int x0 = tx * OUTX - HALO;
-    const int gx = x0 + lane;
+    const int x0 = tx * out_cols<T>() - HALO;
+    const int gx0 = x0 + NC * lane;
     const int y0 = ty * a.tile_y;
     const int y1 = min(y0 + a.tile_y, a.ny);   // rows [y0, y1) are written
-    const uint32_t vlane = (uint32_t)lane * (uint32_t)sizeof(T);
+    const uint32_t vlane = (uint32_t)(NC * lane) * (uint32_t)sizeof(T);
 
-    const bool interior = x0 >= 0 && x0 + WAVE - 1 <= a.nx - 1 && y0 - 2 >= 0 && y1 + 1 <= a.ny - 1;
+    const bool interior = x0 >= 0 && x0 + WAVE * NC - 1 <= a.nx - 1 && y0 - 2 >= 0 && y1 + 1 <= a.ny - 1;
     if (interior) {
-        Strip2D<T, HAS_EPS, HAS_MU, false> s{a, rU, rE, rM, rO, fbytes, vlane, vlane, x0, gx, T(1), false,
-                                             lane >= HALO && lane < WAVE - HALO, y0, y1};
-        s.run();
+        Strip2D<T, NC, HAS_EPS, HAS_MU, false> s{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0};
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            s.vx[k] = 0;
+            s.sgx[k] = T(1);
+            s.nrx[k] = false;
+            s.writer[k] = NC * lane + k >= HALO && NC * lane + k < WAVE * NC - HALO;
+        }
+        s.y0 = y0;
+        s.y1 = y1;
+        s.run(ty & 1);
     } else {
-        bool mirx, nrx;
-        const int sx = map_axis(gx, a.nx, a.bc[0], a.bc[1], mirx, nrx);
-        Strip2D<T, HAS_EPS, HAS_MU, true> s{a, rU, rE, rM, rO, fbytes, (uint32_t)sx * (uint32_t)sizeof(T), vlane, x0, gx,
-                                            mirx ? T(-1) : T(1), nrx,
-                                            lane >= HALO && lane < WAVE - HALO && gx < a.nx, y0, y1};
-        s.run();
+        Strip2D<T, NC, HAS_EPS, HAS_MU, true> s{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0};
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            bool mirx, nrx;
+            const int sx = map_axis(gx0 + k, a.nx, a.bc[0], a.bc[1], mirx, nrx);
+            s.vx[k] = (uint32_t)sx * (uint32_t)sizeof(T);
+            s.sgx[k] = mirx ? T(-1) : T(1);   // x mirror: Ez and Hx odd, Hy even
+            s.nrx[k] = nrx;
+            s.writer[k] = NC * lane + k >= HALO && NC * lane + k < WAVE * NC - HALO && gx0 + k < a.nx;
+        }
+        s.y0 = y0;
+        s.y1 = y1;
+        s.run(ty & 1);
     }
 }
 
@@ -239,6 +354,6 @@ int launch_cart2d_step(const Cart2DArgs<T> &a, void *stream)
 template int launch_cart2d_step<float>(const Cart2DArgs<float> &, void *);
 template int launch_cart2d_step<double>(const Cart2DArgs<double> &, void *);
 
-int cart2d_tile_x() { return OUTX; }
+int cart2d_tile_x(int precision) { return precision == GKS_FP64 ? out_cols<double>() : out_cols<float>(); }
 
 }  // namespace gks
