@@ -176,11 +176,17 @@ gks_status step_cart2d(gks_ctx *x, const void *Uin, void *Uout, double tn)
     a.nty = (a.ny + a.tile_y - 1) / a.tile_y;
     a.ops = (const FaceOpTM<T> *)x->d_ops;
     const int64_t ns = (int64_t)x->src_cells.size();
+    // dt * S_z = -dt * J_z(t^n), scaled by 1/eps of the cell in the kernels
+    const double amp = ns ? -x->dt * source_pulse(x, tn) : 0.0;
+    a.src_row = -1;
+    if (ns == 1) {   // a single source cell is added inside the step kernel
+        a.src_row = (int32_t)(x->src_cells[0] / x->n[0]);
+        a.src_col = (int32_t)(x->src_cells[0] % x->n[0]);
+        a.src_amp = amp * x->src_w[0];
+    }
     int e = launch_cart2d_step<T>(a, x->stream);
     if (e) return hip_fail(x, e, "GKS step launch");
-    if (ns > 0) {
-        // dt * S_z = -dt * J_z(t^n), scaled by 1/eps of the cell in the kernel
-        const double amp = -x->dt * source_pulse(x, tn);
+    if (ns > 1) {
         e = launch_source_scatter<T>((T *)Uout, (const T *)x->epsinv, x->ncell, (int64_t)x->nfields * x->ncell,
                                      (int32_t)x->batch, 0, x->d_src_cells, x->d_src_w, amp, (int32_t)ns, x->stream);
         if (e) return hip_fail(x, e, "source launch");

@@ -54,6 +54,8 @@ struct Cart2DArgs {
     int32_t ntx, nty;     // tiles per row / column
     int32_t tile_y;       // rows per tile
     const FaceOpTM<T> *ops;   // device: x-face and y-face operators
+    int32_t src_row, src_col; // one point source applied inside the step (src_row < 0: none)
+    double src_amp;           // its dt * S_z = -dt * J_z(t^n) (before the 1/eps factor)
 };
 
 // Arguments of the Cartesian 2D TM adjoint kernel.

@@ -12,9 +12,10 @@
 //   3. evaluates the GKS flux of the horizontal face below the middle row and of the vertical
 //      face right of each column, as sparse linear forms of the stencil values (the
 //      closed-form moments of Sec. 3.1 folded into coefficients on the host);
-//   4. forms the flux divergence of each cell of the row it finishes, adds it to the old value
-//      in double precision and stores once.  (Explicit point sources are added afterwards by a
-//      small scatter kernel, which keeps the per-cell source test out of the marching loop.)
+//   4. forms the flux divergence of each cell of the row it finishes, adds it and the explicit
+//      source of a single source cell to the old value in double precision and stores once
+//      (longer source lists are added afterwards by a small scatter kernel, which keeps the
+//      per-cell source tests out of the marching loop).
 // The row loop is unrolled six times so that the rotating window (six row slots, two gradient
 // slots, two flux slots) lives in fixed registers without copies.
 // Strips that touch no domain side take a path without index mapping.  On the others, ghost
@@ -197,10 +198,20 @@ struct Strip2D {
             apply_op<PatTMx>(v, Rs.mE[k] + mEr, Rs.mH[k] + mHr, opx, fx[k]);
         }
 
-        // update: per-cell flux divergence (FP32 in FP32 mode), then the old value added in
-        // FP64 with a single rounding (point sources are added by a separate scatter kernel)
-        const uint32_t rowc = (uint32_t)(q - 2 * sd) * (uint32_t)a.nx;
+        // update: per-cell flux divergence (FP32 in FP32 mode), then the old value and the
+        // source added in FP64 with a single rounding (a single point-source cell is handled
+        // here; longer source lists by a separate scatter kernel)
+        const int row = q - 2 * sd;
+        const uint32_t rowc = (uint32_t)row * (uint32_t)a.nx;
         T nv[NC][3];
+        double src[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) src[k] = 0.0;
+        if (row == a.src_row) {   // uniform: the row holding the (single) point source
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+                if (gx0 + k == a.src_col) src[k] = a.src_amp;
+        }
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
 #pragma unroll
@@ -209,7 +220,8 @@ struct Strip2D {
                 const T dyf = DN ? fyP[k][f] - fyN[k][f] : fyN[k][f] - fyP[k][f];   // upper - lower face
                 const T div = (fx[k][f] - fl) + dyf;
                 const double m = (f == 0) ? (double)Rs.mE[k] : (double)Rs.mH[k];
-                nv[k][f] = (T)((double)Rs.u[k][f] - m * (double)div);
+                const double add = (f == 0) ? src[k] : 0.0;
+                nv[k][f] = (T)((double)Rs.u[k][f] + m * (add - (double)div));
             }
         }
         if constexpr (!BND) {
