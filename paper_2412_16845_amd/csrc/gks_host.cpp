@@ -56,6 +56,8 @@ struct gks_ctx {
     size_t d_out_count = 0;
     double *h_out = nullptr;        // pinned host mirror
     size_t h_out_count = 0;
+    void *adj_scratch = nullptr;    // adjoint: padded face adjoints, ghost co-states, ghost material gradients
+    size_t adj_scratch_bytes = 0;
 
     std::string err;
 };
@@ -199,6 +201,50 @@ gks_status do_step(gks_ctx *x, const void *Uin, void *Uout, double tn)
     if (x->kind == GKS_CART2D)
         return x->prec == GKS_FP64 ? step_cart2d<double>(x, Uin, Uout, tn) : step_cart2d<float>(x, Uin, Uout, tn);
     return fail(x, GKS_ESTATE, "this mesh kind has no step kernel");
+}
+
+template <typename T>
+gks_status adjoint_cart2d(gks_ctx *x, const void *Un, const void *lam_np1, void *lam_n, double *g_epsinv,
+                          double *g_muinv, double tn)
+{
+    const int64_t npos = (x->n[0] + 4) * (x->n[1] + 4);
+    const size_t n9 = (size_t)x->batch * 9 * npos, n3 = (size_t)x->batch * 3 * npos, n2 = (size_t)x->batch * 2 * npos;
+    const size_t bytes = n2 * sizeof(double) + (n9 + n3) * sizeof(T);
+    if (x->adj_scratch_bytes < bytes) {
+        if (x->adj_scratch) hipFree(x->adj_scratch);
+        x->adj_scratch = nullptr;
+        x->adj_scratch_bytes = 0;
+        if (hipMalloc(&x->adj_scratch, bytes) != hipSuccess)
+            return fail(x, GKS_ENOMEM, "cannot allocate the %zu-byte adjoint scratch", bytes);
+        x->adj_scratch_bytes = bytes;
+    }
+    double *padg = (double *)x->adj_scratch;
+    T *pad9 = (T *)(padg + n2);
+    T *padpsi = pad9 + n9;
+    Cart2DAdjArgs<T> a;
+    std::memset(&a, 0, sizeof a);
+    a.U = (const T *)Un;
+    a.lam = (const T *)lam_np1;
+    a.lam_out = (T *)lam_n;
+    a.g_epsinv = g_epsinv;
+    a.g_muinv = g_muinv;
+    a.epsinv = (const T *)x->epsinv;
+    a.muinv = (const T *)x->muinv;
+    a.nx = (int32_t)x->n[0];
+    a.ny = (int32_t)x->n[1];
+    a.batch = (int32_t)x->batch;
+    for (int i = 0; i < 4; ++i) a.bc[i] = x->bc[i];
+    a.ops = (const FaceOpTM<T> *)x->d_ops;
+    int e = launch_cart2d_adjoint<T>(a, pad9, padpsi, padg, x->stream);
+    if (e) return hip_fail(x, e, "adjoint launch");
+    const int64_t ns = (int64_t)x->src_cells.size();
+    if (ns > 0 && g_epsinv) {
+        const double amp = -x->dt * source_pulse(x, tn);
+        e = launch_adjoint_source<T>((const T *)lam_np1, g_epsinv, x->ncell, (int64_t)x->nfields * x->ncell,
+                                     (int32_t)x->batch, x->d_src_cells, x->d_src_w, amp, (int32_t)ns, x->stream);
+        if (e) return hip_fail(x, e, "adjoint source launch");
+    }
+    return GKS_OK;
 }
 
 gks_status ensure_out(gks_ctx *x, size_t count)
@@ -371,6 +417,7 @@ extern "C" gks_status gks_destroy(gks_ctx *ctx)
     if (ctx->h_out) hipHostFree(ctx->h_out);
     if (ctx->d_src_cells) hipFree(ctx->d_src_cells);
     if (ctx->d_src_w) hipFree(ctx->d_src_w);
+    if (ctx->adj_scratch) hipFree(ctx->adj_scratch);
     delete ctx;
     return GKS_OK;
 }
@@ -565,6 +612,16 @@ extern "C" gks_status gks_adjoint_step(gks_ctx *ctx, const void *U_n, const void
                                        double *g_epsinv, double *g_muinv, double t_n)
 {
     if (!ctx) return GKS_EINVAL;
-    (void)U_n; (void)lam_np1; (void)lam_n; (void)g_epsinv; (void)g_muinv; (void)t_n;
-    return fail(ctx, GKS_ESTATE, "the adjoint step is not available in this build");
+    if (ctx->kind != GKS_CART2D) return fail(ctx, GKS_ESTATE, "the adjoint step exists for Cartesian 2D TM contexts only");
+    if (!U_n || !lam_np1 || !lam_n) return fail(ctx, GKS_EINVAL, "U_n, lam_np1 or lam_n is NULL");
+    const size_t sb = state_bytes(ctx), gb = (size_t)ctx->batch * ctx->ncell * sizeof(double);
+    if (ranges_overlap(lam_n, lam_np1, sb) || ranges_overlap(lam_n, U_n, sb))
+        return fail(ctx, GKS_EINVAL, "lam_n overlaps lam_np1 or U_n");
+    if (g_epsinv && g_muinv && ranges_overlap(g_epsinv, g_muinv, gb))
+        return fail(ctx, GKS_EINVAL, "g_epsinv and g_muinv overlap");
+    if (!std::isfinite(t_n)) return fail(ctx, GKS_EINVAL, "t_n is not finite");
+    gks_status st = check_device(ctx);
+    if (st) return st;
+    return ctx->prec == GKS_FP64 ? adjoint_cart2d<double>(ctx, U_n, lam_np1, lam_n, g_epsinv, g_muinv, t_n)
+                                 : adjoint_cart2d<float>(ctx, U_n, lam_np1, lam_n, g_epsinv, g_muinv, t_n);
 }

@@ -58,7 +58,7 @@ struct Cart2DArgs {
     double src_amp;           // its dt * S_z = -dt * J_z(t^n) (before the 1/eps factor)
 };
 
-// Arguments of the Cartesian 2D TM adjoint kernel.
+// Arguments of the Cartesian 2D TM adjoint kernels.
 template <typename T>
 struct Cart2DAdjArgs {
     const T *U;           // state the forward step started from
@@ -66,18 +66,23 @@ struct Cart2DAdjArgs {
     T *lam_out;           // lambda^n
     double *g_epsinv;     // nullable, accumulated
     double *g_muinv;      // nullable, accumulated
-    const T *epsinv;
-    const T *muinv;
+    const T *epsinv;      // nullable: vacuum
+    const T *muinv;       // nullable: vacuum
     int32_t nx, ny, batch;
     int32_t bc[4];
-    int32_t ntx, nty;
-    int32_t tile_y;
     const FaceOpTM<T> *ops;   // device: x-face and y-face operators
 };
 
 // Launchers (defined in the .hip files).  Return a hipError_t as int.
 template <typename T> int launch_cart2d_step(const Cart2DArgs<T> &a, void *stream);
-template <typename T> int launch_cart2d_adjoint(const Cart2DAdjArgs<T> &a, void *stream);
+// Adjoint of one 2D step.  Scratch (device): pad9 [batch][9][(nx+4)(ny+4)] and padpsi
+// [batch][3][(nx+4)(ny+4)] of T, padg [batch][2][(nx+4)(ny+4)] doubles; all fully overwritten.
+template <typename T> int launch_cart2d_adjoint(const Cart2DAdjArgs<T> &a, T *pad9, T *padpsi, double *padg,
+                                                void *stream);
+// g_epsinv[b][cells[s]] += lam[b][Ez][cells[s]] * amp * weight[s]  (1/eps gradient of the source)
+template <typename T> int launch_adjoint_source(const T *lam, double *g_epsinv, int64_t ncell, int64_t fstride,
+                                                int32_t batch, const int64_t *cells, const double *weight,
+                                                double amp, int32_t n, void *stream);
 // U[b][field][cells[s]] += (1/eps) * amp * weight[s]  (explicit point source after a step)
 template <typename T> int launch_source_scatter(T *U, const T *epsinv, int64_t ncell, int64_t fstride,
                                                 int32_t batch, int32_t field, const int64_t *cells,
