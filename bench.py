@@ -1,6 +1,6 @@
 """Benchmark of the GKS step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-adjoint]
 
 Workload: 2D TM fields on a 4096 x 4096 Cartesian grid of the unit square, kinetic
 non-reflecting sides, eps map of 64 seeded circular inclusions (eps in [1, 4]), Gaussian point
@@ -16,7 +16,9 @@ One JSON line on stdout:
                  launch) against the 8 TB/s peak; traffic = HBM bytes per launch from the
                  committed rocprofv3 counter summary (null when the kernel source changed since)
   cpu_baseline   the FP64 oracle on the host cores, on a bounded sample of the same workload
-  adjoint        forward + adjoint step time of the differentiable workload (when built)
+  adjoint        forward + adjoint step time of the differentiable workload (1024^2 x 8 maps,
+                 800 steps, checkpoints every 50) beside the plain FP64 and FP32 steps of the
+                 same grids, and the adjoint step's own per-launch time
 
 Helper modes for the profiles: --profile-kernel PREC runs only step kernels (for rocprofv3);
 --copy-calibration runs a plain device copy of known size (counter scale factor).
@@ -158,12 +160,95 @@ def cpu_baseline(wl, dt):
                                         f"{el:.1f} s, FP64 literal per-face lattice sums"}
 
 
+ADJ_N, ADJ_BATCH, ADJ_STEPS, ADJ_K = 1024, 8, 800, 50
+# adjoint step, algorithmic bytes per cell: read lambda' (3) and U^n (3) and 1/eps, write lambda (3)
+# in the field type; read and write the FP64 1/eps gradient
+ADJ_BYTES_PER_CELL = 7 * 4 + 3 * 4 + 16
+
+
+def adjoint_leg(torch):
+    """The differentiable workload: 8 dielectric maps of 1024 x 1024, probe-box loss after 800
+    steps, reverse mode with checkpoints every 50 steps (FP32 fields, FP64 gradient sums),
+    timed end to end (forward with checkpoints, then per segment recompute + adjoint steps)
+    next to the plain FP64 and FP32 runs of the same grids."""
+    from paper_2412_16845_amd import autograd as AG
+    from paper_2412_16845_amd import inputs as I
+    from paper_2412_16845_amd.gks import Solver
+    wl = I.tm_batch_probe(n=ADJ_N, batch=ADJ_BATCH, seed=0, nsteps=ADJ_STEPS)
+    ncell = ADJ_N * ADJ_N * ADJ_BATCH
+
+    def solver(prec):
+        dtype = torch.float64 if prec == "fp64" else torch.float32
+        s = Solver("cart2d", n=wl.n, bc=wl.bc, precision=prec, batch=wl.batch, cfl=wl.cfl,
+                   tau_over_dt=wl.tau_over_dt)
+        E = torch.tensor(wl.epsinv, dtype=dtype, device="cuda")
+        s.set_material(E)
+        return s, E, torch.tensor(wl.U0, dtype=dtype, device="cuda")
+
+    def timed(s, fn):
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s.stream)
+        fn()
+        b.record(s.stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3
+
+    plain = {}
+    for prec in ("fp64", "fp32"):
+        s, E, U = solver(prec)
+        s.run(U, 50)
+        plain[prec] = timed(s, lambda: s.run(U, ADJ_STEPS)) / ADJ_STEPS
+        del s, E, U
+    s, E, U0 = solver("fp32")
+    E.requires_grad_(True)
+
+    def fwd_bwd(nsteps):
+        E.grad = None
+        UN = AG.run(s, U0, nsteps, E, None, checkpoint_every=ADJ_K)
+        AG.probe_energy(s, UN, wl.probe).sum().backward()
+
+    fwd_bwd(2 * ADJ_K)
+    t_fb = timed(s, lambda: fwd_bwd(ADJ_STEPS))
+    if not torch.isfinite(E.grad).all():
+        raise RuntimeError("non-finite permittivity gradient")
+    # per-launch duration of the adjoint step (its kernels together) on the solver's stream
+    lam = torch.randn_like(U0)
+    out = torch.empty_like(U0)
+    g = torch.zeros((wl.batch,) + s.grid, dtype=torch.float64, device="cuda")
+    Ed = E.detach()
+    s.set_material(Ed)
+    for _ in range(5):
+        s.adjoint_step(U0, lam, out, g)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(50)]
+    for e0, e1 in evs:
+        e0.record(s.stream)
+        s.adjoint_step(U0, lam, out, g)
+        e1.record(s.stream)
+    torch.cuda.synchronize()
+    t_adj = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs])) / 1e3
+    alg = ADJ_BYTES_PER_CELL * ncell
+    return {"workload": f"tm_batch_probe: 2D TM {ADJ_N}x{ADJ_N} x batch {ADJ_BATCH}, non-reflecting sides, "
+                        f"16 dielectric discs per map, probe-box Ez energy after {ADJ_STEPS} steps, "
+                        f"checkpoints every {ADJ_K} steps, FP32 fields, FP64 gradient accumulation",
+            "fwd_adj_ms_per_step": round(t_fb * 1e3 / ADJ_STEPS, 5),
+            "plain_fp64_ms_per_step": round(plain["fp64"] * 1e3, 5),
+            "plain_fp32_ms_per_step": round(plain["fp32"] * 1e3, 5),
+            "fwd_adj_over_fp64_step": round(t_fb / ADJ_STEPS / plain["fp64"], 3),
+            "adjoint_step_us_per_launch": round(t_adj * 1e6, 2),
+            "adjoint_roofline": {"bound": "hbm", "achieved": round(alg / t_adj / 1e9, 1), "peak": PEAK_GBS,
+                                 "unit": "GB/s", "frac": round(alg / t_adj / 1e9 / PEAK_GBS, 4),
+                                 "algorithmic_bytes_per_launch": alg}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--profile-kernel", choices=["fp32", "fp64"])
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -232,6 +317,9 @@ def main():
                  "ms_per_step": round(f64["seconds"] * 1e3 / args.steps, 5), "dtype": "f64",
                  "roofline": roofline("fp64", f64["t_launch"])},
     }
+    if not args.no_adjoint:
+        log("[bench] adjoint: 1024x1024 x 8, 800 steps forward + reverse with checkpoints every 50")
+        out["adjoint"] = adjoint_leg(torch)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline: oracle on a 1024x1024 window")
         out["cpu_baseline"] = cpu_baseline(wl, f64["dt"])

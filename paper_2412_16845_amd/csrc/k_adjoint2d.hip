@@ -264,6 +264,27 @@ __global__ __launch_bounds__(ADJ_BLOCK) void adj2d_psi_kernel(Cart2DAdjArgs<T> a
     }
 }
 
+// Cells within two cells of a side (the only ones a ghost position reads): the first and
+// last two rows in full, then the first and last two columns of the rows between.
+struct Band2D {
+    int nx, ny, nrow, ncol;   // band rows (all rows if ny <= 4), band columns of the middle rows
+    __host__ __device__ Band2D(int nx_, int ny_) : nx(nx_), ny(ny_), nrow(ny_ <= 4 ? ny_ : 4), ncol(nx_ <= 4 ? nx_ : 4) {}
+    __host__ __device__ int64_t count() const { return (int64_t)nrow * nx + (int64_t)(ny > 4 ? ny - 4 : 0) * ncol; }
+    __device__ void cell(int64_t t, int &i, int &j) const
+    {
+        if (t < (int64_t)nrow * nx) {
+            const int r = (int)(t / nx);
+            i = (int)(t % nx);
+            j = (ny <= 4 || r < 2) ? r : ny - 4 + r;
+        } else {
+            const int64_t u = t - (int64_t)nrow * nx;
+            const int c = (int)(u % ncol);
+            j = 2 + (int)(u / ncol);
+            i = (nx <= 4 || c < 2) ? c : nx - 4 + c;
+        }
+    }
+};
+
 // pad^T: each cell within two cells of a side gathers the ghost positions that read it.
 template <typename T>
 __global__ __launch_bounds__(ADJ_BLOCK) void adj2d_fold_kernel(Cart2DAdjArgs<T> a, const T *padpsi, const double *padg)
@@ -272,11 +293,12 @@ __global__ __launch_bounds__(ADJ_BLOCK) void adj2d_fold_kernel(Cart2DAdjArgs<T> 
     const int64_t npos = pd.size();
     const int64_t ncell = (int64_t)a.nx * a.ny;
     const int b = blockIdx.y;
-    const int64_t t = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
-    if (t >= ncell) return;
-    const int i = (int)(t % a.nx), j = (int)(t / a.nx);
-    const bool nearx = i < 2 || i >= a.nx - 2, neary = j < 2 || j >= a.ny - 2;
-    if (!nearx && !neary) return;
+    const Band2D band(a.nx, a.ny);
+    const int64_t tb = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
+    if (tb >= band.count()) return;
+    int i, j;
+    band.cell(tb, i, j);
+    const int64_t t = (int64_t)j * a.nx + i;
     // candidate images along each axis: the cell itself and the ghost indices that map to it
     int cx[5], cy[5], nxc = 0, nyc = 0;
     T sx[5], sy[5];
@@ -327,14 +349,14 @@ int launch_cart2d_adjoint(const Cart2DAdjArgs<T> &a, T *pad9, T *padpsi, double 
 {
     hipStream_t s = (hipStream_t)stream;
     const int64_t npos = (int64_t)(a.nx + 4) * (a.ny + 4);
-    const int64_t ncell = (int64_t)a.nx * a.ny;
-    dim3 gpad((unsigned)((npos + ADJ_BLOCK - 1) / ADJ_BLOCK), a.batch), gcell((unsigned)((ncell + ADJ_BLOCK - 1) / ADJ_BLOCK), a.batch);
+    const int64_t nband = Band2D(a.nx, a.ny).count();
+    dim3 gpad((unsigned)((npos + ADJ_BLOCK - 1) / ADJ_BLOCK), a.batch), gband((unsigned)((nband + ADJ_BLOCK - 1) / ADJ_BLOCK), a.batch);
     if (a.epsinv && a.muinv) hipLaunchKernelGGL((adj2d_faces_kernel<T, true, true>), gpad, dim3(ADJ_BLOCK), 0, s, a, pad9, padg);
     else if (a.epsinv) hipLaunchKernelGGL((adj2d_faces_kernel<T, true, false>), gpad, dim3(ADJ_BLOCK), 0, s, a, pad9, padg);
     else if (a.muinv) hipLaunchKernelGGL((adj2d_faces_kernel<T, false, true>), gpad, dim3(ADJ_BLOCK), 0, s, a, pad9, padg);
     else hipLaunchKernelGGL((adj2d_faces_kernel<T, false, false>), gpad, dim3(ADJ_BLOCK), 0, s, a, pad9, padg);
     hipLaunchKernelGGL(adj2d_psi_kernel<T>, gpad, dim3(ADJ_BLOCK), 0, s, a, (const T *)pad9, padpsi);
-    hipLaunchKernelGGL(adj2d_fold_kernel<T>, gcell, dim3(ADJ_BLOCK), 0, s, a, (const T *)padpsi, (const double *)padg);
+    hipLaunchKernelGGL(adj2d_fold_kernel<T>, gband, dim3(ADJ_BLOCK), 0, s, a, (const T *)padpsi, (const double *)padg);
     return (int)hipGetLastError();
 }
 

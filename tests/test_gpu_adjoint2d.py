@@ -263,3 +263,48 @@ def test_autograd_run_against_oracle(torch, precision):
             rel_l2(E.grad.cpu().numpy(), np.stack(gE)), rel_l2(M.grad.cpu().numpy(), np.stack(gH)))
     print(f"autograd {precision}: loss {errs[0]:.2e} dU0 {errs[1]:.2e} deps {errs[2]:.2e} dmu {errs[3]:.2e}")
     assert max(errs) <= TOL[precision]
+
+
+def test_c5_gradient_against_finite_differences(torch):
+    """The differentiable workload at full size: 1024 x 1024 x 8 dielectric maps, probe-box Ez
+    energy after 800 steps, reverse mode with checkpoints every 50 steps.  The FP64 gradient
+    with respect to 1/eps at 16 seeded cells between the pulse and the probe box (in every map)
+    against central finite differences of whole forward runs (step 1e-4 of the value), and the
+    FP32-field gradient (FP64 accumulation) against the FP64 one over the whole map."""
+    from paper_2412_16845_amd import autograd as AG
+    wl = full_workload()
+    n, K = wl.n[0], wl.nsteps
+    grads = {}
+    for prec in ("fp64", "fp32"):
+        s, E, _ = solver_for(torch, n, n, wl.bc, wl.tau_over_dt, prec, wl.batch, wl.epsinv, None)
+        U0 = dev(torch, wl.U0, prec)
+        E.requires_grad_(True)
+        UN = AG.run(s, U0, K, E, None, checkpoint_every=50)
+        AG.probe_energy(s, UN, wl.probe).sum().backward()
+        grads[prec] = E.grad.to(torch.float64).cpu().numpy()
+        del s, E, U0, UN
+    s, E, _ = solver_for(torch, n, n, wl.bc, wl.tau_over_dt, "fp64", wl.batch, wl.epsinv, None)
+    U0 = dev(torch, wl.U0, "fp64")
+    rng = np.random.default_rng(16)
+    xs = rng.integers(int(0.35 * n), int(0.6 * n), 16)
+    ys = rng.integers(int(0.42 * n), int(0.58 * n), 16)
+    fd, an = [], []
+    for ix, iy in zip(xs, ys):
+        h = 1e-4 * E[:, iy, ix].clone()
+        vals = []
+        for sign in (1.0, -1.0):
+            Ep = E.clone()
+            Ep[:, iy, ix] += sign * h
+            s.set_material(Ep)
+            U = U0.clone()
+            s.run(U, K)
+            vals.append(s.probe_energy(U, wl.probe))
+        fd.append((vals[0] - vals[1]) / (2 * h.cpu().numpy()))
+        an.append(grads["fp64"][:, iy, ix])
+    fd, an = np.concatenate(fd), np.concatenate(an)
+    err_fd = rel_l2(an, fd)
+    err32 = rel_l2(grads["fp32"], grads["fp64"])
+    print(f"C5 gradient: FP64 vs central differences at 128 cells {err_fd:.2e}; FP32 vs FP64 field {err32:.2e}; "
+          f"|g| range {np.abs(an).min():.2e}..{np.abs(an).max():.2e}")
+    assert err_fd <= 1e-6
+    assert err32 <= 1e-4
