@@ -34,6 +34,7 @@ struct gks_ctx {
     int device = 0;
     int ncu = 256;                  // compute units of the device
     int32_t tile_y = 64;            // rows per wave tile (Cartesian 2D)
+    int32_t tile_z = 64;            // planes per workgroup tile (Cartesian 3D)
     const void *epsinv = nullptr, *muinv = nullptr;
 
     // face operators in double precision: [orientation][...]
@@ -152,6 +153,27 @@ int gks::cart2d_pick_tile_y(int nx, int ny, int batch, int ncu, int precision)
     return std::max(1, std::min(16, ny));
 }
 
+int gks::cart3d_pick_tile_z(int nx, int ny, int nz, int batch, int ncu, int precision)
+{
+    // One workgroup per compute unit at a time (its LDS tile takes most of the unit): the step
+    // takes about (rounds of workgroups) x (planes per tile + the three planes the march reads
+    // beyond its tile).
+    const int tx = cart3d_tile_x(precision), ty = cart3d_tile_y(precision);
+    const int64_t per_z = (int64_t)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * batch;
+    double best = 1e300;
+    int pick = nz;
+    for (int tz = std::min(4, nz); tz <= nz; ++tz) {
+        const int64_t ntz = (nz + tz - 1) / tz;
+        const int64_t rounds = (per_z * ntz + ncu - 1) / ncu;
+        const double cost = (double)rounds * (tz + 3);
+        if (cost < best) {
+            best = cost;
+            pick = tz;
+        }
+    }
+    return pick;
+}
+
 namespace {
 
 double source_pulse(const gks_ctx *x, double t)
@@ -196,10 +218,44 @@ gks_status step_cart2d(gks_ctx *x, const void *Uin, void *Uout, double tn)
     return GKS_OK;
 }
 
+template <typename T>
+gks_status step_cart3d(gks_ctx *x, const void *Uin, void *Uout, double tn)
+{
+    Cart3DArgs<T> a;
+    std::memset(&a, 0, sizeof a);
+    a.U = (const T *)Uin;
+    a.Unew = (T *)Uout;
+    a.epsinv = (const T *)x->epsinv;
+    a.muinv = (const T *)x->muinv;
+    a.nx = (int32_t)x->n[0];
+    a.ny = (int32_t)x->n[1];
+    a.nz = (int32_t)x->n[2];
+    a.batch = (int32_t)x->batch;
+    for (int i = 0; i < 6; ++i) a.bc[i] = x->bc[i];
+    const int tx = cart3d_tile_x(x->prec), ty = cart3d_tile_y(x->prec);
+    a.ntx = (a.nx + tx - 1) / tx;
+    a.nty = (a.ny + ty - 1) / ty;
+    a.tile_z = x->tile_z;
+    a.ntz = (a.nz + a.tile_z - 1) / a.tile_z;
+    a.ops = (const FaceOpEM<T> *)x->d_ops;
+    int e = launch_cart3d_step<T>(a, x->stream);
+    if (e) return hip_fail(x, e, "GKS 3D step launch");
+    const int64_t ns = (int64_t)x->src_cells.size();
+    if (ns > 0) {   // J_z drives Ez (field 2)
+        const double amp = -x->dt * source_pulse(x, tn);
+        e = launch_source_scatter<T>((T *)Uout, (const T *)x->epsinv, x->ncell, (int64_t)x->nfields * x->ncell,
+                                     (int32_t)x->batch, 2, x->d_src_cells, x->d_src_w, amp, (int32_t)ns, x->stream);
+        if (e) return hip_fail(x, e, "source launch");
+    }
+    return GKS_OK;
+}
+
 gks_status do_step(gks_ctx *x, const void *Uin, void *Uout, double tn)
 {
     if (x->kind == GKS_CART2D)
         return x->prec == GKS_FP64 ? step_cart2d<double>(x, Uin, Uout, tn) : step_cart2d<float>(x, Uin, Uout, tn);
+    if (x->kind == GKS_CART3D)
+        return x->prec == GKS_FP64 ? step_cart3d<double>(x, Uin, Uout, tn) : step_cart3d<float>(x, Uin, Uout, tn);
     return fail(x, GKS_ESTATE, "this mesh kind has no step kernel");
 }
 
@@ -396,6 +452,8 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
     }
     if (x->kind == GKS_CART2D)
         x->tile_y = cart2d_pick_tile_y((int)x->n[0], (int)x->n[1], (int)x->batch, x->ncu, x->prec);
+    if (x->kind == GKS_CART3D)
+        x->tile_z = cart3d_pick_tile_z((int)x->n[0], (int)x->n[1], (int)x->n[2], (int)x->batch, x->ncu, x->prec);
     {
         gks_status st = upload_ops(x);
         if (st) return bail(st);

@@ -58,6 +58,21 @@ struct Cart2DArgs {
     double src_amp;           // its dt * S_z = -dt * J_z(t^n) (before the 1/eps factor)
 };
 
+// Arguments of the Cartesian 3D (six-field) step kernel.
+template <typename T>
+struct Cart3DArgs {
+    const T *U;
+    T *Unew;
+    const T *epsinv;      // nullable: vacuum
+    const T *muinv;       // nullable: vacuum
+    int32_t nx, ny, nz;
+    int32_t batch;
+    int32_t bc[6];        // x-, x+, y-, y+, z-, z+
+    int32_t ntx, nty, ntz;   // workgroup tiles along x, y and z
+    int32_t tile_z;          // planes per z tile
+    const FaceOpEM<T> *ops;  // device: x-, y- and z-face operators
+};
+
 // Arguments of the Cartesian 2D TM adjoint kernels.
 template <typename T>
 struct Cart2DAdjArgs {
@@ -87,6 +102,12 @@ template <typename T> int launch_adjoint_source(const T *lam, double *g_epsinv, 
 template <typename T> int launch_source_scatter(T *U, const T *epsinv, int64_t ncell, int64_t fstride,
                                                 int32_t batch, int32_t field, const int64_t *cells,
                                                 const double *weight, double amp, int32_t n, void *stream);
+template <typename T> int launch_cart3d_step(const Cart3DArgs<T> &a, void *stream);
+// Output columns / rows per 3D workgroup tile (depend on the element size).
+int cart3d_tile_x(int precision);
+int cart3d_tile_y(int precision);
+// Planes per 3D z tile for an nx x ny x nz x batch grid on ncu compute units.
+int cart3d_pick_tile_z(int nx, int ny, int nz, int batch, int ncu, int precision);
 // Columns written per wave strip (depends on the element size).
 int cart2d_tile_x(int precision);
 // Rows per wave tile for an nx x ny x batch grid on a device with ncu compute units: the

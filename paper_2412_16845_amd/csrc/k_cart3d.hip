@@ -1,0 +1,315 @@
+// Fused GKS step on a 3D Cartesian grid, six fields (Ex, Ey, Ez, Hx, Hy, Hz).
+//
+// A workgroup owns a tile of 64 columns (x) by ROWS rows (y) and marches it through a range of
+// z planes.  Wave w holds row w of the tile, one column per lane; the two outermost columns and
+// rows on each side are halo, the rest are written.  Per plane q the workgroup:
+//   1. issues the loads of plane q+2 (each lane: six fields and the materials of its cell), so
+//      one plane of loads is in flight while plane q is processed;
+//   2. shares the fields of plane q through LDS and forms the Green-Gauss (central) differences
+//      of plane q: along x from the neighbouring lanes (DPP row shifts), along y from the rows
+//      above and below (LDS), along z from the planes q-1 and q+1 it holds in registers;
+//   3. shares the differences and evaluates, as sparse linear forms of the face inputs (the
+//      closed-form moments of Sec. 3.1 folded into coefficients on the host), the flux of the
+//      face above each cell (y, with the upper row's data from LDS), right of it (x, with the
+//      next lane's data by DPP) and below it in z (from the previous plane kept in registers);
+//   4. shares the y fluxes and finishes the flux divergence of each cell of plane q-1, adding
+//      it to the old value in double precision with a single rounding on store.
+// Each face is evaluated once; each field value is loaded once per workgroup.  The three LDS
+// slots (fields, differences and materials, y fluxes) are single-buffered: the barriers of
+// one plane order every read of a slot before the next plane's write to it.
+// Boundaries follow the 2D kernel: ghost cells read the wrapped (periodic), mirrored (PEC:
+// tangential E and normal H odd) or clamped (non-reflecting) cell; the ghost side of a
+// non-reflecting boundary face carries no distribution (zero state and slopes).
+#include "gks_device.h"
+
+namespace gks {
+
+namespace {
+
+template <typename T> constexpr int rows3d() { return sizeof(T) == 4 ? 16 : 8; }
+constexpr int OUT_X3 = WAVE - 4;
+
+// Fields that change sign under a PEC mirror across an x-, y- or z-wall (tangential E, normal H).
+constexpr uint32_t ODD_X = (1u << 1) | (1u << 2) | (1u << 3);
+constexpr uint32_t ODD_Y = (1u << 0) | (1u << 2) | (1u << 4);
+constexpr uint32_t ODD_Z = (1u << 0) | (1u << 1) | (1u << 5);
+
+template <typename T>
+struct Plane3 {
+    T u[6];
+    T mE, mH;
+};
+
+template <typename T>
+struct Lds3 {
+    static constexpr int R = rows3d<T>();
+    T u[6][R][WAVE];      // fields of the current plane
+    T g[20][R][WAVE];     // differences [x(6) y(6) z(6)] and mE, mH
+    T p[6][R][WAVE];      // flux of the face above each cell (y)
+};
+
+__device__ __forceinline__ bool side_nr(int g, int n, int bclo, int bchi)
+{
+    return (g < 0 && bclo == GKS_BC_NONREFLECT) || (g >= n && bchi == GKS_BC_NONREFLECT);
+}
+
+template <typename T, bool HAS_EPS, bool HAS_MU, bool BXY>
+struct March3D {
+    static constexpr int R = rows3d<T>();
+    const Cart3DArgs<T> &a;
+    Lds3<T> &s;
+    Rsrc rU, rE, rM, rO;
+    uint32_t fbytes, pbytes;   // bytes per field, per plane
+    uint32_t vcol;             // byte offset of the cell this lane reads, inside a plane
+    uint32_t sgn;              // BXY: fields negated by the x/y mirror of this lane's cell
+    bool nr_c, nr_x, nr_y;     // BXY: non-reflecting ghost at (x, y), (x+1, y), (x, y+1)
+    bool writer;
+    int lane, row, rowp, rowm, z0, z1;
+    bool need_g, need_yf, need_all;   // wave roles by row
+
+    __device__ __forceinline__ void load(int gz, Plane3<T> &p) const
+    {
+        bool mz, nrz;
+        const int sz = map_axis(gz, a.nz, a.bc[4], a.bc[5], mz, nrz);
+        const uint32_t so = (uint32_t)sz * pbytes;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) p.u[f] = buf_load<T>(rU, vcol, so + f * fbytes);
+        p.mE = HAS_EPS ? buf_load<T>(rE, vcol, so) : T(1);
+        p.mH = HAS_MU ? buf_load<T>(rM, vcol, so) : T(1);
+        if constexpr (BXY) {
+#pragma unroll
+            for (int f = 0; f < 6; ++f)
+                if ((sgn >> f) & 1u) p.u[f] = -p.u[f];
+        }
+        if (mz) {   // uniform: a mirrored ghost plane
+#pragma unroll
+            for (int f = 0; f < 6; ++f)
+                if ((ODD_Z >> f) & 1u) p.u[f] = -p.u[f];
+        }
+    }
+
+    __device__ __forceinline__ bool plane_nr(int gz) const { return side_nr(gz, a.nz, a.bc[4], a.bc[5]); }
+
+    // One march step with central plane q: A = q-1, B = q, C = q+1 (loaded), D receives q+2.
+    // Gp / G: differences of planes q-1 / q.  acc: on entry the x and y divergence of plane
+    // q-1 minus the flux of the z face below it; on exit the same for plane q.
+    __device__ __forceinline__ void step(int q, Plane3<T> &A, Plane3<T> &B, Plane3<T> &C, Plane3<T> &D,
+                                         T (&Gp)[18], T (&G)[18], T (&acc)[6]) const
+    {
+        // plane q+2 (beyond the range: re-read the last halo plane, already cached, so that the
+        // load stays unconditional)
+        load(min(q + 2, z1 + 1), D);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) s.u[f][row][lane] = B.u[f];
+        __syncthreads();
+        T uy[6];   // fields of the row above (plane q)
+        if (need_g) {
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                uy[f] = s.u[f][rowp][lane];
+                G[f] = from_right(B.u[f]) - from_left(B.u[f]);
+                G[6 + f] = uy[f] - s.u[f][rowm][lane];
+                G[12 + f] = C.u[f] - A.u[f];
+            }
+            // every face that reads the differences of a non-reflecting ghost zeroes them:
+            // zero them at the source (the lane itself), so that the values neighbours receive
+            // by DPP or LDS need no select on the receiving side
+            if constexpr (BXY) {
+#pragma unroll
+                for (int k = 0; k < 18; ++k) G[k] = nr_c ? T(0) : G[k];
+            }
+        }
+        // face below plane q, then the update of plane q-1, whose divergence it completes
+        if (q >= z0 && need_all) {
+            // inputs [UL UR dzL dxL dyL dzR dxR dyR], L plane q-1
+            const bool zl = plane_nr(q - 1) || (BXY && nr_c), zr = plane_nr(q) || (BXY && nr_c);
+            const auto opz = scalar_ptr_after(a.ops + 2, G[17]);
+            T w[48], Z[6];
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                w[f] = zl ? T(0) : A.u[f];
+                w[6 + f] = zr ? T(0) : B.u[f];
+                w[12 + f] = zl ? T(0) : Gp[12 + f];
+                w[18 + f] = zl ? T(0) : Gp[f];
+                w[24 + f] = zl ? T(0) : Gp[6 + f];
+                w[30 + f] = zr ? T(0) : G[12 + f];
+                w[36 + f] = zr ? T(0) : G[f];
+                w[42 + f] = zr ? T(0) : G[6 + f];
+            }
+            apply_op<PatEMz>(w, A.mE + B.mE, A.mH + B.mH, opz, Z);
+            if (q - 1 >= z0) {
+                const uint32_t so = (uint32_t)(q - 1) * pbytes;
+#pragma unroll
+                for (int f = 0; f < 6; ++f) {
+                    const T div = acc[f] + Z[f];
+                    const double m = (f < 3) ? (double)A.mE : (double)A.mH;
+                    const T nv = (T)((double)A.u[f] - m * (double)div);
+                    if (writer) buf_store(nv, rO, vcol, so + f * fbytes);
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < 6; ++f) acc[f] = -Z[f];
+        }
+        if (need_g) {
+#pragma unroll
+            for (int k = 0; k < 18; ++k) s.g[k][row][lane] = G[k];
+            s.g[18][row][lane] = B.mE;
+            s.g[19][row][lane] = B.mH;
+        }
+        __syncthreads();
+        const bool outp = q >= z0 && q < z1;
+        T px[6], py[6];
+        // this cell's fields as a face side: zero on a non-reflecting ghost (the DPP moves
+        // below then read them unconditionally: a move under a partial lane mask would read the
+        // masked lanes as zero)
+        T su[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) su[f] = (BXY && nr_c) ? T(0) : B.u[f];
+        if (outp && need_yf) {
+            // face above: inputs [UL UR dyL dxL dzL dyR dxR dzR], L this row, R the row above
+            const bool zr = BXY && nr_y;
+            const auto opy = scalar_ptr(a.ops + 1);
+            T w[48];
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                w[f] = su[f];
+                w[6 + f] = zr ? T(0) : uy[f];
+                w[12 + f] = G[6 + f];
+                w[18 + f] = G[f];
+                w[24 + f] = G[12 + f];
+                w[30 + f] = s.g[6 + f][rowp][lane];
+                w[36 + f] = s.g[f][rowp][lane];
+                w[42 + f] = s.g[12 + f][rowp][lane];
+            }
+            apply_op<PatEMy>(w, B.mE + s.g[18][rowp][lane], B.mH + s.g[19][rowp][lane], opy, py);
+#pragma unroll
+            for (int f = 0; f < 6; ++f) s.p[f][row][lane] = py[f];
+        }
+        if (outp && need_all) {
+            // face to the right: inputs [UL UR dxL dyL dzL dxR dyR dzR], R the next lane
+            const auto opx = scalar_ptr_after(a.ops, py[5]);
+            T w[48];
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                w[f] = su[f];
+                w[6 + f] = from_right(su[f]);
+                w[12 + f] = G[f];
+                w[18 + f] = G[6 + f];
+                w[24 + f] = G[12 + f];
+                w[30 + f] = from_right(G[f]);
+                w[36 + f] = from_right(G[6 + f]);
+                w[42 + f] = from_right(G[12 + f]);
+            }
+            apply_op<PatEMx>(w, B.mE + from_right(B.mE), B.mH + from_right(B.mH), opx, px);
+        }
+        __syncthreads();
+        if (outp && need_all) {
+#pragma unroll
+            for (int f = 0; f < 6; ++f) acc[f] += (px[f] - from_left(px[f])) + (py[f] - s.p[f][rowm][lane]);
+        }
+    }
+
+    __device__ __forceinline__ void run() const
+    {
+        Plane3<T> P0, P1, P2, P3;
+        T G0[18], G1[18], acc[6];
+#pragma unroll
+        for (int k = 0; k < 18; ++k) G0[k] = G1[k] = T(0);
+#pragma unroll
+        for (int f = 0; f < 6; ++f) acc[f] = T(0);
+        const int qs = z0 - 1;
+        load(qs - 1, P0);
+        load(qs, P1);
+        load(qs + 1, P2);
+        const int n = z1 - z0 + 2;   // central planes z0-1 .. z1
+        for (int i = 0; i < n; i += 4) {
+            step(qs + i, P0, P1, P2, P3, G1, G0, acc);
+            if (i + 1 >= n) break;
+            step(qs + i + 1, P1, P2, P3, P0, G0, G1, acc);
+            if (i + 2 >= n) break;
+            step(qs + i + 2, P2, P3, P0, P1, G1, G0, acc);
+            if (i + 3 >= n) break;
+            step(qs + i + 3, P3, P0, P1, P2, G0, G1, acc);
+        }
+    }
+};
+
+template <typename T, bool HAS_EPS, bool HAS_MU>
+__global__ __launch_bounds__(WAVE * rows3d<T>()) void cart3d_step_kernel(Cart3DArgs<T> a)
+{
+    constexpr int R = rows3d<T>();
+    __shared__ Lds3<T> lds;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int row = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    int t = xcd_logical_block();
+    const int tx = t % a.ntx;
+    t /= a.ntx;
+    const int ty = t % a.nty;
+    t /= a.nty;
+    const int tz = t % a.ntz;
+    const int b = t / a.ntz;
+
+    const int64_t ncell = (int64_t)a.nx * a.ny * a.nz;
+    const uint32_t fbytes = (uint32_t)(ncell * (int64_t)sizeof(T));
+    const uint32_t pbytes = (uint32_t)((int64_t)a.nx * a.ny * (int64_t)sizeof(T));
+    const Rsrc rU = make_rsrc(a.U + (int64_t)b * 6 * ncell, 6ull * fbytes);
+    const Rsrc rO = make_rsrc(a.Unew + (int64_t)b * 6 * ncell, 6ull * fbytes);
+    const Rsrc rE = make_rsrc(a.epsinv ? a.epsinv + (int64_t)b * ncell : a.U, fbytes);
+    const Rsrc rM = make_rsrc(a.muinv ? a.muinv + (int64_t)b * ncell : a.U, fbytes);
+
+    const int x0 = tx * OUT_X3 - 2, y0 = ty * (R - 4) - 2;
+    const int x = x0 + lane, y = y0 + row;
+    const int z0 = tz * a.tile_z, z1 = min(z0 + a.tile_z, a.nz);
+    bool mx, nrx, my, nry, mx1, nrx1, my1, nry1;
+    const int sx = map_axis(x, a.nx, a.bc[0], a.bc[1], mx, nrx);
+    const int sy = map_axis(y, a.ny, a.bc[2], a.bc[3], my, nry);
+    map_axis(x + 1, a.nx, a.bc[0], a.bc[1], mx1, nrx1);
+    map_axis(y + 1, a.ny, a.bc[2], a.bc[3], my1, nry1);
+    const bool bxy = x0 < 0 || x0 + WAVE > a.nx || y0 < 0 || y0 + R > a.ny;   // uniform
+
+    auto go = [&](auto bnd) {
+        constexpr bool BXY = decltype(bnd)::value;
+        March3D<T, HAS_EPS, HAS_MU, BXY> m{a, lds, rU, rE, rM, rO, fbytes, pbytes};
+        m.vcol = (uint32_t)((int64_t)sy * a.nx + sx) * (uint32_t)sizeof(T);
+        m.sgn = (mx ? ODD_X : 0u) ^ (my ? ODD_Y : 0u);
+        m.nr_c = nrx || nry;
+        m.nr_x = nrx1 || nry;
+        m.nr_y = nrx || nry1;
+        m.writer = lane >= 2 && lane < WAVE - 2 && row >= 2 && row < R - 2 && x < a.nx && y < a.ny;
+        m.lane = lane;
+        m.row = row;
+        m.rowp = min(row + 1, R - 1);
+        m.rowm = max(row - 1, 0);
+        m.z0 = z0;
+        m.z1 = z1;
+        m.need_g = row >= 1 && row <= R - 2;
+        m.need_yf = row >= 1 && row <= R - 3;
+        m.need_all = row >= 2 && row <= R - 3;
+        m.run();
+    };
+    if (bxy) go(std::integral_constant<bool, true>{});
+    else go(std::integral_constant<bool, false>{});
+}
+
+}  // namespace
+
+template <typename T>
+int launch_cart3d_step(const Cart3DArgs<T> &a, void *stream)
+{
+    const unsigned blocks = (unsigned)(a.ntx * a.nty * a.ntz * a.batch);
+    dim3 grid(blocks), block(WAVE * rows3d<T>());
+    hipStream_t s = (hipStream_t)stream;
+    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, true, true>), grid, block, 0, s, a);
+    else if (a.epsinv) hipLaunchKernelGGL((cart3d_step_kernel<T, true, false>), grid, block, 0, s, a);
+    else if (a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, false, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((cart3d_step_kernel<T, false, false>), grid, block, 0, s, a);
+    return (int)hipGetLastError();
+}
+
+template int launch_cart3d_step<float>(const Cart3DArgs<float> &, void *);
+template int launch_cart3d_step<double>(const Cart3DArgs<double> &, void *);
+
+int cart3d_tile_x(int) { return OUT_X3; }
+int cart3d_tile_y(int precision) { return precision == GKS_FP64 ? rows3d<double>() - 4 : rows3d<float>() - 4; }
+
+}  // namespace gks

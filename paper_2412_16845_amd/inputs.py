@@ -87,15 +87,19 @@ def circles_eps(x, y, rng, count, r_range, eps_range):
     return eps
 
 
-def boxes_eps(x, y, z, rng, count, side_range, eps_range):
-    """Background eps = 1 with `count` axis-aligned boxes inside the unit cube, painted in order."""
-    eps = np.ones_like(x)
+def boxes_eps(ax, ay, az, rng, count, side_range, eps_range):
+    """Background eps = 1 with `count` axis-aligned boxes inside the unit cube, painted in order
+    on the cells whose centre lies in the box.  ax, ay, az: 1D cell-centre coordinates; returns
+    an array of shape (len(az), len(ay), len(ax))."""
+    eps = np.ones((len(az), len(ay), len(ax)))
     for _ in range(count):
         s = rng.uniform(side_range[0], side_range[1], 3)
         a = rng.uniform(0.0, 1.0 - s)
         e = rng.uniform(eps_range[0], eps_range[1])
-        m = (x >= a[0]) & (x < a[0] + s[0]) & (y >= a[1]) & (y < a[1] + s[1]) & (z >= a[2]) & (z < a[2] + s[2])
-        eps[m] = e
+        ix = np.nonzero((ax >= a[0]) & (ax < a[0] + s[0]))[0]
+        iy = np.nonzero((ay >= a[1]) & (ay < a[1] + s[1]))[0]
+        iz = np.nonzero((az >= a[2]) & (az < a[2] + s[2]))[0]
+        eps[np.ix_(iz, iy, ix)] = e
     return eps
 
 
@@ -141,11 +145,12 @@ def em_blocks_pec(n=384, seed=0, nsteps=500, cfl=1.0 / 3.0, tau_over_dt=0.01, nb
     if not np.isscalar(n):
         nx, ny, nz = n
     rng = np.random.default_rng(seed)
-    x, y, z = centres_3d(nx, ny, nz)
-    eps = boxes_eps(x, y, z, rng, nboxes, (0.05, 0.25), (1.0, 6.0))
+    ax, ay, az = ((np.arange(m) + 0.5) / m for m in (nx, ny, nz))
+    eps = boxes_eps(ax, ay, az, rng, nboxes, (0.05, 0.25), (1.0, 6.0))
     xc, yc = rng.uniform(0.3, 0.7, 2)
+    x, y = np.meshgrid(ax, ay, indexing="xy")
     U = np.zeros((1, 6, nz, ny, nx))
-    U[0, 2] = np.exp(-((x - xc) ** 2 + (y - yc) ** 2) / (2 * w * w))
+    U[0, 2] = np.exp(-((x - xc) ** 2 + (y - yc) ** 2) / (2 * w * w))[None]
     bc = (NONREFLECT, NONREFLECT, NONREFLECT, NONREFLECT, PEC, PEC)
     return Workload("em_blocks_pec", "cart3d", (nx, ny, nz), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), bc, U,
                     (1.0 / eps)[None], None, cfl, tau_over_dt, nsteps)

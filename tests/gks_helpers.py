@@ -89,3 +89,36 @@ def window_check_2d(wl, U_start, U_end, nsteps, dt, t0, centres, half=None, b=0)
         orc_vals.append(ref[:, ly:hy, lx:hx].ravel())
         gpu_vals.append(np.asarray(U_end[b][:, y0 + ly:y0 + hy, x0 + lx:x0 + hx], dtype=np.float64).ravel())
     return np.concatenate(gpu_vals), np.concatenate(orc_vals)
+
+
+def window_check_3d(wl, U_start, U_end, nsteps, dt, t0, centres, half=None, b=0):
+    """The 3D form of window_check_2d: centres (ix, iy, iz); returns (gpu, oracle) values on
+    the trusted cores of the windows."""
+    n = wl.n
+    margin = 2 * nsteps + 2
+    half = half or margin + 4
+    bc = [BCODE[v] for v in wl.bc]
+    gpu_vals, orc_vals = [], []
+    for c in centres:
+        lo = [max(c[d] - half, 0) for d in range(3)]
+        hi = [min(c[d] + half, n[d]) for d in range(3)]
+        mesh = O.cart_window(tuple(n), tuple(wl.lo), tuple(wl.hi), bc, tuple(lo), tuple(hi), 3)
+        sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+        sub = np.asarray(U_start[b][(slice(None),) + sl], dtype=np.float64)
+        U = O.from_soa(sub.reshape(6, -1), "em3d")
+        ei = None if wl.epsinv is None else np.ascontiguousarray(wl.epsinv[b][sl], dtype=np.float64).reshape(-1)
+        mi = None if wl.muinv is None else np.ascontiguousarray(wl.muinv[b][sl], dtype=np.float64).reshape(-1)
+        out = O.run(mesh, U, nsteps, dt, wl.tau_over_dt * dt, epsinv=ei, muinv=mi, t0=t0)
+        m = [hi[d] - lo[d] for d in range(3)]
+        ref = O.to_soa(out, "em3d").reshape(6, m[2], m[1], m[0])
+        core = []
+        for d in range(3):
+            a = 0 if lo[d] == 0 else margin
+            z = m[d] if hi[d] == n[d] else m[d] - margin
+            assert z > a, "window too small for the step count"
+            core.append((a, z))
+        cs = (slice(None), slice(*core[2]), slice(*core[1]), slice(*core[0]))
+        gs = (slice(None),) + tuple(slice(lo[d] + core[d][0], lo[d] + core[d][1]) for d in (2, 1, 0))
+        orc_vals.append(ref[cs].ravel())
+        gpu_vals.append(np.asarray(U_end[b][gs], dtype=np.float64).ravel())
+    return np.concatenate(gpu_vals), np.concatenate(orc_vals)
