@@ -1,6 +1,6 @@
 """Benchmark of the GKS step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-adjoint]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-adjoint] [--no-3d]
 
 Workload: 2D TM fields on a 4096 x 4096 Cartesian grid of the unit square, kinetic
 non-reflecting sides, eps map of 64 seeded circular inclusions (eps in [1, 4]), Gaussian point
@@ -16,6 +16,7 @@ One JSON line on stdout:
                  launch) against the 8 TB/s peak; traffic = HBM bytes per launch from the
                  committed rocprofv3 counter summary (null when the kernel source changed since)
   cpu_baseline   the FP64 oracle on the host cores, on a bounded sample of the same workload
+  cart3d         the 3D six-field 384^3 workload (FP32 and FP64): throughput and roofline
   adjoint        forward + adjoint step time of the differentiable workload (1024^2 x 8 maps,
                  800 steps, checkpoints every 50) beside the plain FP64 and FP32 steps of the
                  same grids, and the adjoint step's own per-launch time
@@ -242,6 +243,53 @@ def adjoint_leg(torch):
                                  "algorithmic_bytes_per_launch": alg}}
 
 
+C3_N, C3_STEPS = 384, 500
+# 3D step, algorithmic bytes per cell-update: read six fields and 1/eps, write six fields
+C3_BYTES_PER_CELL = {"fp32": 13 * 4, "fp64": 13 * 8}
+# arithmetic per 3D cell-update: two flops per multiply-add of the three face operators a cell
+# owns (80 + 12 + 12 structural non-zeros each), 18 differences and the six-field update
+C3_FLOPS_PER_CELL = 2 * 3 * (80 + 24) + 18 + 6 * 4
+
+
+def cart3d_leg(torch):
+    """The 3D six-field workload: 384^3, dielectric blocks, PEC z walls, non-reflecting x/y
+    sides, nu = 1/3, 500 steps (the whole job timed, and each launch with events)."""
+    from paper_2412_16845_amd import inputs as I
+    from paper_2412_16845_amd.gks import Solver
+    wl = I.em_blocks_pec(n=C3_N, seed=0, nsteps=C3_STEPS)
+    ncell = C3_N ** 3
+    out = {"workload": f"em_blocks_pec: 3D six-field {C3_N}^3, 32 dielectric blocks (eps in [1,6]), PEC z walls, "
+                       f"non-reflecting x/y sides, CFL 1/3, tau = 0.01 dt, {C3_STEPS} steps"}
+    for prec in ("fp32", "fp64"):
+        dtype = torch.float64 if prec == "fp64" else torch.float32
+        s = Solver("cart3d", n=wl.n, bc=wl.bc, precision=prec, cfl=wl.cfl, tau_over_dt=wl.tau_over_dt)
+        E = torch.tensor(wl.epsinv, dtype=dtype, device="cuda")
+        s.set_material(E)
+        U = torch.tensor(wl.U0, dtype=dtype, device="cuda")
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s.stream)
+        s.run(U, C3_STEPS)
+        b.record(s.stream)
+        torch.cuda.synchronize()
+        t_run = a.elapsed_time(b) / 1e3
+        if not torch.isfinite(U).all():
+            raise RuntimeError(f"3D {prec} run produced non-finite values")
+        t_launch, _ = time_kernel(torch, s, U, launches=30)
+        alg = C3_BYTES_PER_CELL[prec] * ncell
+        out[prec] = {"value": round(ncell * C3_STEPS / t_run, 1), "unit": "cell-updates/s",
+                     "ms_per_step": round(t_run * 1e3 / C3_STEPS, 4),
+                     "roofline": {"bound": "hbm", "achieved": round(alg / t_launch / 1e9, 1), "peak": PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(alg / t_launch / 1e9 / PEAK_GBS, 4),
+                                  "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch},
+                     "vector_alu": {"flops_per_cell": C3_FLOPS_PER_CELL,
+                                    "achieved_tflops": round(C3_FLOPS_PER_CELL * ncell / t_launch / 1e12, 2),
+                                    "peak_tflops_non_packed": 78.6}}
+        del s, E, U
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +297,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--profile-kernel", choices=["fp32", "fp64"])
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -317,6 +366,9 @@ def main():
                  "ms_per_step": round(f64["seconds"] * 1e3 / args.steps, 5), "dtype": "f64",
                  "roofline": roofline("fp64", f64["t_launch"])},
     }
+    if not args.no_3d:
+        log("[bench] 3D: 384^3 six fields, 500 steps, fp32 and fp64")
+        out["cart3d"] = cart3d_leg(torch)
     if not args.no_adjoint:
         log("[bench] adjoint: 1024x1024 x 8, 800 steps forward + reverse with checkpoints every 50")
         out["adjoint"] = adjoint_leg(torch)
