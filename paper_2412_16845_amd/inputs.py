@@ -181,3 +181,159 @@ def random_smooth_tm(nx, ny, seed, modes=4, batch=1):
                 kx, ky = rng.integers(-3, 4, size=2)
                 U[b, f] += rng.normal() * np.cos(2 * np.pi * (kx * x + ky * y) + rng.uniform(0, 2 * np.pi))
     return U
+
+
+# ----------------------------------------------------------------------------- triangle meshes
+def _hilbert_index(x, y, order=16):
+    """Index along a Hilbert curve of points in [0, 1)^2 (order bits per axis), vectorised."""
+    n = 1 << order
+    xi = np.clip((x * n).astype(np.int64), 0, n - 1)
+    yi = np.clip((y * n).astype(np.int64), 0, n - 1)
+    d = np.zeros_like(xi)
+    s = n >> 1
+    while s > 0:
+        rx = ((xi & s) > 0).astype(np.int64)
+        ry = ((yi & s) > 0).astype(np.int64)
+        d += s * s * ((3 * rx) ^ ry)
+        # rotate the quadrant
+        flip = ry == 0
+        swap_x = flip & (rx == 1)
+        xi = np.where(swap_x, s - 1 - xi, xi)
+        yi = np.where(swap_x, s - 1 - yi, yi)
+        xi, yi = np.where(flip, yi, xi), np.where(flip, xi, yi)
+        s >>= 1
+    return d
+
+
+def _ellipse_points(centre, axes, h):
+    """Points on the ellipse at arc-length spacing close to h (counter-clockwise)."""
+    t = np.linspace(0.0, 2 * np.pi, 20001)
+    x = centre[0] + axes[0] * np.cos(t)
+    y = centre[1] + axes[1] * np.sin(t)
+    s = np.concatenate([[0.0], np.cumsum(np.hypot(np.diff(x), np.diff(y)))])
+    m = max(8, int(round(s[-1] / h)))
+    tt = np.interp(np.arange(m) * s[-1] / m, s, t)
+    return np.stack([centre[0] + axes[0] * np.cos(tt), centre[1] + axes[1] * np.sin(tt)], axis=1)
+
+
+def tri_ellipse_mesh(h, seed=0, centre=(0.5, 0.5), axes=(0.2, 0.1), cache=True):
+    """Cached form of _tri_ellipse_mesh (see there): large meshes take tens of seconds to
+    triangulate, so they are kept in the temporary directory (or GKS_MESH_CACHE), keyed by the
+    arguments and by this module's source."""
+    import hashlib
+    import os
+    import tempfile
+    if not cache:
+        return _tri_ellipse_mesh(h, seed, centre, axes)
+    with open(__file__, "rb") as f:
+        tag = hashlib.sha256(f.read() + repr((h, seed, centre, axes)).encode()).hexdigest()[:20]
+    d = os.environ.get("GKS_MESH_CACHE") or tempfile.gettempdir()
+    path = os.path.join(d, f"gks_tri_{tag}.npz")
+    if os.path.exists(path):
+        with np.load(path, allow_pickle=False) as z:
+            return z["verts"], z["tris"], z["face_cells"], z["face_verts"]
+    out = _tri_ellipse_mesh(h, seed, centre, axes)
+    try:
+        tmp = path + f".{os.getpid()}.npz"
+        np.savez(tmp, verts=out[0], tris=out[1], face_cells=out[2], face_verts=out[3])
+        os.replace(tmp, path)
+    except OSError:
+        pass
+    return out
+
+
+def _tri_ellipse_mesh(h, seed=0, centre=(0.5, 0.5), axes=(0.2, 0.1)):
+    """Triangle mesh of the unit square minus an elliptical hole.
+
+    Jittered lattice (spacing h, jitter U[-h/4, h/4]^2) without the points closer than h/2 to
+    the square's sides or to the ellipse (or inside it), plus boundary points at spacing h on
+    the square and the ellipse; Delaunay triangulation; triangles whose centroid lies inside the
+    ellipse dropped; cells in Hilbert order of their centroids.  Edges on the square are
+    non-reflecting, edges on the ellipse PEC.
+    Returns (verts (nv, 2), tris (nc, 3), face_cells (nf, 2), face_verts (nf, 2)) with
+    face_cells[s] = (owner, neighbour or -(1 + bc))."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(seed)
+    n = int(round(1.0 / h))
+    hh = 1.0 / n
+    g = (np.arange(n) + 0.5) * hh
+    X, Y = np.meshgrid(g, g, indexing="xy")
+    P = np.stack([X.ravel(), Y.ravel()], axis=1) + rng.uniform(-0.25 * hh, 0.25 * hh, (n * n, 2))
+    # exclusion bands
+    keep = (P[:, 0] > 0.5 * hh) & (P[:, 0] < 1 - 0.5 * hh) & (P[:, 1] > 0.5 * hh) & (P[:, 1] < 1 - 0.5 * hh)
+    E = _ellipse_points(centre, axes, hh)
+    # distance to the ellipse, approximated by the distance to its dense polygon
+    from scipy.spatial import cKDTree
+    dense = _ellipse_points(centre, axes, hh / 16)
+    dist, _ = cKDTree(dense).query(P, distance_upper_bound=0.5 * hh, workers=-1)
+    inside = ((P[:, 0] - centre[0]) / axes[0]) ** 2 + ((P[:, 1] - centre[1]) / axes[1]) ** 2 < 1.0
+    keep &= (dist > 0.5 * hh) & ~inside
+    P = P[keep]
+    side = np.arange(n + 1) * hh
+    B = np.concatenate([np.stack([side, np.zeros_like(side)], 1), np.stack([side, np.ones_like(side)], 1),
+                        np.stack([np.zeros_like(side[1:-1]), side[1:-1]], 1),
+                        np.stack([np.ones_like(side[1:-1]), side[1:-1]], 1)])
+    verts = np.concatenate([B, E, P])
+    ne0 = B.shape[0]
+    tri = Delaunay(verts).simplices.astype(np.int64)
+    cen = verts[tri].mean(axis=1)
+    inside = ((cen[:, 0] - centre[0]) / axes[0]) ** 2 + ((cen[:, 1] - centre[1]) / axes[1]) ** 2 < 1.0
+    tri = tri[~inside]
+    # counter-clockwise orientation
+    a, b, c = verts[tri[:, 0]], verts[tri[:, 1]], verts[tri[:, 2]]
+    cw = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0]) < 0
+    tri[cw] = tri[cw][:, [0, 2, 1]]
+    # Hilbert order of the cells
+    cen = verts[tri].mean(axis=1)
+    tri = tri[np.argsort(_hilbert_index(cen[:, 0], cen[:, 1]), kind="stable")]
+    # unique edges and their cells
+    nc = tri.shape[0]
+    e = np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]])
+    cell = np.tile(np.arange(nc), 3)
+    e.sort(axis=1)
+    key = e[:, 0] * verts.shape[0] + e[:, 1]
+    order = np.argsort(key, kind="stable")
+    key, cell, e = key[order], cell[order], e[order]
+    first = np.concatenate([[True], key[1:] != key[:-1]])
+    starts = np.nonzero(first)[0]
+    counts = np.diff(np.concatenate([starts, [key.shape[0]]]))
+    assert counts.max() <= 2, "an edge is shared by more than two triangles"
+    face_verts = e[starts]
+    owner = cell[starts]
+    nb = np.where(counts == 2, cell[np.minimum(starts + 1, key.shape[0] - 1)], -1)
+    # boundary edges: on the ellipse (both ends ellipse points) PEC, otherwise non-reflecting
+    on_e = (face_verts >= ne0) & (face_verts < ne0 + E.shape[0])
+    bnd = nb < 0
+    pec = bnd & on_e.all(axis=1)
+    nb = np.where(pec, -(1 + 2), np.where(bnd, -(1 + 1), nb))
+    # every ellipse polygon edge is a mesh edge (the hole is resolved exactly by the mesh)
+    m = E.shape[0]
+    ring = np.stack([ne0 + np.arange(m), ne0 + (np.arange(m) + 1) % m], 1)
+    ring.sort(axis=1)
+    have = set((face_verts[pec, 0] * verts.shape[0] + face_verts[pec, 1]).tolist())
+    assert all(int(r0) * verts.shape[0] + int(r1) in have for r0, r1 in ring), "ellipse edge missing from the mesh"
+    face_cells = np.stack([owner, nb], axis=1)
+    return verts, tri, face_cells, face_verts
+
+
+def tri_ellipse_workload(h=6.8e-4, seed=0, nsteps=2000, cfl=0.5, tau_over_dt=0.01, w=0.05, eps_discs=0,
+                         batch=1) -> Workload:
+    """2D TM on the square with an elliptical PEC hole (non-reflecting outer square): Ez
+    Gaussian (w = 0.05) centred at a seeded point at least 0.15 from the ellipse, H = 0.
+    eps_discs > 0 adds that many dielectric discs (radii [0.02, 0.06], eps [1, 4])."""
+    verts, tri, fc, fv = tri_ellipse_mesh(h, seed)
+    rng = np.random.default_rng(seed + 1)
+    cen = verts[tri].mean(axis=1)
+    while True:
+        xc, yc = rng.uniform(0.15, 0.85, 2)
+        if ((xc - 0.5) / 0.35) ** 2 + ((yc - 0.5) / 0.25) ** 2 > 1.0:
+            break
+    U = np.zeros((batch, 3, tri.shape[0]))
+    U[:, 0] = gaussian(cen[:, 0], cen[:, 1], xc, yc, w)[None]
+    epsinv = None
+    if eps_discs:
+        eps = circles_eps(cen[:, 0], cen[:, 1], rng, eps_discs, (0.02, 0.06), (1.0, 4.0))
+        epsinv = np.repeat((1.0 / eps)[None], batch, axis=0)
+    return Workload("tri_ellipse", "tri2d", (tri.shape[0],), (0.0, 0.0), (1.0, 1.0), (NONREFLECT, PEC), U, epsinv,
+                    None, cfl, tau_over_dt, nsteps,
+                    extra={"verts": verts, "tris": tri, "face_cells": fc, "face_verts": fv, "centre": (xc, yc)})
