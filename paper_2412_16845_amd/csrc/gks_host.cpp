@@ -60,6 +60,12 @@ struct gks_ctx {
     void *adj_scratch = nullptr;    // adjoint: padded face adjoints, ghost co-states, ghost material gradients
     size_t adj_scratch_bytes = 0;
 
+    // triangle meshes: per cell-face neighbours and geometry, cell areas, gradient scratch
+    int32_t *d_tri_nb = nullptr;
+    void *d_tri_geo = nullptr;
+    double *d_area = nullptr;
+    void *d_grad = nullptr;
+
     std::string err;
 };
 
@@ -115,7 +121,11 @@ void fill_op(FaceOp<T, N0, NE, NH> &o, const double *k0, const double *ke, const
 template <typename T>
 void pack_ops(const gks_ctx *x, std::vector<char> &buf)
 {
-    if (x->model == GKS_TM2D) {
+    if (x->kind == GKS_TRI2D) {
+        std::vector<FaceOpTM<T>> ops(1);
+        fill_op(ops[0], x->k0[0], x->ke[0], x->kh[0]);
+        buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
+    } else if (x->model == GKS_TM2D) {
         std::vector<FaceOpTM<T>> ops(2);
         for (int ax = 0; ax < 2; ++ax) fill_op(ops[ax], x->k0[ax], x->ke[ax], x->kh[ax]);
         buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
@@ -250,8 +260,55 @@ gks_status step_cart3d(gks_ctx *x, const void *Uin, void *Uout, double tn)
     return GKS_OK;
 }
 
+template <typename T>
+gks_status step_tri(gks_ctx *x, const void *Uin, void *Uout, double tn)
+{
+    TriArgs<T> a;
+    std::memset(&a, 0, sizeof a);
+    a.U = (const T *)Uin;
+    a.Unew = (T *)Uout;
+    a.epsinv = (const T *)x->epsinv;
+    a.muinv = (const T *)x->muinv;
+    a.grad = (T *)x->d_grad;
+    a.ncell = (int32_t)x->ncell;
+    a.batch = (int32_t)x->batch;
+    a.nb = x->d_tri_nb;
+    a.geo = (const T *)x->d_tri_geo;
+    a.op = (const FaceOpTM<T> *)x->d_ops;
+    int e = launch_tri_step<T>(a, x->stream);
+    if (e) return hip_fail(x, e, "triangle step launch");
+    const int64_t ns = (int64_t)x->src_cells.size();
+    if (ns > 0) {
+        const double amp = -x->dt * source_pulse(x, tn);
+        e = launch_source_scatter<T>((T *)Uout, (const T *)x->epsinv, x->ncell, (int64_t)x->nfields * x->ncell,
+                                     (int32_t)x->batch, 0, x->d_src_cells, x->d_src_w, amp, (int32_t)ns, x->stream);
+        if (e) return hip_fail(x, e, "source launch");
+    }
+    return GKS_OK;
+}
+
+template <typename T>
+gks_status upload_tri(gks_ctx *x, const TriGeometry &g)
+{
+    const size_t nc = (size_t)g.ncell;
+    std::vector<T> geo(g.geo.size());
+    for (size_t q = 0; q < geo.size(); ++q) geo[q] = (T)g.geo[q];
+    if (hipMalloc((void **)&x->d_tri_nb, 3 * nc * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&x->d_tri_geo, geo.size() * sizeof(T)) != hipSuccess ||
+        hipMalloc((void **)&x->d_area, nc * sizeof(double)) != hipSuccess ||
+        hipMalloc(&x->d_grad, (size_t)x->batch * 6 * nc * sizeof(T)) != hipSuccess)
+        return fail(x, GKS_ENOMEM, "cannot allocate the triangle mesh arrays");
+    int e = hipMemcpy(x->d_tri_nb, g.nb.data(), 3 * nc * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (!e) e = hipMemcpy(x->d_tri_geo, geo.data(), geo.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (!e) e = hipMemcpy(x->d_area, g.area.data(), nc * sizeof(double), hipMemcpyHostToDevice);
+    if (e) return hip_fail(x, e, "triangle mesh upload");
+    return GKS_OK;
+}
+
 gks_status do_step(gks_ctx *x, const void *Uin, void *Uout, double tn)
 {
+    if (x->kind == GKS_TRI2D)
+        return x->prec == GKS_FP64 ? step_tri<double>(x, Uin, Uout, tn) : step_tri<float>(x, Uin, Uout, tn);
     if (x->kind == GKS_CART2D)
         return x->prec == GKS_FP64 ? step_cart2d<double>(x, Uin, Uout, tn) : step_cart2d<float>(x, Uin, Uout, tn);
     if (x->kind == GKS_CART3D)
@@ -327,13 +384,14 @@ gks_status ensure_out(gks_ctx *x, size_t count)
 gks_status launch_energy_into(gks_ctx *x, const void *U, double *dst)
 {
     const double vol = x->h[0] * x->h[1] * (x->kind == GKS_CART3D ? x->h[2] : 1.0);
+    const double *cell_vol = (x->kind == GKS_TRI2D) ? x->d_area : nullptr;
     int e;
     if (x->prec == GKS_FP64)
         e = launch_energy<double>((const double *)U, (const double *)x->epsinv, (const double *)x->muinv, x->ncell,
-                                  x->nfields, (int32_t)x->batch, nullptr, vol, x->d_partial, x->nblk, dst, x->stream);
+                                  x->nfields, (int32_t)x->batch, cell_vol, vol, x->d_partial, x->nblk, dst, x->stream);
     else
         e = launch_energy<float>((const float *)U, (const float *)x->epsinv, (const float *)x->muinv, x->ncell,
-                                 x->nfields, (int32_t)x->batch, nullptr, vol, x->d_partial, x->nblk, dst, x->stream);
+                                 x->nfields, (int32_t)x->batch, cell_vol, vol, x->d_partial, x->nblk, dst, x->stream);
     if (e) return hip_fail(x, e, "energy launch");
     return GKS_OK;
 }
@@ -371,6 +429,7 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
     if (p->energy_every < 0) return fail(nullptr, GKS_EINVAL, "energy_every must be >= 0");
     if (!(p->unstable_growth >= 0)) return fail(nullptr, GKS_EINVAL, "unstable_growth must be >= 0");
 
+    TriGeometry tri;
     gks_ctx *x = new (std::nothrow) gks_ctx();
     if (!x) return fail(nullptr, GKS_ENOMEM, "cannot allocate the context");
     x->kind = m->kind;
@@ -425,7 +484,20 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
         if (nu > 0.5 * (1 + 1e-12))
             return bail(fail(x, GKS_EINVAL, "Courant number c dt / h = %g exceeds the stability limit 0.5", nu));
     } else if (m->kind == GKS_TRI2D) {
-        return bail(fail(x, GKS_ESTATE, "triangle meshes are not available in this build"));
+        if (m->model != GKS_TM2D) return bail(fail(x, GKS_EINVAL, "triangle meshes carry TM2D fields"));
+        char err[256];
+        if (!build_tri_geometry(m, tri, err, sizeof err)) return bail(fail(x, GKS_EINVAL, "%s", err));
+        x->ncell = m->ncells;
+        x->n[0] = m->ncells;
+        x->nfields = 3;
+        if ((int64_t)3 * x->ncell * ((m->precision == GKS_FP64) ? 8 : 4) > (int64_t)0xFFFFFFFF)
+            return bail(fail(x, GKS_EINVAL, "mesh too large: one batch item's fields exceed 4 GiB"));
+        // the step is stable for c dt <= 0.5 x (smallest inradius 2|Omega|/perimeter)
+        x->dt = (p->dt > 0) ? p->dt : p->cfl * tri.rmin / p->c;
+        if (!(x->dt > 0) || !std::isfinite(x->dt)) return bail(fail(x, GKS_EINVAL, "dt must be positive (set dt or cfl)"));
+        const double nu = p->c * x->dt / tri.rmin;
+        if (nu > 0.5 * (1 + 1e-12))
+            return bail(fail(x, GKS_EINVAL, "c dt / (smallest inradius) = %g exceeds 0.5", nu));
     } else {
         return bail(fail(x, GKS_EINVAL, "bad mesh kind %d", m->kind));
     }
@@ -435,6 +507,9 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
 
     // face operators: local frames of the x-, y- (and z-) faces
     char err[256];
+    if (x->kind == GKS_TRI2D &&
+        !tri_face_operator(x->c, x->C, x->k0[0], x->ke[0], x->kh[0], err, sizeof err))
+        return bail(fail(x, GKS_EINVAL, "%s", err));
     if (x->kind == GKS_CART2D || x->kind == GKS_CART3D) {
         // the kernels feed full central differences U(i+1) - U(i-1) = 2 h dU/dx
         const int nax = (x->kind == GKS_CART2D) ? 2 : 3;
@@ -454,6 +529,10 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
         x->tile_y = cart2d_pick_tile_y((int)x->n[0], (int)x->n[1], (int)x->batch, x->ncu, x->prec);
     if (x->kind == GKS_CART3D)
         x->tile_z = cart3d_pick_tile_z((int)x->n[0], (int)x->n[1], (int)x->n[2], (int)x->batch, x->ncu, x->prec);
+    if (x->kind == GKS_TRI2D) {
+        gks_status st = (x->prec == GKS_FP64) ? upload_tri<double>(x, tri) : upload_tri<float>(x, tri);
+        if (st) return bail(st);
+    }
     {
         gks_status st = upload_ops(x);
         if (st) return bail(st);
@@ -476,6 +555,10 @@ extern "C" gks_status gks_destroy(gks_ctx *ctx)
     if (ctx->d_src_cells) hipFree(ctx->d_src_cells);
     if (ctx->d_src_w) hipFree(ctx->d_src_w);
     if (ctx->adj_scratch) hipFree(ctx->adj_scratch);
+    if (ctx->d_tri_nb) hipFree(ctx->d_tri_nb);
+    if (ctx->d_tri_geo) hipFree(ctx->d_tri_geo);
+    if (ctx->d_area) hipFree(ctx->d_area);
+    if (ctx->d_grad) hipFree(ctx->d_grad);
     delete ctx;
     return GKS_OK;
 }

@@ -3,6 +3,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/gks.h"
 
@@ -72,6 +73,34 @@ struct Cart3DArgs {
     int32_t tile_z;          // planes per z tile
     const FaceOpEM<T> *ops;  // device: x-, y- and z-face operators
 };
+
+// Triangle meshes: per cell and face slot (three per cell) the neighbour (or -(1 + bc) on a
+// boundary face) and TRI_GEO geometry attributes [nx ny lw ax ay bx by] (outward unit normal,
+// |l|/|Omega|, midpoint minus own centroid, midpoint minus neighbour centroid), each stored as
+// [attribute][slot][cell].
+constexpr int TRI_GEO = 7;
+struct TriGeometry {
+    int64_t ncell = 0;
+    std::vector<int32_t> nb;     // [3][ncell]
+    std::vector<double> geo;     // [TRI_GEO][3][ncell]
+    std::vector<double> area;    // [ncell]
+    double rmin = 0;             // smallest inradius 2|Omega| / perimeter
+};
+bool build_tri_geometry(const gks_mesh_desc *m, TriGeometry &g, char *err, size_t errlen);
+
+template <typename T>
+struct TriArgs {
+    const T *U;
+    T *Unew;
+    const T *epsinv;      // nullable: vacuum
+    const T *muinv;       // nullable: vacuum
+    T *grad;              // scratch [batch][6][ncell]: d/dx (Ez Hx Hy), d/dy (Ez Hx Hy)
+    int32_t ncell, batch;
+    const int32_t *nb;    // device [3][ncell]
+    const T *geo;         // device [TRI_GEO][3][ncell]
+    const FaceOpTM<T> *op;   // device: the face operator (face-frame inputs, PatTri)
+};
+template <typename T> int launch_tri_step(const TriArgs<T> &a, void *stream);
 
 // Arguments of the Cartesian 2D TM adjoint kernels.
 template <typename T>

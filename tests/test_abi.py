@@ -94,3 +94,38 @@ def test_null_arguments(gks):
     assert L.gks_step(None, None, None, 0.0) == -1
     out = (ctypes.c_double * 5)()
     assert L.gks_flux_coefficients(-1.0, 0.0, out) == -1
+
+
+def _tri_init(gks, verts, tris, fc, fv, cfl=0.5):
+    d = gks.MeshDesc()
+    d.kind, d.model, d.precision, d.batch = 2, 0, 0, 1
+    arrs = [np.ascontiguousarray(verts, dtype=np.float64), np.ascontiguousarray(tris, dtype=np.int32),
+            np.ascontiguousarray(fc, dtype=np.int32), np.ascontiguousarray(fv, dtype=np.int32)]
+    d.nverts, d.ncells, d.nfaces = arrs[0].shape[0], arrs[1].shape[0], arrs[2].shape[0]
+    d.vert_xy, d.cell_verts, d.face_cells, d.face_verts = (a.ctypes.data for a in arrs)
+    p = gks.Params(1.0, cfl, 0.0, 0.01, 0, 0.0)
+    h = ctypes.c_void_p()
+    st = gks.lib().gks_init_mesh(ctypes.byref(d), ctypes.byref(p), None, ctypes.byref(h))
+    msg = gks.lib().gks_last_error(None).decode()
+    if h.value:
+        gks.lib().gks_destroy(h)
+    return st, msg
+
+
+def test_triangle_topology_is_checked(gks):
+    """Triangle meshes are validated on the host before any device work."""
+    from tests.test_oracle_tri import square_tri_mesh
+    verts, tris, fc, fv = square_tri_mesh(4)
+    cases = []
+    bad = fc.copy(); bad[0, 1] = -1; cases.append((bad, fv, "neighbour"))            # periodic code
+    bad = fc.copy(); bad[3, 0] = tris.shape[0]; cases.append((bad, fv, "owner"))     # owner out of range
+    cases.append((fc[1:], fv[1:], "faces (a triangle has 3)"))                         # a cell with two faces
+    badv = fv.copy(); badv[5] = badv[6]; cases.append((fc, badv, "not an edge"))      # wrong edge
+    for f, v, needle in cases:
+        st, msg = _tri_init(gks, verts, tris, f, v)
+        assert st == -1 and needle in msg, (st, msg)
+    st, msg = _tri_init(gks, verts, tris, fc, fv, cfl=0.6)
+    assert st == -1 and "exceeds 0.5" in msg
+    # a valid mesh passes the host checks (and then needs a device)
+    st, msg = _tri_init(gks, verts, tris, fc, fv)
+    assert st in (0, -3), (st, msg)
