@@ -58,7 +58,9 @@ typedef enum { GKS_FP64 = 0, GKS_FP32 = 1 } gks_precision;
  *   Triangles (GKS_TRI2D with GKS_TM2D): nverts vertices vert_xy[2*v], ncells triangles
  *   cell_verts[3*c], nfaces edges face_cells[2*s] = (owner, neighbour) with neighbour < 0
  *   meaning a boundary edge of type -(1 + gks_bc) (non-reflecting or PEC), and
- *   face_verts[2*s] = the edge's two vertices.
+ *   face_verts[2*s] = the edge's two vertices.  Every cell must be a side of exactly three
+ *   faces, and a face's vertices an edge of its cells (checked: GKS_EINVAL).  Cells ordered
+ *   along a space-filling curve keep the neighbour reads of the kernels in cache.
  *   batch: number of independent problems sharing the mesh (fields and materials carry a
  *   leading batch axis).
  */
@@ -79,7 +81,10 @@ typedef struct {
  * Scheme parameters (host memory, copied).
  *   c:            lattice speed = speed of light (> 0).
  *   cfl, dt:      dt > 0 is used as given; otherwise dt = cfl * h / c with h the smallest
- *                 cell width (Cartesian) or the smallest 2|Omega|/perimeter (triangles).
+ *                 cell width (Cartesian) or the smallest inradius 2|Omega|/perimeter
+ *                 (triangles).  c dt / h above 0.5 is rejected (GKS_EINVAL): 0.5 is the
+ *                 scheme's stability limit in 2D.  3D grids are stable only up to 1/3 (the
+ *                 D3Q4 scheme grows at 1/2); that is left to the caller.
  *   tau_over_dt:  collision time tau = tau_over_dt * dt (>= 0; +INFINITY = collisionless).
  *   energy_every: gks_run records the energy every this many steps (0 = never).
  *   unstable_growth: gks_run fails with GKS_EUNSTABLE when a recorded energy exceeds this
@@ -139,8 +144,9 @@ gks_status gks_step(gks_ctx *ctx, const void *U_in, void *U_out, double t_n);
  * nsteps steps in place on U (device) starting at t0 (t^n = t0 + n dt), ping-ponging with a
  * library-owned buffer.  energy_host: NULL, or host memory for (nsteps / energy_every) x batch
  * doubles receiving W = 1/2 sum |Omega| (eps |E|^2 + mu |H|^2) after every energy_every-th
- * step; when given, a NaN/Inf energy returns GKS_ENONFINITE and growth beyond
- * unstable_growth returns GKS_EUNSTABLE (U then holds the state at that check).
+ * step; when given, the recorded energies are checked once all steps are done: a NaN/Inf
+ * energy returns GKS_ENONFINITE and growth beyond unstable_growth returns GKS_EUNSTABLE (U
+ * holds the state after the last step either way).
  */
 gks_status gks_run(gks_ctx *ctx, void *U, int64_t nsteps, double t0, double *energy_host);
 
