@@ -1,6 +1,6 @@
 """Benchmark of the GKS step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-adjoint] [--no-3d]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-adjoint] [--no-3d] [--no-tri]
 
 Workload: 2D TM fields on a 4096 x 4096 Cartesian grid of the unit square, kinetic
 non-reflecting sides, eps map of 64 seeded circular inclusions (eps in [1, 4]), Gaussian point
@@ -17,6 +17,7 @@ One JSON line on stdout:
                  committed rocprofv3 counter summary (null when the kernel source changed since)
   cpu_baseline   the FP64 oracle on the host cores, on a bounded sample of the same workload
   cart3d         the 3D six-field 384^3 workload (FP32 and FP64): throughput and roofline
+  tri2d          the ~4M-triangle workload (FP32 and FP64): throughput and roofline
   adjoint        forward + adjoint step time of the differentiable workload (1024^2 x 8 maps,
                  800 steps, checkpoints every 50) beside the plain FP64 and FP32 steps of the
                  same grids, and the adjoint step's own per-launch time
@@ -290,6 +291,57 @@ def cart3d_leg(torch):
     return out
 
 
+C4_H, C4_STEPS = 6.8e-4, 2000
+
+
+def tri_bytes_per_cell(prec):
+    """Compulsory bytes per cell-update of the triangle step with its stored geometry (vacuum):
+    gradient kernel: fields, 3 neighbour ids, 3 x (normal, |l|/|Omega|), write 6 gradients;
+    face/update kernel: fields, 6 gradients, 3 neighbour ids, 3 x 7 geometry values, write fields
+    (the neighbours' fields and gradients are gathered from cache)."""
+    e = 8 if prec == "fp64" else 4
+    grad = 3 * e + 3 * 4 + 9 * e + 6 * e
+    step = 3 * e + 6 * e + 3 * 4 + 21 * e + 3 * e
+    return grad + step
+
+
+def tri_leg(torch):
+    """The triangle workload: ~4.06M triangles (square with an elliptical PEC hole,
+    non-reflecting outer square), Gaussian pulse, 2000 steps, FP32 and FP64."""
+    from paper_2412_16845_amd import inputs as I
+    from paper_2412_16845_amd.gks import Solver
+    wl = I.tri_ellipse_workload(h=C4_H, seed=0, nsteps=C4_STEPS)
+    ex = wl.extra
+    mesh4 = (ex["verts"], ex["tris"], ex["face_cells"], ex["face_verts"])
+    ncell = mesh4[1].shape[0]
+    out = {"workload": f"tri_ellipse: 2D TM on {ncell} triangles (jittered-lattice Delaunay mesh, h = {C4_H}, of the "
+                       f"unit square minus an elliptical PEC hole; non-reflecting outer square), Gaussian pulse, "
+                       f"CFL 0.5 on the smallest inradius, tau = 0.01 dt, {C4_STEPS} steps", "cells": ncell}
+    for prec in ("fp32", "fp64"):
+        dtype = torch.float64 if prec == "fp64" else torch.float32
+        s = Solver("tri2d", tri=mesh4, precision=prec, cfl=wl.cfl, tau_over_dt=wl.tau_over_dt)
+        U = torch.tensor(wl.U0, dtype=dtype, device="cuda")
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s.stream)
+        s.run(U, C4_STEPS)
+        b.record(s.stream)
+        torch.cuda.synchronize()
+        t_run = a.elapsed_time(b) / 1e3
+        if not torch.isfinite(U).all():
+            raise RuntimeError(f"triangle {prec} run produced non-finite values")
+        t_launch, _ = time_kernel(torch, s, U, launches=100)
+        alg = tri_bytes_per_cell(prec) * ncell
+        out[prec] = {"value": round(ncell * C4_STEPS / t_run, 1), "unit": "cell-updates/s",
+                     "ms_per_step": round(t_run * 1e3 / C4_STEPS, 5), "dt": s.dt,
+                     "roofline": {"bound": "hbm", "achieved": round(alg / t_launch / 1e9, 1), "peak": PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(alg / t_launch / 1e9 / PEAK_GBS, 4),
+                                  "algorithmic_bytes_per_launch": alg, "step_seconds_per_launch": t_launch}}
+        del s, U
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -298,6 +350,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-tri", action="store_true")
     ap.add_argument("--profile-kernel", choices=["fp32", "fp64"])
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -369,6 +422,9 @@ def main():
     if not args.no_3d:
         log("[bench] 3D: 384^3 six fields, 500 steps, fp32 and fp64")
         out["cart3d"] = cart3d_leg(torch)
+    if not args.no_tri:
+        log("[bench] triangles: ~4M cells, 2000 steps, fp32 and fp64")
+        out["tri2d"] = tri_leg(torch)
     if not args.no_adjoint:
         log("[bench] adjoint: 1024x1024 x 8, 800 steps forward + reverse with checkpoints every 50")
         out["adjoint"] = adjoint_leg(torch)
