@@ -172,6 +172,35 @@ __device__ __forceinline__ void apply_op(const T (&w)[NIN], T mE, T mH, Op K, T 
     }
 }
 
+// As apply_op, and also returns the material parts e = KE w and h = KH w (per output row; the
+// rows outside EROWS / HROWS are zero): phi = K0 w + mE e + mH h.
+template <typename P, typename T, int NF, int NIN, typename Op>
+__device__ __forceinline__ void apply_op_parts(const T (&w)[NIN], T mE, T mH, Op K, T (&phi)[NF], T (&e)[NF],
+                                               T (&h)[NF])
+{
+    T a[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) a[r] = e[r] = h[r] = T(0);
+    constexpr int CH = 12;   // coefficient chunks, as in apply_op
+#pragma unroll
+    for (int q = 0; q < P::N0; ++q) {
+        if (q % CH == 1 && q + CH - 1 < P::N0) asm volatile("" : "+s"(K) : "v"(a[P::R0[q - 1]]));
+        a[P::R0[q]] = fma(K->k0[q], w[P::C0[q]], a[P::R0[q]]);
+    }
+    asm volatile("" : "+s"(K) : "v"(a[P::R0[P::N0 - 1]]));
+#pragma unroll
+    for (int q = 0; q < P::NE; ++q) e[P::RE[q]] = fma(K->ke[q], w[P::CE[q]], e[P::RE[q]]);
+#pragma unroll
+    for (int q = 0; q < P::NH; ++q) h[P::RH[q]] = fma(K->kh[q], w[P::CH[q]], h[P::RH[q]]);
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+        T v = a[r];
+        if ((P::EROWS >> r) & 1u) v = fma(mE, e[r], v);
+        if ((P::HROWS >> r) & 1u) v = fma(mH, h[r], v);
+        phi[r] = v;
+    }
+}
+
 // Transpose: wbar += K(mE, mH)^T abar.
 template <typename P, typename T, int NF, int NIN, typename Op>
 __device__ __forceinline__ void apply_op_transpose(const T (&abar)[NF], T mE, T mH, Op K, T (&wbar)[NIN])
@@ -182,8 +211,13 @@ __device__ __forceinline__ void apply_op_transpose(const T (&abar)[NF], T mE, T 
         ae[r] = mE * abar[r];
         ah[r] = mH * abar[r];
     }
+    constexpr int CH = 12;   // coefficient chunks, as in apply_op
 #pragma unroll
-    for (int q = 0; q < P::N0; ++q) wbar[P::C0[q]] = fma(K->k0[q], abar[P::R0[q]], wbar[P::C0[q]]);
+    for (int q = 0; q < P::N0; ++q) {
+        if (q % CH == 1 && q + CH - 1 < P::N0) asm volatile("" : "+s"(K) : "v"(wbar[P::C0[q - 1]]));
+        wbar[P::C0[q]] = fma(K->k0[q], abar[P::R0[q]], wbar[P::C0[q]]);
+    }
+    asm volatile("" : "+s"(K) : "v"(wbar[P::C0[P::N0 - 1]]));
 #pragma unroll
     for (int q = 0; q < P::NE; ++q) wbar[P::CE[q]] = fma(K->ke[q], ae[P::RE[q]], wbar[P::CE[q]]);
 #pragma unroll

@@ -3,29 +3,32 @@
 // The forward step is U' = U - M^{-1} div Phi(pad(U)) + dt M^{-1} S, with pad() the ghost
 // extension of the grid by the boundary conditions (periodic wrap, PEC mirror with signs,
 // non-reflecting clamp for the Green-Gauss gradient) and Phi the face fluxes, each a sparse
-// linear form K(m_s) w_f of the left/right states and central differences (the same operators
-// as the forward kernel).  For lambda' = dJ/dU' the adjoint is
-//     lambda = pad^T psi,   psi(p) = lambda'(p) - sum_f W_f^T K(m_s)^T a_f,
-//     a_f = mu_L - mu_R,    mu = (1/eps, 1/mu) lambda' on cells, 0 on ghost positions,
-// and the material gradients collect, per cell, -lambda'.div(Phi) (the 1/eps, 1/mu factors of
-// the update) plus, per face, -a_f . d Phi_f / d m for both cells of the face (the mean face
-// material of the equilibrium time derivative).  Three kernels:
-//   1. faces:  one thread per padded position p next to a cell gathers the 13-point stencil of
-//      U (mapped through the boundary conditions), lambda' and the materials, evaluates the four
-//      faces of p (forward flux, transposed operator, material sensitivities) and stores p's
-//      share: the direct adjoint Ubar(p) and the adjoints of its two central differences
-//      (Dxbar, Dybar), and its material-gradient contributions;
-//   2. psi:    the transposed differences, psi(p) = [cell] lambda'(p) - Ubar(p)
-//              - Dxbar(p-x) + Dxbar(p+x) - Dybar(p-y) + Dybar(p+y), written to lambda on cells
-//              and to a ghost buffer on ghost positions;
-//   3. fold:   each cell within two cells of a side adds the psi and material gradients of the
-//      ghost positions that read it (pad^T), with the mirror signs.
-// Everything runs in a fixed order (no atomics), so the adjoint is deterministic.
+// linear form K(m_s) w_f of the left/right states and central differences (the operators of
+// the forward kernel).  For lambda' = dJ/dU' the adjoint is
+//     lambda = pad^T psi,   psi(p) = lambda'(p) - ubar(p) - Dxbar(p-x) + Dxbar(p+x)
+//                                   - Dybar(p-y) + Dybar(p+y),
+// where, over the faces f of p, ubar(p), Dxbar(p), Dybar(p) collect p's share of
+// wbar_f = K(m_s)^T a_f (its state, x-difference and y-difference parts), a_f = mu_L - mu_R and
+// mu = (1/eps, 1/mu) lambda' on cells, 0 on ghost positions.  The material gradients collect, per
+// cell, -lambda'.div(Phi) (the 1/eps, 1/mu factors of the update) and, per face and for both of
+// its cells, -a_f . d Phi_f / d m_s (the face material of the equilibrium time derivative).
+//
+// One kernel marches it, in the forward kernel's layout: a wave owns a strip of 64 columns (two
+// halo columns each side) and marches a tile of rows.  Per row step (head row q) it loads row
+// q+1, forms the central differences of row q-1, evaluates the x faces of row q-1 and the y
+// face between rows q-2 and q-1 (forward flux with its material parts, transposed operator,
+// material sensitivities), accumulates their shares per position (the right cell's share of an
+// x face by DPP), and finishes row q-3, whose faces and whose neighbours' faces are then all
+// known.  Cells receive lambda and their gradients; ghost positions (two layers around the
+// grid) write psi and their material gradients to a padded scratch that a small kernel then
+// adds, with the mirror signs, onto the cells they image.  Everything runs in a fixed order
+// (no atomics), so the adjoint is deterministic.
 #include "gks_device.h"
 
 namespace gks {
 
 constexpr int ADJ_BLOCK = 256;
+constexpr int ADJ_TILE_Y = 16;
 
 struct Pad2D {
     int nx, ny, px;   // px = nx + 4
@@ -34,234 +37,311 @@ struct Pad2D {
 };
 
 template <typename T>
-struct Pos {
-    T u[3];        // padded field values (mirror signs applied)
-    T lam[3];      // lambda' (0 on ghost positions)
+struct APos {
+    T u[3];        // fields (ghosts: the imaged cell with mirror signs)
+    T l[3];        // lambda' (0 on ghost positions)
     T mE, mH;      // materials of the cell read
-    bool ghost;    // outside the grid
-    bool nr;       // non-reflecting ghost (its side of a boundary face carries nothing)
+};
+
+template <typename T>
+struct AAcc {
+    T ub[3], dxb[3], dyb[3];   // adjoints of the state and of the two central differences
+    T div[3];                  // forward flux divergence
+    T sE, sH;                  // sum of the faces' material sensitivities a . (dPhi / dm_s)
+};
+
+template <typename T>
+__device__ __forceinline__ void zero_acc(AAcc<T> &A)
+{
+#pragma unroll
+    for (int f = 0; f < 3; ++f) A.ub[f] = A.dxb[f] = A.dyb[f] = A.div[f] = T(0);
+    A.sE = A.sH = T(0);
+}
+
+__device__ __forceinline__ bool row_is_nr(int gy, int ny, int bclo, int bchi)
+{
+    return (gy < 0 && bclo == GKS_BC_NONREFLECT) || (gy >= ny && bchi == GKS_BC_NONREFLECT);
+}
+
+template <typename T, bool HAS_EPS, bool HAS_MU, bool BND>
+struct AdjStrip {
+    const Cart2DAdjArgs<T> &a;
+    Rsrc rU, rL, rE, rM;
+    uint32_t fbytes;
+    int lane, x, x0;
+    uint32_t vx;        // byte offset of the column this lane reads
+    T sgx;              // x-mirror sign of the column this lane reads (Ez, Hx odd)
+    bool gx, nrx;       // this lane's column is a ghost / a non-reflecting ghost
+    bool nrx1;          // the next column is a non-reflecting ghost
+    bool own_x;         // this wave writes this lane's positions
+    int R0, R1;         // rows finished by this wave: [R0, R1)
+    bool first_y, last_y;
+    int64_t ncell;
+    int b;
+    T *padpsi;
+    double *padg;
+
+    __device__ __forceinline__ void load(int gy, APos<T> &p) const
+    {
+        if constexpr (BND) {
+            bool my, nry;
+            const int sy = map_axis(gy, a.ny, a.bc[2], a.bc[3], my, nry);
+            const bool gyst = gy < 0 || gy >= a.ny;
+            const uint32_t so = (uint32_t)sy * (uint32_t)a.nx * (uint32_t)sizeof(T);
+            const T sgy = my ? T(-1) : T(1);
+            p.u[0] = buf_load<T>(rU, vx, so) * (sgx * sgy);
+            p.u[1] = buf_load<T>(rU, vx, so + fbytes) * sgx;
+            p.u[2] = buf_load<T>(rU, vx, so + 2 * fbytes) * sgy;
+            const bool ghost = gx || gyst;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const T v = buf_load<T>(rL, vx, so + f * fbytes);
+                p.l[f] = ghost ? T(0) : v;
+            }
+            p.mE = HAS_EPS ? buf_load<T>(rE, vx, so) : T(1);
+            p.mH = HAS_MU ? buf_load<T>(rM, vx, so) : T(1);
+        } else {
+            const uint32_t so = ((uint32_t)gy * (uint32_t)a.nx + (uint32_t)x0) * (uint32_t)sizeof(T);
+            const uint32_t vo = (uint32_t)lane * (uint32_t)sizeof(T);
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                p.u[f] = buf_load<T>(rU, vo, so + f * fbytes);
+                p.l[f] = buf_load<T>(rL, vo, so + f * fbytes);
+            }
+            p.mE = HAS_EPS ? buf_load<T>(rE, vo, so) : T(1);
+            p.mH = HAS_MU ? buf_load<T>(rM, vo, so) : T(1);
+        }
+    }
+
+    __device__ __forceinline__ bool pos_nr(int gy) const
+    {
+        return BND && (nrx || row_is_nr(gy, a.ny, a.bc[2], a.bc[3]));
+    }
+
+    // One face: L/R data, inputs w (already zeroed on non-reflecting ghost sides).  Returns the
+    // forward flux phi, the transposed operator wbar = K^T a and the sensitivities.
+    template <typename P, typename Op>
+    __device__ __forceinline__ void face(const T (&w)[18], T mEs, T mHs, const T (&ad)[3], Op K, T (&phi)[3],
+                                         T (&wbar)[18], T &sE, T &sH) const
+    {
+        T e[3], h[3];
+        apply_op_parts<P>(w, mEs, mHs, K, phi, e, h);
+#pragma unroll
+        for (int q = 0; q < 18; ++q) wbar[q] = T(0);
+        // reload the coefficients for the transposed pass rather than keeping them live
+        asm volatile("" : "+s"(K) : "v"(phi[2]));
+        apply_op_transpose<P>(ad, mEs, mHs, K, wbar);
+        sE = ad[0] * e[0] + ad[1] * e[1] + ad[2] * e[2];
+        sH = ad[0] * h[0] + ad[1] * h[1] + ad[2] * h[2];
+    }
+
+    // Step i of the march (head row q = qs + i); I = i mod 4 selects the register slots:
+    // data row q-k in P[(i-k)&3], accumulators of row q-k in S[(i-k)&3], differences of row
+    // q-k in G[(i-k)&1].
+    template <int I>
+    __device__ __forceinline__ void step(int i, int qs, APos<T> (&P)[4], AAcc<T> (&S)[4], T (&G)[2][6]) const
+    {
+        const int q = qs + i;
+        APos<T> &P3 = P[(I + 1) & 3], &P2 = P[(I + 2) & 3], &P1 = P[(I + 3) & 3], &P0 = P[I];
+        AAcc<T> &A4 = S[I], &A3 = S[(I + 1) & 3], &A2 = S[(I + 2) & 3], &A1 = S[(I + 3) & 3];
+        T(&G2)[6] = G[I & 1];
+        T(&G1)[6] = G[(I + 1) & 1];
+        // lambda' of row q-3 (finished below), then row q+1 into its slot
+        T lf[3];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) lf[f] = P3.l[f];
+        load(min(q + 1, R1 + 2), P3);
+        zero_acc(A1);
+
+        // central differences of row q-1: [d/dx(3) d/dy(3)]
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            G1[f] = from_right(P1.u[f]) - from_left(P1.u[f]);
+            G1[3 + f] = P0.u[f] - P2.u[f];
+        }
+
+        // x faces of row q-1: inputs [UL UR dxL dyL dxR dyR], R the next lane
+        {
+            const bool nr = pos_nr(q - 1);
+            T su[3], sg[6], mu[3];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) su[f] = nr ? T(0) : P1.u[f];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sg[k] = nr ? T(0) : G1[k];
+            mu[0] = P1.mE * P1.l[0];
+            mu[1] = P1.mH * P1.l[1];
+            mu[2] = P1.mH * P1.l[2];
+            T w[18], ad[3];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                w[f] = su[f];
+                w[3 + f] = from_right(su[f]);
+                w[6 + f] = sg[f];
+                w[9 + f] = sg[3 + f];
+                w[12 + f] = from_right(sg[f]);
+                w[15 + f] = from_right(sg[3 + f]);
+                ad[f] = mu[f] - from_right(mu[f]);
+            }
+            const T mEs = P1.mE + from_right(P1.mE), mHs = P1.mH + from_right(P1.mH);
+            T phi[3], wbar[18], sE, sH;
+            face<PatTMx>(w, mEs, mHs, ad, scalar_ptr_after(a.ops, G1[5]), phi, wbar, sE, sH);
+            // the left cell (this lane) and the right cell (the next lane, by DPP); a
+            // non-reflecting ghost side receives nothing: the sending lane zeroes the right
+            // cell's share, so the moves need no select on the receiving side
+            const bool nrR = BND && (nrx1 || row_is_nr(q - 1, a.ny, a.bc[2], a.bc[3]));
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const T sub = nrR ? T(0) : wbar[3 + f], sdx = nrR ? T(0) : wbar[12 + f], sdy = nrR ? T(0) : wbar[15 + f];
+                A1.ub[f] += (nr ? T(0) : wbar[f]) + from_left(sub);
+                A1.dxb[f] += (nr ? T(0) : wbar[6 + f]) + from_left(sdx);
+                A1.dyb[f] += (nr ? T(0) : wbar[9 + f]) + from_left(sdy);
+                A1.div[f] += phi[f] - from_left(phi[f]);
+            }
+            A1.sE += sE + from_left(sE);
+            A1.sH += sH + from_left(sH);
+        }
+
+        // y face between rows q-2 and q-1: inputs [UL UR dyL dxL dyR dxR]
+        if (i >= 1) {
+            const bool zl = pos_nr(q - 2), zr = pos_nr(q - 1);
+            T w[18], ad[3];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                w[f] = zl ? T(0) : P2.u[f];
+                w[3 + f] = zr ? T(0) : P1.u[f];
+                w[6 + f] = zl ? T(0) : G2[3 + f];
+                w[9 + f] = zl ? T(0) : G2[f];
+                w[12 + f] = zr ? T(0) : G1[3 + f];
+                w[15 + f] = zr ? T(0) : G1[f];
+            }
+            ad[0] = P2.mE * P2.l[0] - P1.mE * P1.l[0];
+            ad[1] = P2.mH * P2.l[1] - P1.mH * P1.l[1];
+            ad[2] = P2.mH * P2.l[2] - P1.mH * P1.l[2];
+            T phi[3], wbar[18], sE, sH;
+            face<PatTMy>(w, P2.mE + P1.mE, P2.mH + P1.mH, ad, scalar_ptr_after(a.ops + 1, G1[2]), phi, wbar, sE, sH);
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                A2.ub[f] += zl ? T(0) : wbar[f];
+                A2.dyb[f] += zl ? T(0) : wbar[6 + f];
+                A2.dxb[f] += zl ? T(0) : wbar[9 + f];
+                A2.div[f] += phi[f];
+                A1.ub[f] += zr ? T(0) : wbar[3 + f];
+                A1.dyb[f] += zr ? T(0) : wbar[12 + f];
+                A1.dxb[f] += zr ? T(0) : wbar[15 + f];
+                A1.div[f] -= phi[f];
+            }
+            A2.sE += sE;
+            A2.sH += sH;
+            A1.sE += sE;
+            A1.sH += sH;
+        }
+
+        // finish row q-3: every face of it and of its four neighbours is known now
+        const int r = q - 3;
+        if (r >= R0 && r < R1) {
+            T psi[3];
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+                psi[f] = lf[f] - A3.ub[f] - from_left(A3.dxb[f]) + from_right(A3.dxb[f]) - A4.dyb[f] + A2.dyb[f];
+            const double gE = -(double)lf[0] * (double)A3.div[0] - (double)A3.sE;
+            const double gH = -((double)lf[1] * (double)A3.div[1] + (double)lf[2] * (double)A3.div[2]) - (double)A3.sH;
+            const bool ry = r >= 0 && r < a.ny;
+            const bool own_y = (r >= -2 && r <= a.ny + 1) && ((r >= R0 && r < R1 && ry) || (!ry && (first_y || last_y)));
+            if (own_x && own_y) {
+                if (!gx && ry) {
+                    const int64_t c = (int64_t)r * a.nx + x;
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) a.lam_out[((int64_t)b * 3 + f) * ncell + c] = psi[f];
+                    if (a.g_epsinv) a.g_epsinv[(int64_t)b * ncell + c] += gE;
+                    if (a.g_muinv) a.g_muinv[(int64_t)b * ncell + c] += gH;
+                } else {
+                    const Pad2D pd{a.nx, a.ny, a.nx + 4};
+                    const int64_t npos = pd.size(), pp = pd.idx(x, r);
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) padpsi[((int64_t)b * 3 + f) * npos + pp] = psi[f];
+                    padg[((int64_t)b * 2 + 0) * npos + pp] = gE;
+                    padg[((int64_t)b * 2 + 1) * npos + pp] = gH;
+                }
+            }
+        }
+    }
+
+    __device__ __forceinline__ void run() const
+    {
+        APos<T> P[4];
+        AAcc<T> S[4];
+        T G[2][6];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) zero_acc(S[k]);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) G[0][k] = G[1][k] = T(0);
+        const int qs = R0 - 1;                 // the first step forms the differences of row R0-2
+        load(qs - 3, P[1]);
+        load(qs - 2, P[2]);
+        load(qs - 1, P[3]);
+        load(qs, P[0]);
+        const int n = R1 - R0 + 4;             // the last step finishes row R1-1
+        for (int i = 0; i < n; i += 4) {
+            step<0>(i, qs, P, S, G);
+            if (i + 1 >= n) break;
+            step<1>(i + 1, qs, P, S, G);
+            if (i + 2 >= n) break;
+            step<2>(i + 2, qs, P, S, G);
+            if (i + 3 >= n) break;
+            step<3>(i + 3, qs, P, S, G);
+        }
+    }
 };
 
 template <typename T, bool HAS_EPS, bool HAS_MU>
-__device__ __forceinline__ void gather(const Cart2DAdjArgs<T> &a, const T *Ub, const T *Lb, const T *Eb, const T *Mb,
-                                       int64_t ncell, int i, int j, Pos<T> &p)
+__global__ __launch_bounds__(ADJ_BLOCK) void adj2d_march_kernel(Cart2DAdjArgs<T> a, T *padpsi, double *padg, int32_t ntx,
+                                                                int32_t nty)
 {
-    bool mx, nrx, my, nry;
-    const int sx = map_axis(i, a.nx, a.bc[0], a.bc[1], mx, nrx);
-    const int sy = map_axis(j, a.ny, a.bc[2], a.bc[3], my, nry);
-    const int64_t c = (int64_t)sy * a.nx + sx;
-    const T sgx = mx ? T(-1) : T(1), sgy = my ? T(-1) : T(1);
-    p.u[0] = Ub[c] * (sgx * sgy);      // Ez: odd in both mirrors
-    p.u[1] = Ub[ncell + c] * sgx;      // Hx: odd in the x mirror
-    p.u[2] = Ub[2 * ncell + c] * sgy;  // Hy: odd in the y mirror
-    p.mE = HAS_EPS ? Eb[c] : T(1);
-    p.mH = HAS_MU ? Mb[c] : T(1);
-    p.ghost = i < 0 || i >= a.nx || j < 0 || j >= a.ny;
-    p.nr = nrx || nry;
-#pragma unroll
-    for (int f = 0; f < 3; ++f) p.lam[f] = p.ghost ? T(0) : Lb[f * ncell + c];
-}
-
-// One face: L/R positions with their central differences dL, dR ([dn(3) dt(3)]).  Adds p's
-// share (side = 0: p is L, 1: p is R) of the transposed operator to ubar/dbar, returns the
-// forward flux in phi and accumulates p's material sensitivity.
-template <typename P, typename T, typename Op>
-__device__ __forceinline__ void face_adjoint(const Pos<T> &L, const Pos<T> &R, const T (&dL)[6], const T (&dR)[6],
-                                             int side, Op K, T (&ubar)[3], T (&dnbar)[3], T (&dtbar)[3], T (&phi)[3],
-                                             double &gE, double &gH)
-{
-    const bool zl = L.ghost && L.nr, zr = R.ghost && R.nr;
-    T w[18];
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        w[f] = zl ? T(0) : L.u[f];
-        w[3 + f] = zr ? T(0) : R.u[f];
-        w[6 + f] = zl ? T(0) : dL[f];
-        w[9 + f] = zl ? T(0) : dL[3 + f];
-        w[12 + f] = zr ? T(0) : dR[f];
-        w[15 + f] = zr ? T(0) : dR[3 + f];
-    }
-    const T mE = L.mE + R.mE, mH = L.mH + R.mH;
-    apply_op<P>(w, mE, mH, K, phi);
-    T abar[3], mu_l[3], mu_r[3];
-    mu_l[0] = L.mE * L.lam[0];
-    mu_l[1] = L.mH * L.lam[1];
-    mu_l[2] = L.mH * L.lam[2];
-    mu_r[0] = R.mE * R.lam[0];
-    mu_r[1] = R.mH * R.lam[1];
-    mu_r[2] = R.mH * R.lam[2];
-#pragma unroll
-    for (int f = 0; f < 3; ++f) abar[f] = mu_l[f] - mu_r[f];
-    T wbar[18];
-#pragma unroll
-    for (int q = 0; q < 18; ++q) wbar[q] = T(0);
-    apply_op_transpose<P>(abar, mE, mH, K, wbar);
-    const bool drop = side == 0 ? zl : zr;   // the ghost side of a non-reflecting face is not read
-    if (!drop) {
-        const int o = side == 0 ? 0 : 3, od = side == 0 ? 6 : 12;
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            ubar[f] += wbar[o + f];
-            dnbar[f] += wbar[od + f];
-            dtbar[f] += wbar[od + 3 + f];
-        }
-    }
-    T sE, sH;
-    material_sens<P>(abar, w, K, sE, sH);
-    gE -= (double)sE;
-    gH -= (double)sH;
-}
-
-template <typename T, bool HAS_EPS, bool HAS_MU>
-__global__ __launch_bounds__(ADJ_BLOCK) void adj2d_faces_kernel(Cart2DAdjArgs<T> a, T *pad9, double *padg)
-{
-    const Pad2D pd{a.nx, a.ny, a.nx + 4};
-    const int64_t npos = pd.size();
-    const int64_t t = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
-    const int b = blockIdx.y;
-    if (t >= npos) return;
-    const int i = (int)(t % pd.px) - 2, j = (int)(t / pd.px) - 2;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = xcd_logical_block() * (ADJ_BLOCK / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int per_b = ntx * nty;
+    const int b = wave / per_b;
+    if (b >= a.batch) return;
+    const int rem = wave - b * per_b;
+    const int ty = rem / ntx;
+    const int tx = rem - ty * ntx;
     const int64_t ncell = (int64_t)a.nx * a.ny;
-    T *out = pad9 + (int64_t)b * 9 * npos;
-    double *gout = padg + (int64_t)b * 2 * npos;
-    // positions two layers outside the grid touch no face of a cell
-    if (i < -1 || i > a.nx || j < -1 || j > a.ny) {
-#pragma unroll
-        for (int q = 0; q < 9; ++q) out[q * npos + t] = T(0);
-        gout[t] = 0.0;
-        gout[npos + t] = 0.0;
-        return;
-    }
-    const T *Ub = a.U + (int64_t)b * 3 * ncell;
-    const T *Lb = a.lam + (int64_t)b * 3 * ncell;
-    const T *Eb = HAS_EPS ? a.epsinv + (int64_t)b * ncell : nullptr;
-    const T *Mb = HAS_MU ? a.muinv + (int64_t)b * ncell : nullptr;
-
-    // 13-point stencil: c = p, x-/x+ = p -+ 1, xx-/xx+ = p -+ 2, same in y, and the diagonals
-    Pos<T> c, xm, xp, xmm, xpp, ym, yp, ymm, ypp, mm, pm, mp, pp;
-    gather<T, HAS_EPS, HAS_MU>(a, Ub, Lb, Eb, Mb, ncell, i, j, c);
-    gather<T, HAS_EPS, HAS_MU>(a, Ub, Lb, Eb, Mb, ncell, i - 1, j, xm);
-    gather<T, HAS_EPS, HAS_MU>(a, Ub, Lb, Eb, Mb, ncell, i + 1, j, xp);
-    gather<T, HAS_EPS, HAS_MU>(a, Ub, Lb, Eb, Mb, ncell, i - 2, j, xmm);
-    gather<T, HAS_EPS, HAS_MU>(a, Ub, Lb, Eb, Mb, ncell, i + 2, j, xpp);
-    gather<T, HAS_EPS, HAS_MU>(a, Ub, Lb, Eb, Mb, ncell, i, j - 1, ym);
-    gather<T, HAS_EPS, HAS_MU>(a, Ub, Lb, Eb, Mb, ncell, i, j + 1, yp);
-    gather<T, HAS_EPS, HAS_MU>(a, Ub, Lb, Eb, Mb, ncell, i, j - 2, ymm);
-    gather<T, HAS_EPS, HAS_MU>(a, Ub, Lb, Eb, Mb, ncell, i, j + 2, ypp);
-    gather<T, HAS_EPS, HAS_MU>(a, Ub, Lb, Eb, Mb, ncell, i - 1, j - 1, mm);
-    gather<T, HAS_EPS, HAS_MU>(a, Ub, Lb, Eb, Mb, ncell, i + 1, j - 1, pm);
-    gather<T, HAS_EPS, HAS_MU>(a, Ub, Lb, Eb, Mb, ncell, i - 1, j + 1, mp);
-    gather<T, HAS_EPS, HAS_MU>(a, Ub, Lb, Eb, Mb, ncell, i + 1, j + 1, pp);
-
-    // central differences [d/dx(3) d/dy(3)] of the five positions p, p-+x, p-+y
-    T Dc[6], Dxm[6], Dxp[6], Dym[6], Dyp[6];
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        Dc[f] = xp.u[f] - xm.u[f];
-        Dc[3 + f] = yp.u[f] - ym.u[f];
-        Dxm[f] = c.u[f] - xmm.u[f];
-        Dxm[3 + f] = mp.u[f] - mm.u[f];
-        Dxp[f] = xpp.u[f] - c.u[f];
-        Dxp[3 + f] = pp.u[f] - pm.u[f];
-        Dym[f] = pm.u[f] - mm.u[f];
-        Dym[3 + f] = c.u[f] - ymm.u[f];
-        Dyp[f] = pp.u[f] - mp.u[f];
-        Dyp[3 + f] = ypp.u[f] - c.u[f];
-    }
-    // re-ordered [dn dt] per face orientation: x-faces [dx dy], y-faces [dy dx]
-    auto nt_x = [](const T (&D)[6], T (&o)[6]) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) o[q] = D[q];
+    const uint32_t fbytes = (uint32_t)(ncell * (int64_t)sizeof(T));
+    const Rsrc rU = make_rsrc(a.U + (int64_t)b * 3 * ncell, 3ull * fbytes);
+    const Rsrc rL = make_rsrc(a.lam + (int64_t)b * 3 * ncell, 3ull * fbytes);
+    const Rsrc rE = make_rsrc(a.epsinv ? a.epsinv + (int64_t)b * ncell : a.U, fbytes);
+    const Rsrc rM = make_rsrc(a.muinv ? a.muinv + (int64_t)b * ncell : a.U, fbytes);
+    const int x0 = tx * (WAVE - 4) - 2, x = x0 + lane;
+    const int y0 = ty * ADJ_TILE_Y, y1 = min(y0 + ADJ_TILE_Y, a.ny);
+    const bool first_y = ty == 0, last_y = ty == nty - 1;
+    const int R0 = first_y ? -2 : y0, R1 = last_y ? a.ny + 2 : y1;
+    const bool interior = x0 >= 0 && x0 + WAVE - 1 <= a.nx - 1 && R0 - 4 >= 0 && R1 + 2 <= a.ny - 1;
+    auto go = [&](auto bnd) {
+        constexpr bool BND = decltype(bnd)::value;
+        AdjStrip<T, HAS_EPS, HAS_MU, BND> s{a, rU, rL, rE, rM, fbytes, lane, x, x0};
+        bool mx, nrx;
+        const int sx = map_axis(x, a.nx, a.bc[0], a.bc[1], mx, nrx);
+        s.vx = (uint32_t)sx * (uint32_t)sizeof(T);
+        s.sgx = mx ? T(-1) : T(1);
+        s.gx = x < 0 || x >= a.nx;
+        s.nrx = nrx;
+        bool mx1, nrx1;
+        map_axis(x + 1, a.nx, a.bc[0], a.bc[1], mx1, nrx1);
+        s.nrx1 = nrx1;
+        s.own_x = (x >= -2 && x <= a.nx + 1) &&
+                  ((lane >= 2 && lane < WAVE - 2) || x < 0 || (x >= a.nx && tx == ntx - 1));
+        s.R0 = R0;
+        s.R1 = R1;
+        s.first_y = first_y;
+        s.last_y = last_y;
+        s.ncell = ncell;
+        s.b = b;
+        s.padpsi = padpsi;
+        s.padg = padg;
+        s.run();
     };
-    auto nt_y = [](const T (&D)[6], T (&o)[6]) {
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            o[f] = D[3 + f];
-            o[3 + f] = D[f];
-        }
-    };
-    T ubar[3] = {T(0), T(0), T(0)}, dxbar[3] = {T(0), T(0), T(0)}, dybar[3] = {T(0), T(0), T(0)};
-    T div[3] = {T(0), T(0), T(0)};
-    double gE = 0.0, gH = 0.0;
-    const auto opx = scalar_ptr(a.ops), opy = scalar_ptr(a.ops + 1);
-    T dA[6], dB[6], phi[3];
-    // x-face left of p (p is R), x-face right of p (p is L); a face with two ghost sides touches no cell
-    if (!(xm.ghost && c.ghost)) {
-        nt_x(Dxm, dA);
-        nt_x(Dc, dB);
-        face_adjoint<PatTMx>(xm, c, dA, dB, 1, opx, ubar, dxbar, dybar, phi, gE, gH);
-#pragma unroll
-        for (int f = 0; f < 3; ++f) div[f] -= phi[f];
-    }
-    if (!(c.ghost && xp.ghost)) {
-        nt_x(Dc, dA);
-        nt_x(Dxp, dB);
-        face_adjoint<PatTMx>(c, xp, dA, dB, 0, opx, ubar, dxbar, dybar, phi, gE, gH);
-#pragma unroll
-        for (int f = 0; f < 3; ++f) div[f] += phi[f];
-    }
-    if (!(ym.ghost && c.ghost)) {
-        nt_y(Dym, dA);
-        nt_y(Dc, dB);
-        face_adjoint<PatTMy>(ym, c, dA, dB, 1, opy, ubar, dybar, dxbar, phi, gE, gH);
-#pragma unroll
-        for (int f = 0; f < 3; ++f) div[f] -= phi[f];
-    }
-    if (!(c.ghost && yp.ghost)) {
-        nt_y(Dc, dA);
-        nt_y(Dyp, dB);
-        face_adjoint<PatTMy>(c, yp, dA, dB, 0, opy, ubar, dybar, dxbar, phi, gE, gH);
-#pragma unroll
-        for (int f = 0; f < 3; ++f) div[f] += phi[f];
-    }
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        out[f * npos + t] = ubar[f];
-        out[(3 + f) * npos + t] = dxbar[f];
-        out[(6 + f) * npos + t] = dybar[f];
-    }
-    if (!c.ghost) {
-        // the 1/eps, 1/mu factors of the cell update: d/dm (-m lambda'.div) = -lambda'.div
-        gE -= (double)c.lam[0] * (double)div[0];
-        gH -= (double)c.lam[1] * (double)div[1] + (double)c.lam[2] * (double)div[2];
-        const int64_t cc = (int64_t)j * a.nx + i;
-        if (a.g_epsinv) a.g_epsinv[(int64_t)b * ncell + cc] += gE;
-        if (a.g_muinv) a.g_muinv[(int64_t)b * ncell + cc] += gH;
-        gout[t] = 0.0;
-        gout[npos + t] = 0.0;
-    } else {
-        gout[t] = gE;
-        gout[npos + t] = gH;
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(ADJ_BLOCK) void adj2d_psi_kernel(Cart2DAdjArgs<T> a, const T *pad9, T *padpsi)
-{
-    const Pad2D pd{a.nx, a.ny, a.nx + 4};
-    const int64_t npos = pd.size();
-    const int64_t t = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
-    const int b = blockIdx.y;
-    if (t >= npos) return;
-    const int i = (int)(t % pd.px) - 2, j = (int)(t / pd.px) - 2;
-    const int64_t ncell = (int64_t)a.nx * a.ny;
-    const T *in = pad9 + (int64_t)b * 9 * npos;
-    auto at = [&](int q, int ii, int jj) -> T {
-        if (ii < -2 || ii >= a.nx + 2 || jj < -2 || jj >= a.ny + 2) return T(0);
-        return in[q * npos + pd.idx(ii, jj)];
-    };
-    const bool cell = i >= 0 && i < a.nx && j >= 0 && j < a.ny;
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        T v = cell ? a.lam[((int64_t)b * 3 + f) * ncell + (int64_t)j * a.nx + i] : T(0);
-        v -= at(f, i, j);
-        v -= at(3 + f, i - 1, j);
-        v += at(3 + f, i + 1, j);
-        v -= at(6 + f, i, j - 1);
-        v += at(6 + f, i, j + 1);
-        if (cell) a.lam_out[((int64_t)b * 3 + f) * ncell + (int64_t)j * a.nx + i] = v;
-        else padpsi[((int64_t)b * 3 + f) * npos + t] = v;
-    }
+    if (interior) go(std::integral_constant<bool, false>{});
+    else go(std::integral_constant<bool, true>{});
 }
 
 // Cells within two cells of a side (the only ones a ghost position reads): the first and
@@ -347,15 +427,21 @@ __global__ void adj_source_kernel(const T *lam, double *g_epsinv, int64_t ncell,
 template <typename T>
 int launch_cart2d_adjoint(const Cart2DAdjArgs<T> &a, T *pad9, T *padpsi, double *padg, void *stream)
 {
+    (void)pad9;
     hipStream_t s = (hipStream_t)stream;
-    const int64_t npos = (int64_t)(a.nx + 4) * (a.ny + 4);
+    const int ntx = (a.nx + (WAVE - 4) - 1) / (WAVE - 4), nty = (a.ny + ADJ_TILE_Y - 1) / ADJ_TILE_Y;
+    const int64_t waves = (int64_t)ntx * nty * a.batch;
+    dim3 grid((unsigned)((waves + ADJ_BLOCK / WAVE - 1) / (ADJ_BLOCK / WAVE)));
+    if (a.epsinv && a.muinv)
+        hipLaunchKernelGGL((adj2d_march_kernel<T, true, true>), grid, dim3(ADJ_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
+    else if (a.epsinv)
+        hipLaunchKernelGGL((adj2d_march_kernel<T, true, false>), grid, dim3(ADJ_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
+    else if (a.muinv)
+        hipLaunchKernelGGL((adj2d_march_kernel<T, false, true>), grid, dim3(ADJ_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
+    else
+        hipLaunchKernelGGL((adj2d_march_kernel<T, false, false>), grid, dim3(ADJ_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
     const int64_t nband = Band2D(a.nx, a.ny).count();
-    dim3 gpad((unsigned)((npos + ADJ_BLOCK - 1) / ADJ_BLOCK), a.batch), gband((unsigned)((nband + ADJ_BLOCK - 1) / ADJ_BLOCK), a.batch);
-    if (a.epsinv && a.muinv) hipLaunchKernelGGL((adj2d_faces_kernel<T, true, true>), gpad, dim3(ADJ_BLOCK), 0, s, a, pad9, padg);
-    else if (a.epsinv) hipLaunchKernelGGL((adj2d_faces_kernel<T, true, false>), gpad, dim3(ADJ_BLOCK), 0, s, a, pad9, padg);
-    else if (a.muinv) hipLaunchKernelGGL((adj2d_faces_kernel<T, false, true>), gpad, dim3(ADJ_BLOCK), 0, s, a, pad9, padg);
-    else hipLaunchKernelGGL((adj2d_faces_kernel<T, false, false>), gpad, dim3(ADJ_BLOCK), 0, s, a, pad9, padg);
-    hipLaunchKernelGGL(adj2d_psi_kernel<T>, gpad, dim3(ADJ_BLOCK), 0, s, a, (const T *)pad9, padpsi);
+    dim3 gband((unsigned)((nband + ADJ_BLOCK - 1) / ADJ_BLOCK), a.batch);
     hipLaunchKernelGGL(adj2d_fold_kernel<T>, gband, dim3(ADJ_BLOCK), 0, s, a, (const T *)padpsi, (const double *)padg);
     return (int)hipGetLastError();
 }
