@@ -94,7 +94,7 @@ struct TriArgs {
     T *Unew;
     const T *epsinv;      // nullable: vacuum
     const T *muinv;       // nullable: vacuum
-    T *grad;              // scratch [batch][6][ncell]: d/dx (Ez Hx Hy), d/dy (Ez Hx Hy)
+    T *grad;              // scratch [batch][ncell][6]: d/dx (Ez Hx Hy), d/dy (Ez Hx Hy) per cell
     int32_t ncell, batch;
     const int32_t *nb;    // device [3][ncell]
     const T *geo;         // device [TRI_GEO][3][ncell]

@@ -28,6 +28,10 @@
 namespace gks {
 
 constexpr int ADJ_BLOCK = 256;
+// One wave per workgroup for the march: its waves finish at different times, and a single-wave
+// workgroup lets a freed slot take the next tile at once (4-wave workgroups wait for four free
+// slots on one compute unit).  Measured on 1024^2 x 8: 231 vs 241 us (fp32), 503 vs 552 us (fp64).
+constexpr int ADJ_MARCH_BLOCK = 64;
 constexpr int ADJ_TILE_Y = 16;
 
 struct Pad2D {
@@ -294,11 +298,11 @@ struct AdjStrip {
 };
 
 template <typename T, bool HAS_EPS, bool HAS_MU>
-__global__ __launch_bounds__(ADJ_BLOCK) void adj2d_march_kernel(Cart2DAdjArgs<T> a, T *padpsi, double *padg, int32_t ntx,
+__global__ __launch_bounds__(ADJ_MARCH_BLOCK) void adj2d_march_kernel(Cart2DAdjArgs<T> a, T *padpsi, double *padg, int32_t ntx,
                                                                 int32_t nty)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int wave = xcd_logical_block() * (ADJ_BLOCK / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int wave = xcd_logical_block() * (ADJ_MARCH_BLOCK / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int per_b = ntx * nty;
     const int b = wave / per_b;
     if (b >= a.batch) return;
@@ -431,15 +435,15 @@ int launch_cart2d_adjoint(const Cart2DAdjArgs<T> &a, T *pad9, T *padpsi, double 
     hipStream_t s = (hipStream_t)stream;
     const int ntx = (a.nx + (WAVE - 4) - 1) / (WAVE - 4), nty = (a.ny + ADJ_TILE_Y - 1) / ADJ_TILE_Y;
     const int64_t waves = (int64_t)ntx * nty * a.batch;
-    dim3 grid((unsigned)((waves + ADJ_BLOCK / WAVE - 1) / (ADJ_BLOCK / WAVE)));
+    dim3 grid((unsigned)((waves + ADJ_MARCH_BLOCK / WAVE - 1) / (ADJ_MARCH_BLOCK / WAVE)));
     if (a.epsinv && a.muinv)
-        hipLaunchKernelGGL((adj2d_march_kernel<T, true, true>), grid, dim3(ADJ_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
+        hipLaunchKernelGGL((adj2d_march_kernel<T, true, true>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
     else if (a.epsinv)
-        hipLaunchKernelGGL((adj2d_march_kernel<T, true, false>), grid, dim3(ADJ_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
+        hipLaunchKernelGGL((adj2d_march_kernel<T, true, false>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
     else if (a.muinv)
-        hipLaunchKernelGGL((adj2d_march_kernel<T, false, true>), grid, dim3(ADJ_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
+        hipLaunchKernelGGL((adj2d_march_kernel<T, false, true>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
     else
-        hipLaunchKernelGGL((adj2d_march_kernel<T, false, false>), grid, dim3(ADJ_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
+        hipLaunchKernelGGL((adj2d_march_kernel<T, false, false>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
     const int64_t nband = Band2D(a.nx, a.ny).count();
     dim3 gband((unsigned)((nband + ADJ_BLOCK - 1) / ADJ_BLOCK), a.batch);
     hipLaunchKernelGGL(adj2d_fold_kernel<T>, gband, dim3(ADJ_BLOCK), 0, s, a, (const T *)padpsi, (const double *)padg);

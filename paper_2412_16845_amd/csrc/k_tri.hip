@@ -1,7 +1,8 @@
 // GKS step on a triangle mesh, TM fields (Ez, Hx, Hy).
 //
 // Two kernels, one thread per cell (cells in Hilbert order, so the neighbours a thread gathers
-// are mostly cached):
+// are mostly cached; consecutive blocks are renumbered onto one XCD, so that a block's
+// neighbouring blocks share its L2):
 //   1. Green-Gauss gradients (Sec. 3.1): grad U_i = sum_s (U_nb - U_i)/2 n_s |l_s| / |Omega_i|,
 //      with the ghost of a non-reflecting face equal to the cell itself and the ghost of a PEC
 //      face its mirror image (Ez and the normal H odd);
@@ -22,11 +23,41 @@ namespace {
 
 constexpr int TRI_BLOCK = 256;
 
+// The gradient scratch holds one record of six values per cell, [d/dx (Ez Hx Hy), d/dy (Ez Hx
+// Hy)], so that the gradients of a gathered neighbour come from one or two cache lines.
+template <typename T> struct Pair;
+template <> struct Pair<float> { using type = float2; };
+template <> struct Pair<double> { using type = double2; };
+
+template <typename T>
+__device__ __forceinline__ void load_grad(const T *G, int64_t c, T (&gx)[3], T (&gy)[3])
+{
+    using V = typename Pair<T>::type;
+    const V *p = reinterpret_cast<const V *>(G + c * 6);
+    const V v0 = p[0], v1 = p[1], v2 = p[2];
+    gx[0] = v0.x;
+    gx[1] = v0.y;
+    gx[2] = v1.x;
+    gy[0] = v1.y;
+    gy[1] = v2.x;
+    gy[2] = v2.y;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_grad(T *G, int64_t c, const T (&gx)[3], const T (&gy)[3])
+{
+    using V = typename Pair<T>::type;
+    V *p = reinterpret_cast<V *>(G + c * 6);
+    p[0] = V{gx[0], gx[1]};
+    p[1] = V{gx[2], gy[0]};
+    p[2] = V{gy[1], gy[2]};
+}
+
 template <typename T>
 __global__ __launch_bounds__(TRI_BLOCK) void tri_grad_kernel(TriArgs<T> a)
 {
     const int64_t nc = a.ncell;
-    const int64_t i = (int64_t)blockIdx.x * TRI_BLOCK + threadIdx.x;
+    const int64_t i = (int64_t)xcd_logical_block() * TRI_BLOCK + threadIdx.x;
     const int b = blockIdx.y;
     if (i >= nc) return;
     const T *U = a.U + (int64_t)b * 3 * nc;
@@ -58,12 +89,7 @@ __global__ __launch_bounds__(TRI_BLOCK) void tri_grad_kernel(TriArgs<T> a)
             gy[f] = fma(d, ny, gy[f]);
         }
     }
-    T *g = a.grad + (int64_t)b * 6 * nc;
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        g[f * nc + i] = gx[f];
-        g[(3 + f) * nc + i] = gy[f];
-    }
+    store_grad(a.grad + (int64_t)b * 6 * nc, i, gx, gy);
 }
 
 // Face-frame form of a global TM vector (Ez, Hx, Hy) for the normal n: (Ez, H.n, H.t).
@@ -79,7 +105,7 @@ template <typename T, bool HAS_EPS, bool HAS_MU>
 __global__ __launch_bounds__(TRI_BLOCK) void tri_step_kernel(TriArgs<T> a)
 {
     const int64_t nc = a.ncell;
-    const int64_t i = (int64_t)blockIdx.x * TRI_BLOCK + threadIdx.x;
+    const int64_t i = (int64_t)xcd_logical_block() * TRI_BLOCK + threadIdx.x;
     const int b = blockIdx.y;
     if (i >= nc) return;
     const T *U = a.U + (int64_t)b * 3 * nc;
@@ -88,11 +114,8 @@ __global__ __launch_bounds__(TRI_BLOCK) void tri_step_kernel(TriArgs<T> a)
     const T *M = HAS_MU ? a.muinv + (int64_t)b * nc : nullptr;
     T u[3], gx[3], gy[3];
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        u[f] = U[f * nc + i];
-        gx[f] = Gr[f * nc + i];
-        gy[f] = Gr[(3 + f) * nc + i];
-    }
+    for (int f = 0; f < 3; ++f) u[f] = U[f * nc + i];
+    load_grad(Gr, i, gx, gy);
     const T mE = HAS_EPS ? E[i] : T(1), mH = HAS_MU ? M[i] : T(1);
     T div[3] = {T(0), T(0), T(0)};
 #pragma unroll
@@ -125,10 +148,11 @@ __global__ __launch_bounds__(TRI_BLOCK) void tri_step_kernel(TriArgs<T> a)
         T mEs, mHs;
         if (nb >= 0) {
             const T bx = a.geo[(5 * 3 + k) * nc + i], by = a.geo[(6 * 3 + k) * nc + i];
-            T ur[3], dn[3], dt[3];
+            T ur[3], dn[3], dt[3], hxs[3], hys[3];
+            load_grad(Gr, nb, hxs, hys);
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
-                const T v = U[f * nc + nb], hx = Gr[f * nc + nb], hy = Gr[(3 + f) * nc + nb];
+                const T v = U[f * nc + nb], hx = hxs[f], hy = hys[f];
                 ur[f] = v + hx * bx + hy * by;
                 dn[f] = hx * nx + hy * ny;
                 dt[f] = hy * nx - hx * ny;
