@@ -74,15 +74,20 @@ struct Cart3DArgs {
     const FaceOpEM<T> *ops;  // device: x-, y- and z-face operators
 };
 
-// Triangle meshes: per cell and face slot (three per cell) the neighbour (or -(1 + bc) on a
-// boundary face) and TRI_GEO geometry attributes [nx ny lw ax ay bx by] (outward unit normal,
-// |l|/|Omega|, midpoint minus own centroid, midpoint minus neighbour centroid), each stored as
-// [attribute][slot][cell].
-constexpr int TRI_GEO = 7;
+// Triangle meshes: per cell the neighbour of each of its three face slots (-(1 + bc) on a
+// boundary face) and TRI_GEO_ROWS rows of geometry, each an [ncell] array:
+//   TG_NX + k, TG_NY + k   outward unit normal of slot k, k = 0..2 (the two cells of a face store
+//                          exact negatives)
+//   TG_LW + k              |l_k| / |Omega|
+//   TG_AX + k, TG_AY + k   x_s - x_i, the midpoint of slot k minus the cell's centroid, k = 0, 1
+//                          (slot 2: minus their sum, as the three offsets of a triangle add to zero)
+//   TG_BX + k, TG_BY + k   x_s - x_nb, the midpoint minus the neighbour's centroid (0 on boundary
+//                          faces), k = 0..2
+constexpr int TG_NX = 0, TG_NY = 3, TG_LW = 6, TG_AX = 9, TG_AY = 11, TG_BX = 13, TG_BY = 16, TRI_GEO_ROWS = 19;
 struct TriGeometry {
     int64_t ncell = 0;
     std::vector<int32_t> nb;     // [3][ncell]
-    std::vector<double> geo;     // [TRI_GEO][3][ncell]
+    std::vector<double> geo;     // [TRI_GEO_ROWS][ncell]
     std::vector<double> area;    // [ncell]
     double rmin = 0;             // smallest inradius 2|Omega| / perimeter
 };
@@ -97,7 +102,7 @@ struct TriArgs {
     T *grad;              // scratch [batch][ncell][6]: d/dx (Ez Hx Hy), d/dy (Ez Hx Hy) per cell
     int32_t ncell, batch;
     const int32_t *nb;    // device [3][ncell]
-    const T *geo;         // device [TRI_GEO][3][ncell]
+    const T *geo;         // device [TRI_GEO_ROWS][ncell]
     const FaceOpTM<T> *op;   // device: the face operator (face-frame inputs, PatTri)
 };
 template <typename T> int launch_tri_step(const TriArgs<T> &a, void *stream);

@@ -3,12 +3,13 @@
 // Every cell owns its three faces in the kernels (each face is evaluated by both of its cells,
 // each from its own side with its own outward normal: the flux of a face seen from the other
 // side is the negative, which the lattice's half-turn symmetry guarantees), so the geometry is
-// stored per cell and face slot, structure of arrays [attribute][slot][cell]:
+// stored per cell and face slot (layout in gks_internal.h):
 //   nb     neighbour cell, or -(1 + bc) on a boundary face (non-reflecting or PEC)
-//   nx, ny outward unit normal of the face
+//   n      outward unit normal
 //   lw     |l_s| / |Omega_i|
-//   ax, ay x_s - x_i   (face midpoint minus the cell centroid: the cell's reconstruction)
-//   bx, by x_s - x_nb  (the same for the neighbour; 0 on boundary faces)
+//   a      x_s - x_i   (face midpoint minus the cell centroid: the cell's reconstruction), slots
+//          0 and 1 only: the offsets of the three midpoints from the centroid add to zero
+//   b      x_s - x_nb  (the same for the neighbour; 0 on boundary faces)
 // Everything is computed in double precision (Sec. 3.1: Green-Gauss gradients, reconstruction
 // at the face midpoint).
 #include <cmath>
@@ -64,9 +65,9 @@ bool build_tri_geometry(const gks_mesh_desc *m, TriGeometry &g, char *err, size_
     std::vector<int32_t> count(nc, 0);
     g.ncell = nc;
     g.nb.assign(3 * nc, 0);
-    g.geo.assign((size_t)TRI_GEO * 3 * nc, 0.0);
+    g.geo.assign((size_t)TRI_GEO_ROWS * nc, 0.0);
     std::vector<double> perim(nc, 0.0);
-    auto G = [&](int attr, int slot, int64_t c) -> double & { return g.geo[((size_t)attr * 3 + slot) * nc + c]; };
+    auto G = [&](int row, int64_t c) -> double & { return g.geo[(size_t)row * nc + c]; };
     for (int64_t s = 0; s < nf; ++s) {
         const int32_t L = m->face_cells[2 * s], R = m->face_cells[2 * s + 1];
         const int32_t v0 = m->face_verts[2 * s], v1 = m->face_verts[2 * s + 1];
@@ -102,13 +103,15 @@ bool build_tri_geometry(const gks_mesh_desc *m, TriGeometry &g, char *err, size_
             const int k = count[c]++;
             const double sg = side == 0 ? 1.0 : -1.0;
             g.nb[(size_t)k * nc + c] = other;
-            G(0, k, c) = sg * nx;
-            G(1, k, c) = sg * ny;
-            G(2, k, c) = len / area[c];
-            G(3, k, c) = mx - cx[c];
-            G(4, k, c) = my - cy[c];
-            G(5, k, c) = other >= 0 ? mx - cx[other] : 0.0;
-            G(6, k, c) = other >= 0 ? my - cy[other] : 0.0;
+            G(TG_NX + k, c) = sg * nx;
+            G(TG_NY + k, c) = sg * ny;
+            G(TG_LW + k, c) = len / area[c];
+            if (k < 2) {
+                G(TG_AX + k, c) = mx - cx[c];
+                G(TG_AY + k, c) = my - cy[c];
+            }
+            G(TG_BX + k, c) = other >= 0 ? mx - cx[other] : 0.0;
+            G(TG_BY + k, c) = other >= 0 ? my - cy[other] : 0.0;
             perim[c] += len;
         }
     }

@@ -67,8 +67,8 @@ __global__ __launch_bounds__(TRI_BLOCK) void tri_grad_kernel(TriArgs<T> a)
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int32_t nb = a.nb[k * nc + i];
-        const T nx = a.geo[(0 * 3 + k) * nc + i], ny = a.geo[(1 * 3 + k) * nc + i];
-        const T lw = a.geo[(2 * 3 + k) * nc + i];
+        const T nx = a.geo[(TG_NX + k) * nc + i], ny = a.geo[(TG_NY + k) * nc + i];
+        const T lw = a.geo[(TG_LW + k) * nc + i];
         T v[3];
         if (nb >= 0) {
 #pragma unroll
@@ -118,12 +118,16 @@ __global__ __launch_bounds__(TRI_BLOCK) void tri_step_kernel(TriArgs<T> a)
     load_grad(Gr, i, gx, gy);
     const T mE = HAS_EPS ? E[i] : T(1), mH = HAS_MU ? M[i] : T(1);
     T div[3] = {T(0), T(0), T(0)};
+    // midpoint offsets of slots 0 and 1; slot 2's is minus their sum
+    const T ax01[2] = {a.geo[(TG_AX + 0) * nc + i], a.geo[(TG_AX + 1) * nc + i]};
+    const T ay01[2] = {a.geo[(TG_AY + 0) * nc + i], a.geo[(TG_AY + 1) * nc + i]};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int32_t nb = a.nb[k * nc + i];
-        const T nx = a.geo[(0 * 3 + k) * nc + i], ny = a.geo[(1 * 3 + k) * nc + i];
-        const T lw = a.geo[(2 * 3 + k) * nc + i];
-        const T ax = a.geo[(3 * 3 + k) * nc + i], ay = a.geo[(4 * 3 + k) * nc + i];
+        const T nx = a.geo[(TG_NX + k) * nc + i], ny = a.geo[(TG_NY + k) * nc + i];
+        const T lw = a.geo[(TG_LW + k) * nc + i];
+        const T ax = k < 2 ? ax01[k < 2 ? k : 0] : -(ax01[0] + ax01[1]);
+        const T ay = k < 2 ? ay01[k < 2 ? k : 0] : -(ay01[0] + ay01[1]);
         // own side: reconstruction at the midpoint, slopes along n and t, all in the face frame
         T w[18];
         {
@@ -147,7 +151,7 @@ __global__ __launch_bounds__(TRI_BLOCK) void tri_step_kernel(TriArgs<T> a)
         }
         T mEs, mHs;
         if (nb >= 0) {
-            const T bx = a.geo[(5 * 3 + k) * nc + i], by = a.geo[(6 * 3 + k) * nc + i];
+            const T bx = a.geo[(TG_BX + k) * nc + i], by = a.geo[(TG_BY + k) * nc + i];
             T ur[3], dn[3], dt[3], hxs[3], hys[3];
             load_grad(Gr, nb, hxs, hys);
 #pragma unroll
