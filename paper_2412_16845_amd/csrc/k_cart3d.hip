@@ -14,9 +14,12 @@
 //      next lane's data by DPP) and below it in z (from the previous plane kept in registers);
 //   4. shares the y fluxes and finishes the flux divergence of each cell of plane q-1, adding
 //      it to the old value in double precision with a single rounding on store.
-// Each face is evaluated once; each field value is loaded once per workgroup.  The three LDS
-// slots (fields, differences and materials, y fluxes) are single-buffered: the barriers of
-// one plane order every read of a slot before the next plane's write to it.
+// Each face is evaluated once; each field value is loaded once per workgroup.  In fp32 the
+// fields are double-buffered by plane parity (the next plane's fields are written before the
+// last barrier of the current one), which leaves two barriers per plane; in fp64 they are
+// single-buffered and shared at the start of the plane (three barriers).  The differences and
+// materials and the y fluxes are single-buffered, each slot's reads ordered before the next
+// plane's write by a barrier.
 // Boundaries follow the 2D kernel: ghost cells read the wrapped (periodic), mirrored (PEC:
 // tangential E and normal H odd) or clamped (non-reflecting) cell; the ghost side of a
 // non-reflecting boundary face carries no distribution (zero state and slopes).
@@ -43,7 +46,10 @@ struct Plane3 {
 template <typename T>
 struct Lds3 {
     static constexpr int R = rows3d<T>();
-    T u[6][R][WAVE];      // fields of the current plane
+    // fields of the current plane: double-buffered by plane parity in fp32 (one barrier per plane
+    // fewer); single in fp64, whose registers cannot also hold the next plane's fields that long
+    static constexpr int NU = sizeof(T) == 4 ? 2 : 1;
+    T u[NU][6][R][WAVE];
     T g[20][R][WAVE];     // differences [x(6) y(6) z(6)] and mE, mH
     T p[6][R][WAVE];      // flux of the face above each cell (y)
 };
@@ -99,16 +105,21 @@ struct March3D {
         // plane q+2 (beyond the range: re-read the last halo plane, already cached, so that the
         // load stays unconditional)
         load(min(q + 2, z1 + 1), D);
+        constexpr int NU = Lds3<T>::NU;
+        if constexpr (NU == 1) {
 #pragma unroll
-        for (int f = 0; f < 6; ++f) s.u[f][row][lane] = B.u[f];
-        __syncthreads();
+            for (int f = 0; f < 6; ++f) s.u[0][f][row][lane] = B.u[f];
+            __syncthreads();
+        }
+        // (double-buffered: the fields of plane q were shared at the end of the previous step)
+        const int cu = NU == 2 ? (q & 1) : 0;
         T uy[6];   // fields of the row above (plane q)
         if (need_g) {
 #pragma unroll
             for (int f = 0; f < 6; ++f) {
-                uy[f] = s.u[f][rowp][lane];
+                uy[f] = s.u[cu][f][rowp][lane];
                 G[f] = from_right(B.u[f]) - from_left(B.u[f]);
-                G[6 + f] = uy[f] - s.u[f][rowm][lane];
+                G[6 + f] = uy[f] - s.u[cu][f][rowm][lane];
                 G[12 + f] = C.u[f] - A.u[f];
             }
             // every face that reads the differences of a non-reflecting ghost zeroes them:
@@ -202,6 +213,13 @@ struct March3D {
             }
             apply_op<PatEMx>(w, B.mE + from_right(B.mE), B.mH + from_right(B.mH), opx, px);
         }
+        if constexpr (NU == 2) {
+            // share the fields of plane q+1 in the other buffer (its last readers, in the
+            // previous step, are all past this step's first barrier); the barrier below
+            // publishes them with the y fluxes
+#pragma unroll
+            for (int f = 0; f < 6; ++f) s.u[cu ^ 1][f][row][lane] = C.u[f];
+        }
         __syncthreads();
         if (outp && need_all) {
 #pragma unroll
@@ -221,6 +239,11 @@ struct March3D {
         load(qs - 1, P0);
         load(qs, P1);
         load(qs + 1, P2);
+        if constexpr (Lds3<T>::NU == 2) {
+#pragma unroll
+            for (int f = 0; f < 6; ++f) s.u[qs & 1][f][row][lane] = P1.u[f];
+            __syncthreads();
+        }
         const int n = z1 - z0 + 2;   // central planes z0-1 .. z1
         for (int i = 0; i < n; i += 4) {
             step(qs + i, P0, P1, P2, P3, G1, G0, acc);
