@@ -25,6 +25,8 @@
  *    e^{-t/tau} (the printed C4, C5 are the integrals of that reading).
  *  - Cell gradients: Green-Gauss with the arithmetic face value (Sec. 3.1); ghost values
  *    for the gradient: non-reflecting -> the cell's own value, PEC -> the mirror state.
+ *    Optionally least squares over the face neighbours (Sec. 3.1 allows other gradients), with
+ *    each boundary ghost placed at the mirror image of the cell centroid across the face.
  *  - Non-reflecting boundary (Sec. 3.1, last paragraph): the ghost-side distributions are
  *    zero, i.e. the right state and its slopes vanish in the face frame.
  *  - PEC boundary (Sec. 5.5 conditions): mirror ghost in the face frame, even normal E and
@@ -60,6 +62,7 @@ typedef struct {
     double c;      /* lattice speed = speed of light */
     double dt;     /* time step */
     double C[5];   /* time-integrated coefficients C1..C5 */
+    int32_t gradient; /* 0: Green-Gauss (the paper's), 1: least squares */
 } orc_params;
 
 /* ---------------------------------------------------------------- physics (Sec. 2.1) */
@@ -278,6 +281,67 @@ static void gradients(const orc_mesh *m, const double *U, double *grad)
     }
 }
 
+/* Least-squares cell gradients, the "other" reconstruction gradient Sec. 3.1 allows: grad U_i
+ * minimises sum_j |U_i + grad U_i . d_j - U_j|^2 over the face neighbours j of cell i, with
+ * d_j = x_j - x_i.  A boundary face contributes its ghost state (the same ghost as for
+ * Green-Gauss) placed at the mirror image of x_i across the face, d = 2 ((x_s - x_i) . n) n.
+ * The normal equations (sum_j d_j d_j^T) g = sum_j d_j (U_j - U_i) are solved by Cramer's rule,
+ * in the xy plane on 2D meshes.  grad[(i*3 + d)*6 + f]. */
+static void gradients_lsq(const orc_mesh *m, const double *U, double *grad)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m->ncells; ++i) {
+        double M[3][3], b[3][NC];
+        memset(M, 0, sizeof M);
+        memset(b, 0, sizeof b);
+        for (int64_t q = m->cf_ptr[i]; q < m->cf_ptr[i + 1]; ++q) {
+            const int64_t s = m->cf_idx[q];
+            const double *n = m->normal + 3 * s, *dL = m->dL + 3 * s, *dR = m->dR + 3 * s;
+            const int64_t L = m->face_L[s], R = m->face_R[s];
+            double d[3], Unb[NC];
+            if (L == i && R >= 0) {          /* neighbour across the face: x_R - x_i */
+                for (int k = 0; k < 3; ++k) d[k] = dL[k] - dR[k];
+                memcpy(Unb, U + NC * R, sizeof Unb);
+            } else if (L == i) {             /* boundary: the ghost at the mirror point */
+                const double h = dL[0] * n[0] + dL[1] * n[1] + dL[2] * n[2];
+                for (int k = 0; k < 3; ++k) d[k] = 2.0 * h * n[k];
+                ghost_state((int)(-R - 1), n, U + NC * i, Unb);
+            } else {                         /* this cell is the face's neighbour: x_L - x_i */
+                for (int k = 0; k < 3; ++k) d[k] = dR[k] - dL[k];
+                memcpy(Unb, U + NC * L, sizeof Unb);
+            }
+            for (int r = 0; r < 3; ++r) {
+                for (int c = 0; c < 3; ++c) M[r][c] += d[r] * d[c];
+                for (int f = 0; f < NC; ++f) b[r][f] += d[r] * (Unb[f] - U[NC * i + f]);
+            }
+        }
+        double g[3][NC];
+        memset(g, 0, sizeof g);
+        if (m->dim == 2) {
+            const double det = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+            for (int f = 0; f < NC; ++f) {
+                g[0][f] = (b[0][f] * M[1][1] - M[0][1] * b[1][f]) / det;
+                g[1][f] = (M[0][0] * b[1][f] - b[0][f] * M[1][0]) / det;
+            }
+        } else {
+            const double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                               M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                               M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+            for (int f = 0; f < NC; ++f)
+                for (int k = 0; k < 3; ++k) {   /* Cramer: column k replaced by b */
+                    double A[3][3];
+                    for (int r = 0; r < 3; ++r)
+                        for (int c = 0; c < 3; ++c) A[r][c] = (c == k) ? b[r][f] : M[r][c];
+                    g[k][f] = (A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                               A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                               A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0])) / det;
+                }
+        }
+        for (int k = 0; k < 3; ++k)
+            for (int f = 0; f < NC; ++f) grad[(i * 3 + k) * NC + f] = g[k][f];
+    }
+}
+
 /* Numerical flux of every face in the global frame (normal flux along n, L -> R). */
 static void face_fluxes(const orc_mesh *m, const orc_params *p, const double *U, const double *grad,
                         const double *epsinv, const double *muinv, double *flux)
@@ -362,7 +426,8 @@ int orc_step(const orc_mesh *m, const orc_params *p, const double *U, double *Un
     double *grad = malloc(sizeof(double) * (size_t)m->ncells * 3 * NC);
     double *flux = malloc(sizeof(double) * (size_t)m->nfaces * NC);
     if (!grad || !flux) { free(grad); free(flux); return -1; }
-    gradients(m, U, grad);
+    if (p->gradient == 1) gradients_lsq(m, U, grad);
+    else gradients(m, U, grad);
     face_fluxes(m, p, U, grad, epsinv, muinv, flux);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < m->ncells; ++i) {
@@ -415,3 +480,4 @@ void orc_rotation(const double *n, double *T /*[9]*/)
     memcpy(T, TT, sizeof TT);
 }
 void orc_gradients(const orc_mesh *m, const double *U, double *grad) { gradients(m, U, grad); }
+void orc_gradients_lsq(const orc_mesh *m, const double *U, double *grad) { gradients_lsq(m, U, grad); }
