@@ -296,12 +296,12 @@ C4_H, C4_STEPS = 6.8e-4, 2000
 
 def tri_bytes_per_cell(prec):
     """Compulsory bytes per cell-update of the triangle step with its stored geometry (vacuum):
-    gradient kernel: fields, 3 neighbour ids, 3 x (normal, |l|/|Omega|), write 6 gradients;
+    gradient kernel: fields, 3 neighbour ids, 3 gradient weight vectors, write 6 gradients;
     face/update kernel: fields, 6 gradients, 3 neighbour ids, 19 geometry values (3 x normal,
     |l|/|Omega|, midpoint minus the neighbour's centroid; 2 midpoint offsets), write fields
     (the neighbours' fields and gradients are gathered from cache)."""
     e = 8 if prec == "fp64" else 4
-    grad = 3 * e + 3 * 4 + 9 * e + 6 * e
+    grad = 3 * e + 3 * 4 + 6 * e + 6 * e
     step = 3 * e + 6 * e + 3 * 4 + 19 * e + 3 * e
     return grad + step
 

@@ -49,6 +49,7 @@ typedef enum { GKS_CART2D = 0, GKS_CART3D = 1, GKS_TRI2D = 2 } gks_mesh_kind;
 typedef enum { GKS_TM2D = 0, GKS_EM3D = 1 } gks_model;
 typedef enum { GKS_BC_PERIODIC = 0, GKS_BC_NONREFLECT = 1, GKS_BC_PEC = 2 } gks_bc;
 typedef enum { GKS_FP64 = 0, GKS_FP32 = 1 } gks_precision;
+typedef enum { GKS_GRAD_GREEN_GAUSS = 0, GKS_GRAD_LSQ = 1 } gks_gradient;
 
 /*
  * Mesh description (host memory; copied by gks_init_mesh, not retained).
@@ -89,6 +90,13 @@ typedef struct {
  *   energy_every: gks_run records the energy every this many steps (0 = never).
  *   unstable_growth: gks_run fails with GKS_EUNSTABLE when a recorded energy exceeds this
  *                 factor times the first recorded one (0 = no check).
+ *   gradient:     cell gradients of the reconstruction (Sec. 3.1 uses Green-Gauss and allows
+ *                 others).  GKS_GRAD_GREEN_GAUSS: (1/|Omega_i|) sum_s (U_nb - U_i)/2 n_s |l_s|.
+ *                 GKS_GRAD_LSQ: the least-squares fit to the face neighbours, each boundary
+ *                 ghost (the same ghost state) placed at the mirror image of the cell centroid
+ *                 across the face; it is exact for linear fields on any triangle mesh.  On
+ *                 Cartesian grids both give the central difference, and both values are
+ *                 accepted.  Other values: GKS_EINVAL.
  */
 typedef struct {
     double c;
@@ -97,6 +105,7 @@ typedef struct {
     double tau_over_dt;
     int32_t energy_every;
     double unstable_growth;
+    int32_t gradient;
 } gks_params;
 
 /* Creates a context on the current HIP device.  hip_stream: a hipStream_t (NULL = the null

@@ -428,6 +428,8 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
     if (!(p->tau_over_dt >= 0)) return fail(nullptr, GKS_EINVAL, "tau_over_dt must be >= 0");
     if (p->energy_every < 0) return fail(nullptr, GKS_EINVAL, "energy_every must be >= 0");
     if (!(p->unstable_growth >= 0)) return fail(nullptr, GKS_EINVAL, "unstable_growth must be >= 0");
+    if (p->gradient != GKS_GRAD_GREEN_GAUSS && p->gradient != GKS_GRAD_LSQ)
+        return fail(nullptr, GKS_EINVAL, "gradient %d is neither Green-Gauss (0) nor least squares (1)", p->gradient);
 
     TriGeometry tri;
     gks_ctx *x = new (std::nothrow) gks_ctx();
@@ -486,7 +488,7 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
     } else if (m->kind == GKS_TRI2D) {
         if (m->model != GKS_TM2D) return bail(fail(x, GKS_EINVAL, "triangle meshes carry TM2D fields"));
         char err[256];
-        if (!build_tri_geometry(m, tri, err, sizeof err)) return bail(fail(x, GKS_EINVAL, "%s", err));
+        if (!build_tri_geometry(m, p->gradient, tri, err, sizeof err)) return bail(fail(x, GKS_EINVAL, "%s", err));
         x->ncell = m->ncells;
         x->n[0] = m->ncells;
         x->nfields = 3;

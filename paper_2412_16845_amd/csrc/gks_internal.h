@@ -83,7 +83,12 @@ struct Cart3DArgs {
 //                          (slot 2: minus their sum, as the three offsets of a triangle add to zero)
 //   TG_BX + k, TG_BY + k   x_s - x_nb, the midpoint minus the neighbour's centroid (0 on boundary
 //                          faces), k = 0..2
-constexpr int TG_NX = 0, TG_NY = 3, TG_LW = 6, TG_AX = 9, TG_AY = 11, TG_BX = 13, TG_BY = 16, TRI_GEO_ROWS = 19;
+//   TG_WX + k, TG_WY + k   gradient weight of slot k: grad U_i = sum_k W_k (U_k - U_i), with U_k
+//                          the neighbour or the boundary ghost (Green-Gauss: W_k = n_k |l_k| /
+//                          (2 |Omega|); least squares: W_k = M^-1 d_k, M = sum_k d_k d_k^T, d_k the
+//                          neighbour's centroid or the centroid's mirror image minus x_i)
+constexpr int TG_NX = 0, TG_NY = 3, TG_LW = 6, TG_AX = 9, TG_AY = 11, TG_BX = 13, TG_BY = 16, TG_WX = 19, TG_WY = 22;
+constexpr int TRI_GEO_ROWS = 25;
 struct TriGeometry {
     int64_t ncell = 0;
     std::vector<int32_t> nb;     // [3][ncell]
@@ -91,7 +96,7 @@ struct TriGeometry {
     std::vector<double> area;    // [ncell]
     double rmin = 0;             // smallest inradius 2|Omega| / perimeter
 };
-bool build_tri_geometry(const gks_mesh_desc *m, TriGeometry &g, char *err, size_t errlen);
+bool build_tri_geometry(const gks_mesh_desc *m, int gradient, TriGeometry &g, char *err, size_t errlen);
 
 template <typename T>
 struct TriArgs {

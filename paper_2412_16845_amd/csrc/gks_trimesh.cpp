@@ -10,6 +10,10 @@
 //   a      x_s - x_i   (face midpoint minus the cell centroid: the cell's reconstruction), slots
 //          0 and 1 only: the offsets of the three midpoints from the centroid add to zero
 //   b      x_s - x_nb  (the same for the neighbour; 0 on boundary faces)
+//   W      gradient weights, grad U_i = sum_k W_k (U_k - U_i) over the neighbours or boundary
+//          ghosts: Green-Gauss (n |l| / (2 |Omega|)) or the least-squares fit (M^-1 d_k, with
+//          d_k the neighbour's centroid, or the centroid's mirror image across a boundary face,
+//          minus x_i, and M = sum_k d_k d_k^T)
 // Everything is computed in double precision (Sec. 3.1: Green-Gauss gradients, reconstruction
 // at the face midpoint).
 #include <cmath>
@@ -20,7 +24,7 @@
 
 namespace gks {
 
-bool build_tri_geometry(const gks_mesh_desc *m, TriGeometry &g, char *err, size_t errlen)
+bool build_tri_geometry(const gks_mesh_desc *m, int gradient, TriGeometry &g, char *err, size_t errlen)
 {
     const int64_t nv = m->nverts, nc = m->ncells, nf = m->nfaces;
     if (nv < 3 || nc < 1 || nf < 3) {
@@ -67,6 +71,7 @@ bool build_tri_geometry(const gks_mesh_desc *m, TriGeometry &g, char *err, size_
     g.nb.assign(3 * nc, 0);
     g.geo.assign((size_t)TRI_GEO_ROWS * nc, 0.0);
     std::vector<double> perim(nc, 0.0);
+    std::vector<double> am((size_t)6 * nc, 0.0);   // x_s - x_i of every slot: [slot][x|y][cell]
     auto G = [&](int row, int64_t c) -> double & { return g.geo[(size_t)row * nc + c]; };
     for (int64_t s = 0; s < nf; ++s) {
         const int32_t L = m->face_cells[2 * s], R = m->face_cells[2 * s + 1];
@@ -110,6 +115,8 @@ bool build_tri_geometry(const gks_mesh_desc *m, TriGeometry &g, char *err, size_
                 G(TG_AX + k, c) = mx - cx[c];
                 G(TG_AY + k, c) = my - cy[c];
             }
+            am[((size_t)k * 2 + 0) * nc + c] = mx - cx[c];
+            am[((size_t)k * 2 + 1) * nc + c] = my - cy[c];
             G(TG_BX + k, c) = other >= 0 ? mx - cx[other] : 0.0;
             G(TG_BY + k, c) = other >= 0 ? my - cy[other] : 0.0;
             perim[c] += len;
@@ -122,6 +129,43 @@ bool build_tri_geometry(const gks_mesh_desc *m, TriGeometry &g, char *err, size_
             return false;
         }
         rmin = std::min(rmin, 2.0 * area[c] / perim[c]);
+        // gradient weights: grad U_c = sum_k W_k (U_k - U_c)
+        double d[3][2], W[3][2];
+        for (int k = 0; k < 3; ++k) {
+            const double nx = G(TG_NX + k, c), ny = G(TG_NY + k, c);
+            const double ax = am[((size_t)k * 2 + 0) * nc + c], ay = am[((size_t)k * 2 + 1) * nc + c];
+            if (g.nb[(size_t)k * nc + c] >= 0) {   // the neighbour's centroid: (x_s - x_c) - (x_s - x_nb)
+                d[k][0] = ax - G(TG_BX + k, c);
+                d[k][1] = ay - G(TG_BY + k, c);
+            } else {                                // the centroid's mirror image across the face
+                const double hn = ax * nx + ay * ny;
+                d[k][0] = 2.0 * hn * nx;
+                d[k][1] = 2.0 * hn * ny;
+            }
+            W[k][0] = 0.5 * G(TG_LW + k, c) * nx;   // Green-Gauss
+            W[k][1] = 0.5 * G(TG_LW + k, c) * ny;
+        }
+        if (gradient == GKS_GRAD_LSQ) {
+            double M00 = 0, M01 = 0, M11 = 0;
+            for (int k = 0; k < 3; ++k) {
+                M00 += d[k][0] * d[k][0];
+                M01 += d[k][0] * d[k][1];
+                M11 += d[k][1] * d[k][1];
+            }
+            const double det = M00 * M11 - M01 * M01;
+            if (!(det > 1e-14 * (M00 * M11))) {
+                std::snprintf(err, errlen, "cell %lld: least-squares gradient fit is singular", (long long)c);
+                return false;
+            }
+            for (int k = 0; k < 3; ++k) {
+                W[k][0] = (M11 * d[k][0] - M01 * d[k][1]) / det;
+                W[k][1] = (M00 * d[k][1] - M01 * d[k][0]) / det;
+            }
+        }
+        for (int k = 0; k < 3; ++k) {
+            G(TG_WX + k, c) = W[k][0];
+            G(TG_WY + k, c) = W[k][1];
+        }
     }
     g.area = std::move(area);
     g.rmin = rmin;

@@ -3,9 +3,10 @@
 // Two kernels, one thread per cell (cells in Hilbert order, so the neighbours a thread gathers
 // are mostly cached; consecutive blocks are renumbered onto one XCD, so that a block's
 // neighbouring blocks share its L2):
-//   1. Green-Gauss gradients (Sec. 3.1): grad U_i = sum_s (U_nb - U_i)/2 n_s |l_s| / |Omega_i|,
-//      with the ghost of a non-reflecting face equal to the cell itself and the ghost of a PEC
-//      face its mirror image (Ez and the normal H odd);
+//   1. cell gradients grad U_i = sum_s W_s (U_s - U_i) over the three faces, with host weights:
+//      Green-Gauss (Sec. 3.1, W_s = n_s |l_s| / (2 |Omega_i|)) or the least-squares fit; the
+//      ghost of a non-reflecting face equals the cell itself, the ghost of a PEC face is its
+//      mirror image (Ez and the normal H odd);
 //   2. the cell's three faces and its update: each face is reconstructed at its midpoint from
 //      both sides, rotated into its frame (printed rotation of Sec. 3.1: local axes n and
 //      (-n_y, n_x)), evaluated as a sparse linear form of the face-frame states and slopes (the
@@ -67,26 +68,26 @@ __global__ __launch_bounds__(TRI_BLOCK) void tri_grad_kernel(TriArgs<T> a)
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int32_t nb = a.nb[k * nc + i];
-        const T nx = a.geo[(TG_NX + k) * nc + i], ny = a.geo[(TG_NY + k) * nc + i];
-        const T lw = a.geo[(TG_LW + k) * nc + i];
-        T v[3];
+        const T wx = a.geo[(TG_WX + k) * nc + i], wy = a.geo[(TG_WY + k) * nc + i];
+        T d[3];   // U_k - U_i: the neighbour, or the ghost of a boundary face
         if (nb >= 0) {
 #pragma unroll
-            for (int f = 0; f < 3; ++f) v[f] = U[f * nc + nb];
+            for (int f = 0; f < 3; ++f) d[f] = U[f * nc + nb] - u[f];
         } else if (nb == -(1 + GKS_BC_PEC)) {
+            // mirror ghost: Ez and the normal H odd, the tangential H even
+            const T nx = a.geo[(TG_NX + k) * nc + i], ny = a.geo[(TG_NY + k) * nc + i];
             const T hn = u[1] * nx + u[2] * ny;
-            v[0] = -u[0];
-            v[1] = u[1] - T(2) * hn * nx;
-            v[2] = u[2] - T(2) * hn * ny;
-        } else {
+            d[0] = T(-2) * u[0];
+            d[1] = T(-2) * hn * nx;
+            d[2] = T(-2) * hn * ny;
+        } else {   // non-reflecting: the ghost repeats the cell
 #pragma unroll
-            for (int f = 0; f < 3; ++f) v[f] = u[f];
+            for (int f = 0; f < 3; ++f) d[f] = T(0);
         }
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            const T d = T(0.5) * (v[f] - u[f]) * lw;
-            gx[f] = fma(d, nx, gx[f]);
-            gy[f] = fma(d, ny, gy[f]);
+            gx[f] = fma(wx, d[f], gx[f]);
+            gy[f] = fma(wy, d[f], gy[f]);
         }
     }
     store_grad(a.grad + (int64_t)b * 6 * nc, i, gx, gy);

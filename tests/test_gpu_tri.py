@@ -31,39 +31,45 @@ def dev(torch, a, precision):
                         device="cuda")
 
 
-def solver(torch, mesh4, precision, batch, tau_hat, ei=None, mi=None, cells=(), w=()):
+def solver(torch, mesh4, precision, batch, tau_hat, ei=None, mi=None, cells=(), w=(), gradient="green_gauss"):
     from paper_2412_16845_amd.gks import Solver
-    s = Solver("tri2d", tri=mesh4, precision=precision, batch=batch, cfl=0.5, tau_over_dt=tau_hat)
+    s = Solver("tri2d", tri=mesh4, precision=precision, batch=batch, cfl=0.5, tau_over_dt=tau_hat,
+               gradient=gradient)
     s.set_material(dev(torch, ei, precision), dev(torch, mi, precision))
     if len(cells):
         s.set_point_source(cells, w, *SRC)
     return s
 
 
-def oracle_tri(mesh4, U0, nsteps, dt, tau, ei=None, mi=None, source=None, t0=0.0):
+def oracle_tri(mesh4, U0, nsteps, dt, tau, ei=None, mi=None, source=None, t0=0.0, gradient=O.GRAD_GREEN_GAUSS):
     mesh = O.tri_mesh(*mesh4)
     out = []
     for b in range(U0.shape[0]):
         U = O.from_soa(U0[b], "tm2d")
         e = None if ei is None else ei[b]
         m = None if mi is None else mi[b]
-        out.append(O.to_soa(O.run(mesh, U, nsteps, dt, tau, epsinv=e, muinv=m, source=source, t0=t0), "tm2d"))
+        out.append(O.to_soa(O.run(mesh, U, nsteps, dt, tau, epsinv=e, muinv=m, source=source, t0=t0,
+                                  gradient=gradient), "tm2d"))
     return np.stack(out)
 
 
 CASES = {
-    # name: (mesh, batch, tau_hat, eps, mu, sources, steps)
-    "ellipse_eps_mu_src": (lambda: I.tri_ellipse_mesh(0.03, seed=1, cache=False), 2, 0.01, True, True, 2, 30),
-    "ellipse_vacuum_tau0": (lambda: I.tri_ellipse_mesh(0.035, seed=2, cache=False), 1, 0.0, False, False, 0, 25),
-    "ellipse_tau_inf": (lambda: I.tri_ellipse_mesh(0.035, seed=4, cache=False), 1, np.inf, True, False, 1, 25),
-    "pec_square_mu": (lambda: square_tri_mesh(17), 1, 1.0, False, True, 0, 20),
+    # name: (mesh, batch, tau_hat, eps, mu, sources, steps, gradient)
+    "ellipse_eps_mu_src": (lambda: I.tri_ellipse_mesh(0.03, seed=1, cache=False), 2, 0.01, True, True, 2, 30, "green_gauss"),
+    "ellipse_vacuum_tau0": (lambda: I.tri_ellipse_mesh(0.035, seed=2, cache=False), 1, 0.0, False, False, 0, 25, "green_gauss"),
+    "ellipse_tau_inf": (lambda: I.tri_ellipse_mesh(0.035, seed=4, cache=False), 1, np.inf, True, False, 1, 25, "green_gauss"),
+    "pec_square_mu": (lambda: square_tri_mesh(17), 1, 1.0, False, True, 0, 20, "green_gauss"),
+    # least-squares gradients: the same meshes (PEC ellipse, non-reflecting outer square)
+    "ellipse_lsq_eps_mu_src": (lambda: I.tri_ellipse_mesh(0.03, seed=5, cache=False), 2, 0.01, True, True, 2, 30, "lsq"),
+    "pec_square_lsq": (lambda: square_tri_mesh(15), 1, np.inf, True, False, 0, 20, "lsq"),
 }
+GRAD = {"green_gauss": O.GRAD_GREEN_GAUSS, "lsq": O.GRAD_LSQ}
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_tri_parity(torch, name, precision):
-    make, batch, tau_hat, eps, mu, nsrc, nsteps = CASES[name]
+    make, batch, tau_hat, eps, mu, nsrc, nsteps, gradient = CASES[name]
     mesh4 = make()
     nc = mesh4[1].shape[0]
     rng = np.random.default_rng(len(name))
@@ -72,11 +78,11 @@ def test_tri_parity(torch, name, precision):
     mi = rng.uniform(0.5, 1.0, (batch, nc)) if mu else None
     cells = np.sort(rng.choice(nc, nsrc, replace=False)) if nsrc else np.zeros(0, dtype=np.int64)
     w = rng.uniform(0.5, 1.5, nsrc)
-    s = solver(torch, mesh4, precision, batch, tau_hat, ei, mi, cells, w)
+    s = solver(torch, mesh4, precision, batch, tau_hat, ei, mi, cells, w, gradient)
     U = dev(torch, U0, precision)
     s.run(U, nsteps)
     src = (cells, w) + SRC if nsrc else None
-    ref = oracle_tri(mesh4, U0, nsteps, s.dt, tau_hat * s.dt, ei, mi, src)
+    ref = oracle_tri(mesh4, U0, nsteps, s.dt, tau_hat * s.dt, ei, mi, src, gradient=GRAD[gradient])
     err = rel_l2(U.cpu().numpy(), ref)
     print(f"{name} {precision}: rel L2 = {err:.3e} ({nc} cells, {nsteps} steps, dt {s.dt:.3e})")
     assert err <= TOL[precision]
