@@ -23,7 +23,7 @@ import torch
 
 from .gks import Solver
 
-__all__ = ["run", "probe_energy", "GKSRun", "ProbeEnergy"]
+__all__ = ["run", "probe_energy", "GKSFunction", "GKSRun", "ProbeEnergy"]
 
 
 class GKSRun(torch.autograd.Function):
@@ -103,3 +103,19 @@ def run(solver: Solver, U0, nsteps: int, epsinv=None, muinv=None, t0: float = 0.
 def probe_energy(solver: Solver, U, box):
     """(batch,) float64 probe-box energies sum |Omega| Ez^2 (differentiable in U)."""
     return ProbeEnergy.apply(U, solver, box)
+
+
+class GKSFunction:
+    """The differentiable run in one call, for callers that think of it as one function:
+
+        GKSFunction.apply(solver, epsinv, muinv, U0, nsteps, t0=0.0, checkpoint_every=50, probe=None)
+
+    returns the state after ``nsteps`` steps (``run``), or, with ``probe`` a box, the (batch,)
+    probe-box energies of that state (``probe_energy``); differentiable in epsinv, muinv and U0.
+    """
+
+    @staticmethod
+    def apply(solver: Solver, epsinv, muinv, U0, nsteps: int, t0: float = 0.0, checkpoint_every: int = 50,
+              probe=None):
+        UN = run(solver, U0, nsteps, epsinv, muinv, t0, checkpoint_every)
+        return UN if probe is None else probe_energy(solver, UN, probe)

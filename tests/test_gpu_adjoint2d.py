@@ -265,6 +265,29 @@ def test_autograd_run_against_oracle(torch, precision):
     assert max(errs) <= TOL[precision]
 
 
+def test_gksfunction_is_run_then_probe(torch):
+    """The one-call form gives the same loss and gradients, bit for bit, as run + probe_energy."""
+    from paper_2412_16845_amd import autograd as AG
+    nx, ny, K = 18, 14, 5
+    rng = np.random.default_rng(41)
+    U0 = rng.standard_normal((BATCH, 3, ny, nx))
+    ei = rng.uniform(0.25, 1.0, (BATCH, ny, nx))
+    box = (6, 12, 4, 10)
+    grads = []
+    for one_call in (False, True):
+        s, E, _ = solver_for(torch, nx, ny, (N, P, N, N), 0.01, "fp64", BATCH, ei, None, (), ())
+        U = dev(torch, U0, "fp64").requires_grad_(True)
+        E.requires_grad_(True)
+        if one_call:
+            loss = AG.GKSFunction.apply(s, E, None, U, K, checkpoint_every=2, probe=box).sum()
+        else:
+            loss = AG.probe_energy(s, AG.run(s, U, K, E, None, checkpoint_every=2), box).sum()
+        loss.backward()
+        grads.append((loss.item(), U.grad.cpu().numpy(), E.grad.cpu().numpy()))
+    assert grads[0][0] == grads[1][0]
+    assert np.array_equal(grads[0][1], grads[1][1]) and np.array_equal(grads[0][2], grads[1][2])
+
+
 def test_c5_gradient_against_finite_differences(torch):
     """The differentiable workload at full size: 1024 x 1024 x 8 dielectric maps, probe-box Ez
     energy after 800 steps, reverse mode with checkpoints every 50 steps.  The FP64 gradient
