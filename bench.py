@@ -244,6 +244,34 @@ def adjoint_leg(torch):
                                  "algorithmic_bytes_per_launch": alg}}
 
 
+N_OVERSIZED = 8192
+
+
+def oversized_leg(torch):
+    """The same 2D workload on an 8192 x 8192 grid (1.9 GB per fp32 step, far above the 256 MB
+    Infinity Cache): per-launch time of the step kernel against the HBM roofline, so that the
+    4096^2 fraction can be checked not to come from cache hits."""
+    from paper_2412_16845_amd import inputs as I
+    wl = I.tm_dielectric_nr(nx=N_OVERSIZED, seed=0, nsteps=100)
+    ncell = N_OVERSIZED * N_OVERSIZED
+    out = {"workload": f"tm_dielectric_nr: 2D TM {N_OVERSIZED}x{N_OVERSIZED}, the 4096^2 recipe on a finer grid "
+                       f"(step kernel only, 100 timed launches)", "cells": ncell}
+    for prec in ("fp32", "fp64"):
+        s, U, ei = make(torch, wl, prec)
+        s.run(U, 10)
+        t_launch, _ = time_kernel(torch, s, U, launches=100)
+        if not torch.isfinite(U).all():
+            raise RuntimeError(f"oversized {prec} run produced non-finite values")
+        alg = BYTES_PER_CELL[prec] * ncell
+        out[prec] = {"cell_updates_per_s": round(ncell / t_launch, 1),
+                     "roofline": {"bound": "hbm", "achieved": round(alg / t_launch / 1e9, 1), "peak": PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(alg / t_launch / 1e9 / PEAK_GBS, 4),
+                                  "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch}}
+        del s, U, ei
+        torch.cuda.empty_cache()
+    return out
+
+
 C3_N, C3_STEPS = 384, 500
 # 3D step, algorithmic bytes per cell-update: read six fields and 1/eps, write six fields
 C3_BYTES_PER_CELL = {"fp32": 13 * 4, "fp64": 13 * 8}
@@ -352,6 +380,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-tri", action="store_true")
+    ap.add_argument("--no-oversized", action="store_true")
     ap.add_argument("--profile-kernel", choices=["fp32", "fp64"])
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -420,6 +449,9 @@ def main():
                  "ms_per_step": round(f64["seconds"] * 1e3 / args.steps, 5), "dtype": "f64",
                  "roofline": roofline("fp64", f64["t_launch"])},
     }
+    if not args.no_oversized:
+        log("[bench] oversized 2D: 8192x8192, step kernel, fp32 and fp64")
+        out["cart2d_8192"] = oversized_leg(torch)
     if not args.no_3d:
         log("[bench] 3D: 384^3 six fields, 500 steps, fp32 and fp64")
         out["cart3d"] = cart3d_leg(torch)
