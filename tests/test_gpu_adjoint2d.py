@@ -37,6 +37,11 @@ CASES = {
     "mixed2_tau0": (23, 17, (P, N, N, P), "eps_mu", 0.0, [(12, 0)]),
     "mixed2_tauinf": (23, 17, (P, N, N, P), "eps_mu", np.inf, []),
     "nr_large_tau1": (37, 29, (N, P, P, N), "eps_mu", 1.0, [(36, 28), (18, 14)]),
+    # the smallest grid the library accepts, and a grid thinner than a tile (every ghost
+    # position folds back onto the boundary band)
+    "minimum_2x2": (2, 2, (N, P, R, R), "eps_mu", 0.01, [(1, 1)]),
+    "thin_21x3": (21, 3, (P, N, N, P), "eps", 0.01, [(4, 2)]),
+    "thin_70x2_periodic_y": (70, 2, (N, P, R, R), "mu", 0.01, []),
 }
 BATCH = 2
 SRC = (1.5, 0.02, 0.01)      # J0, t0, sigma_t

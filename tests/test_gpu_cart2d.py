@@ -97,6 +97,36 @@ def test_collision_time_limits_fp64(torch, tau_hat):
     assert rel_l2(U[0].cpu().numpy(), ref) <= 1e-12
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [(2, 2), (2, 9), (7, 2), (3, 3), (5, 130), (130, 5)])
+@pytest.mark.parametrize("bc", [("periodic",) * 4, ("pec",) * 4, ("nonreflecting",) * 4,
+                                ("pec", "nonreflecting", "periodic", "periodic")])
+def test_minimum_and_thin_grids(torch, n, bc, precision):
+    """The smallest grids the library accepts (two cells along an axis) and grids narrower
+    than one strip or one tile, where every ghost index folds back into the grid."""
+    nx, ny = n
+    rng = np.random.default_rng(nx * 1000 + ny)
+    U0 = rng.standard_normal((2, 3, ny, nx))
+    U0[1] *= 0.5
+    ei = rng.uniform(0.25, 1.0, (2, ny, nx))
+    mi = rng.uniform(0.5, 1.0, (2, ny, nx))
+    wl = I.Workload("thin", "cart2d", (nx, ny), (0.0, 0.0), (1.0, 1.0), bc, U0, ei, mi, 0.5, 0.01, 12)
+    s, U = setup(torch, wl, precision)
+    s.run(U, wl.nsteps)
+    ref = np.stack([oracle_run(wl, wl.nsteps, s.dt, b=b) for b in range(2)])
+    err = rel_l2(U.cpu().numpy(), ref)
+    print(f"{n} {bc} {precision}: rel L2 = {err:.3e}")
+    assert err <= TOL[precision]
+
+
+def test_zero_steps_is_a_no_op(torch):
+    wl = I.tm_gaussian_periodic(32, nsteps=1)
+    s, U = setup(torch, wl, "fp64")
+    before = U.clone()
+    s.run(U, 0)
+    assert torch.equal(U, before)
+
+
 def test_batch_and_long_source_list_fp64(torch):
     """Batch of 3 different dielectric maps; 7 source cells (beyond the fused limit)."""
     nx, ny = 90, 75

@@ -75,6 +75,10 @@ CASES = {
                 "t0": 0.01, "sigma_t": 0.02}),
     "nr_all_batch2": lambda: random_case((18, 19, 17), (N,) * 6, seed=6, batch=2, nsteps=8),
     "mixed_nr_pec_periodic": lambda: random_case((13, 27, 11), (N, P, R, R, P, N), seed=7, mu=True, tau_hat=1.0),
+    # the smallest grid the library accepts, and grids thinner than a tile along one axis
+    "minimum_2x2x2": lambda: random_case((2, 2, 2), (P, N, R, R, N, P), seed=8, batch=2, mu=True),
+    "thin_2x3x40": lambda: random_case((2, 3, 40), (N, N, P, P, R, R), seed=9),
+    "thin_70x2x3": lambda: random_case((70, 2, 3), (R, R, N, P, P, N), seed=10, mu=True),
 }
 
 

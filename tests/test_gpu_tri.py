@@ -53,6 +53,14 @@ def oracle_tri(mesh4, U0, nsteps, dt, tau, ei=None, mi=None, source=None, t0=0.0
     return np.stack(out)
 
 
+def _one_triangle(bc):
+    verts = np.array([[0.0, 0.0], [1.0, 0.1], [0.3, 0.8]])
+    tris = np.array([[0, 1, 2]])
+    fv = np.array([[0, 1], [1, 2], [2, 0]])
+    fc = np.array([[0, -(1 + bc)]] * 3)
+    return verts, tris, fc, fv
+
+
 CASES = {
     # name: (mesh, batch, tau_hat, eps, mu, sources, steps, gradient)
     "ellipse_eps_mu_src": (lambda: I.tri_ellipse_mesh(0.03, seed=1, cache=False), 2, 0.01, True, True, 2, 30, "green_gauss"),
@@ -62,6 +70,11 @@ CASES = {
     # least-squares gradients: the same meshes (PEC ellipse, non-reflecting outer square)
     "ellipse_lsq_eps_mu_src": (lambda: I.tri_ellipse_mesh(0.03, seed=5, cache=False), 2, 0.01, True, True, 2, 30, "lsq"),
     "pec_square_lsq": (lambda: square_tri_mesh(15), 1, np.inf, True, False, 0, 20, "lsq"),
+    # the smallest meshes: one triangle with three boundary faces, and two triangles
+    "one_triangle_pec": (lambda: _one_triangle(O.BC_PEC), 2, 0.01, True, True, 0, 6, "green_gauss"),
+    "one_triangle_nr_lsq": (lambda: _one_triangle(O.BC_NONREFLECT), 1, 0.01, True, False, 1, 6, "lsq"),
+    "two_triangles": (lambda: square_tri_mesh(1), 1, 1.0, False, True, 0, 6, "green_gauss"),
+    "two_triangles_lsq": (lambda: square_tri_mesh(1), 1, 0.0, True, True, 0, 6, "lsq"),
 }
 GRAD = {"green_gauss": O.GRAD_GREEN_GAUSS, "lsq": O.GRAD_LSQ}
 
