@@ -27,6 +27,9 @@
  *    for the gradient: non-reflecting -> the cell's own value, PEC -> the mirror state.
  *    Optionally least squares over the face neighbours (Sec. 3.1 allows other gradients), with
  *    each boundary ghost placed at the mirror image of the cell centroid across the face.
+ *  - Limiter (Sec. 5, Riemann problem; its type is not given): optionally minmod of the two
+ *    one-sided differences per axis, applied to the characteristic variables along that axis
+ *    (E_a +/- H_b, E_b +/- H_a and the normal components), on Cartesian grids.
  *  - Non-reflecting boundary (Sec. 3.1, last paragraph): the ghost-side distributions are
  *    zero, i.e. the right state and its slopes vanish in the face frame.
  *  - PEC boundary (Sec. 5.5 conditions): mirror ghost in the face frame, even normal E and
@@ -63,6 +66,7 @@ typedef struct {
     double dt;     /* time step */
     double C[5];   /* time-integrated coefficients C1..C5 */
     int32_t gradient; /* 0: Green-Gauss (the paper's), 1: least squares */
+    int32_t limiter;  /* 0: none, 1: minmod slopes (Cartesian meshes only) */
 } orc_params;
 
 /* ---------------------------------------------------------------- physics (Sec. 2.1) */
@@ -342,6 +346,82 @@ static void gradients_lsq(const orc_mesh *m, const double *U, double *grad)
     }
 }
 
+static double minmod(double a, double b)
+{
+    if (a > 0.0 && b > 0.0) return a < b ? a : b;
+    if (a < 0.0 && b < 0.0) return a > b ? a : b;
+    return 0.0;
+}
+
+/* Limited slopes (Sec. 5, Riemann problem: the limiter is not named; this is minmod on the
+ * characteristic variables): along each axis d the one-sided slopes (U_+ - U_i)/h_+ and
+ * (U_i - U_-)/h_-, with U_+ and U_- the values across the faces whose outward normals are +e_d
+ * and -e_d (the neighbour, or the boundary ghost placed at the mirror image of x_i, h its
+ * centroid distance), are limited by minmod in the variables that travel along d.  Only meshes
+ * whose every cell has one face per axis direction qualify (Cartesian grids); returns -1
+ * otherwise. */
+static int gradients_limited(const orc_mesh *m, const double *U, double *grad)
+{
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t i = 0; i < m->ncells; ++i) {
+        double up[3][NC], um[3][NC], hp[3] = {0, 0, 0}, hm[3] = {0, 0, 0};
+        int np[3] = {0, 0, 0}, nm[3] = {0, 0, 0};
+        for (int64_t q = m->cf_ptr[i]; q < m->cf_ptr[i + 1]; ++q) {
+            const int64_t s = m->cf_idx[q];
+            const double *n = m->normal + 3 * s, *dL = m->dL + 3 * s, *dR = m->dR + 3 * s;
+            const int64_t L = m->face_L[s], R = m->face_R[s];
+            double nout[3], d[3], Unb[NC];
+            if (L == i && R >= 0) {
+                for (int k = 0; k < 3; ++k) { nout[k] = n[k]; d[k] = dL[k] - dR[k]; }
+                memcpy(Unb, U + NC * R, sizeof Unb);
+            } else if (L == i) {
+                const double h = dL[0] * n[0] + dL[1] * n[1] + dL[2] * n[2];
+                for (int k = 0; k < 3; ++k) { nout[k] = n[k]; d[k] = 2.0 * h * n[k]; }
+                ghost_state((int)(-R - 1), n, U + NC * i, Unb);
+            } else {
+                for (int k = 0; k < 3; ++k) { nout[k] = -n[k]; d[k] = dR[k] - dL[k]; }
+                memcpy(Unb, U + NC * L, sizeof Unb);
+            }
+            int ax = 0;
+            for (int k = 1; k < 3; ++k)
+                if (fabs(nout[k]) > fabs(nout[ax])) ax = k;
+            const double dist = fabs(d[ax]);
+            if (nout[ax] > 0) { memcpy(up[ax], Unb, sizeof Unb); hp[ax] = dist; ++np[ax]; }
+            else              { memcpy(um[ax], Unb, sizeof Unb); hm[ax] = dist; ++nm[ax]; }
+        }
+        for (int k = 0; k < 3; ++k) {
+            const int present = np[k] + nm[k];
+            if (present && (np[k] != 1 || nm[k] != 1)) bad = 1;
+            double *g = grad + (i * 3 + k) * NC;
+            if (present != 2) {
+                for (int f = 0; f < NC; ++f) g[f] = 0.0;
+                continue;
+            }
+            double sp[NC], sm[NC];   /* one-sided slopes */
+            for (int f = 0; f < NC; ++f) {
+                sp[f] = (up[k][f] - U[NC * i + f]) / hp[k];
+                sm[f] = (U[NC * i + f] - um[k][f]) / hm[k];
+            }
+            /* along axis k Maxwell's equations pair E_a with H_b and E_b with H_a (a, b the
+             * other two axes) into waves E_a +/- H_b, E_b +/- H_a at the speed of light; the
+             * normal components E_k, H_k do not move.  Limit those characteristic variables. */
+            const int a = (k + 1) % 3, b = (k + 2) % 3;
+            const int pe[2] = {a, b}, ph[2] = {3 + b, 3 + a};
+            for (int q = 0; q < 2; ++q) {
+                const int e = pe[q], h = ph[q];
+                const double s = minmod(sp[e] + sp[h], sm[e] + sm[h]);
+                const double r = minmod(sp[e] - sp[h], sm[e] - sm[h]);
+                g[e] = 0.5 * (s + r);
+                g[h] = 0.5 * (s - r);
+            }
+            g[k] = minmod(sp[k], sm[k]);
+            g[3 + k] = minmod(sp[3 + k], sm[3 + k]);
+        }
+    }
+    return bad ? -1 : 0;
+}
+
 /* Numerical flux of every face in the global frame (normal flux along n, L -> R). */
 static void face_fluxes(const orc_mesh *m, const orc_params *p, const double *U, const double *grad,
                         const double *epsinv, const double *muinv, double *flux)
@@ -418,7 +498,8 @@ static void face_fluxes(const orc_mesh *m, const orc_params *p, const double *U,
  *   U_i^{n+1} = U_i^n - dt/|Omega_i| M_i^{-1} sum_s sigma_is |l_s| F_s + dt M_i^{-1} S_i^n,
  * sigma = +1 on the owner, -1 on the neighbour.  S = (-J, 0) (Sec. 2.1 source term);
  * J is [3*ncells] (current density at t^n) or NULL.
- * Returns 0, or -1 when a work buffer cannot be allocated.
+ * Returns 0, -1 when a work buffer cannot be allocated, or -2 when the limiter is asked for on a
+ * mesh that is not Cartesian.
  */
 int orc_step(const orc_mesh *m, const orc_params *p, const double *U, double *Unew,
              const double *epsinv, const double *muinv, const double *J)
@@ -426,7 +507,9 @@ int orc_step(const orc_mesh *m, const orc_params *p, const double *U, double *Un
     double *grad = malloc(sizeof(double) * (size_t)m->ncells * 3 * NC);
     double *flux = malloc(sizeof(double) * (size_t)m->nfaces * NC);
     if (!grad || !flux) { free(grad); free(flux); return -1; }
-    if (p->gradient == 1) gradients_lsq(m, U, grad);
+    if (p->limiter) {
+        if (gradients_limited(m, U, grad) != 0) { free(grad); free(flux); return -2; }
+    } else if (p->gradient == 1) gradients_lsq(m, U, grad);
     else gradients(m, U, grad);
     face_fluxes(m, p, U, grad, epsinv, muinv, flux);
 #pragma omp parallel for schedule(static)
@@ -481,3 +564,4 @@ void orc_rotation(const double *n, double *T /*[9]*/)
 }
 void orc_gradients(const orc_mesh *m, const double *U, double *grad) { gradients(m, U, grad); }
 void orc_gradients_lsq(const orc_mesh *m, const double *U, double *grad) { gradients_lsq(m, U, grad); }
+int orc_gradients_limited(const orc_mesh *m, const double *U, double *grad) { return gradients_limited(m, U, grad); }

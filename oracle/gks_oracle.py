@@ -56,9 +56,10 @@ class _Mesh(ctypes.Structure):
 
 class _Params(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("dt", ctypes.c_double), ("C", ctypes.c_double * 5),
-                ("gradient", ctypes.c_int32)]
+                ("gradient", ctypes.c_int32), ("limiter", ctypes.c_int32)]
 
 GRAD_GREEN_GAUSS, GRAD_LSQ = 0, 1
+LIMITER_NONE, LIMITER_MINMOD = 0, 1
 
 
 _lib = None
@@ -78,6 +79,8 @@ def lib():
         _lib.orc_rotation.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         _lib.orc_gradients.argtypes = [ctypes.POINTER(_Mesh), ctypes.c_void_p, ctypes.c_void_p]
         _lib.orc_gradients_lsq.argtypes = [ctypes.POINTER(_Mesh), ctypes.c_void_p, ctypes.c_void_p]
+        _lib.orc_gradients_limited.restype = ctypes.c_int
+        _lib.orc_gradients_limited.argtypes = [ctypes.POINTER(_Mesh), ctypes.c_void_p, ctypes.c_void_p]
     return _lib
 
 
@@ -270,9 +273,10 @@ def tri_mesh(verts: np.ndarray, tris: np.ndarray, face_cells: np.ndarray, face_v
 
 # ----------------------------------------------------------------------------- the step
 def step(mesh: Mesh, U: np.ndarray, dt: float, tau: float, c: float = 1.0, epsinv=None,
-         muinv=None, J=None, C=None, gradient: int = GRAD_GREEN_GAUSS) -> np.ndarray:
+         muinv=None, J=None, C=None, gradient: int = GRAD_GREEN_GAUSS, limiter: int = LIMITER_NONE) -> np.ndarray:
     """One explicit GKS step (Sec. 3.1).  U: (ncells, 6).  J: (ncells, 3) current density or None.
-    gradient: GRAD_GREEN_GAUSS (the paper's) or GRAD_LSQ (least squares over the face neighbours)."""
+    gradient: GRAD_GREEN_GAUSS (the paper's) or GRAD_LSQ (least squares over the face neighbours).
+    limiter: LIMITER_MINMOD replaces the gradients by minmod-limited slopes (Cartesian meshes)."""
     nc = mesh.ncells
     U = np.ascontiguousarray(U, dtype=np.float64).reshape(nc, 6)
     out = np.empty_like(U)
@@ -281,10 +285,13 @@ def step(mesh: Mesh, U: np.ndarray, dt: float, tau: float, c: float = 1.0, epsin
     Jp = None
     if J is not None:
         Jp = np.ascontiguousarray(J, dtype=np.float64).reshape(nc, 3)
-    prm = _Params(c, dt, (ctypes.c_double * 5)(*(C if C is not None else coefficients(dt, tau))), int(gradient))
+    prm = _Params(c, dt, (ctypes.c_double * 5)(*(C if C is not None else coefficients(dt, tau))), int(gradient),
+                  int(limiter))
     ms = mesh._struct()
     rc = lib().orc_step(ctypes.byref(ms), ctypes.byref(prm), _ptr(U), _ptr(out), _ptr(ei), _ptr(mi),
                         _ptr(Jp) if Jp is not None else None)
+    if rc == -2:
+        raise ValueError("the limiter needs a Cartesian mesh")
     if rc != 0:
         raise MemoryError("oracle step could not allocate its work arrays")
     return out
@@ -297,7 +304,7 @@ def gaussian_pulse(t: float, J0: float, t0: float, sigma_t: float) -> float:
 
 def run(mesh: Mesh, U: np.ndarray, nsteps: int, dt: float, tau: float, c: float = 1.0,
         epsinv=None, muinv=None, source=None, t0: float = 0.0, energy_every: int = 0,
-        eps=None, mu=None, gradient: int = GRAD_GREEN_GAUSS):
+        eps=None, mu=None, gradient: int = GRAD_GREEN_GAUSS, limiter: int = LIMITER_NONE):
     """nsteps explicit steps from time t0; t^n = t0 + n dt.
     source: None or (cells, weights, J0, tc, sigma_t): J_z = weight * J0 exp(-((t^n-tc)/sigma_t)^2).
     Returns the final state (and the energy history when energy_every > 0)."""
@@ -310,7 +317,7 @@ def run(mesh: Mesh, U: np.ndarray, nsteps: int, dt: float, tau: float, c: float 
             cells, w, J0, tc, sg = source
             J = np.zeros((mesh.ncells, 3))
             J[np.asarray(cells), 2] = np.asarray(w) * gaussian_pulse(tn, J0, tc, sg)
-        U = step(mesh, U, dt, tau, c, epsinv, muinv, J, C, gradient)
+        U = step(mesh, U, dt, tau, c, epsinv, muinv, J, C, gradient, limiter)
         if energy_every and (n + 1) % energy_every == 0:
             hist.append(energy(mesh, U, eps, mu))
     return (U, hist) if energy_every else U
@@ -324,11 +331,15 @@ def energy(mesh: Mesh, U: np.ndarray, eps=None, mu=None) -> float:
     return float(0.5 * np.sum(mesh.vol * (e * np.sum(U[:, :3] ** 2, axis=1) + m * np.sum(U[:, 3:] ** 2, axis=1))))
 
 
-def gradients(mesh: Mesh, U: np.ndarray, gradient: int = GRAD_GREEN_GAUSS) -> np.ndarray:
-    """Cell gradients (Green-Gauss, or least squares), shape (ncells, 3, 6)."""
+def gradients(mesh: Mesh, U: np.ndarray, gradient: int = GRAD_GREEN_GAUSS, limiter: int = LIMITER_NONE) -> np.ndarray:
+    """Cell gradients (Green-Gauss, least squares, or minmod-limited slopes), shape (ncells, 3, 6)."""
     U = np.ascontiguousarray(U, dtype=np.float64).reshape(mesh.ncells, 6)
     g = np.empty((mesh.ncells, 3, 6))
     ms = mesh._struct()
+    if limiter:
+        if lib().orc_gradients_limited(ctypes.byref(ms), _ptr(U), _ptr(g)) != 0:
+            raise ValueError("the limiter needs a Cartesian mesh")
+        return g
     fn = lib().orc_gradients_lsq if gradient == GRAD_LSQ else lib().orc_gradients
     fn(ctypes.byref(ms), _ptr(U), _ptr(g))
     return g
