@@ -58,11 +58,11 @@ def workload():
     return I.tm_dielectric_nr(nx=N, seed=0, nsteps=1000)
 
 
-def make(torch, wl, precision, energy_every=0):
+def make(torch, wl, precision, energy_every=0, limiter="none"):
     from paper_2412_16845_amd.gks import Solver
     dtype = torch.float64 if precision == "fp64" else torch.float32
     s = Solver("cart2d", n=wl.n, bc=wl.bc, precision=precision, cfl=wl.cfl, tau_over_dt=wl.tau_over_dt,
-               energy_every=energy_every)
+               energy_every=energy_every, limiter=limiter)
     ei = torch.tensor(wl.epsinv, dtype=dtype, device="cuda")
     s.set_material(ei)
     src = wl.source
@@ -244,6 +244,27 @@ def adjoint_leg(torch):
                                  "algorithmic_bytes_per_launch": alg}}
 
 
+def limited_leg(torch, wl):
+    """The 4096^2 workload with minmod-limited slopes (the step for discontinuous data): per-launch
+    time of the limited step kernel against the same algorithmic bytes."""
+    out = {"workload": "tm_dielectric_nr 4096x4096 with limiter = minmod (step kernel only, 100 timed launches)"}
+    ncell = N * N
+    for prec in ("fp32", "fp64"):
+        s, U, ei = make(torch, wl, prec, limiter="minmod")
+        s.run(U, 10)
+        t_launch, _ = time_kernel(torch, s, U, launches=100)
+        if not torch.isfinite(U).all():
+            raise RuntimeError(f"limited {prec} run produced non-finite values")
+        alg = BYTES_PER_CELL[prec] * ncell
+        out[prec] = {"cell_updates_per_s": round(ncell / t_launch, 1),
+                     "roofline": {"bound": "hbm", "achieved": round(alg / t_launch / 1e9, 1), "peak": PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(alg / t_launch / 1e9 / PEAK_GBS, 4),
+                                  "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch}}
+        del s, U, ei
+        torch.cuda.empty_cache()
+    return out
+
+
 N_OVERSIZED = 8192
 
 
@@ -381,6 +402,7 @@ def main():
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-tri", action="store_true")
     ap.add_argument("--no-oversized", action="store_true")
+    ap.add_argument("--no-limited", action="store_true")
     ap.add_argument("--profile-kernel", choices=["fp32", "fp64"])
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -449,6 +471,9 @@ def main():
                  "ms_per_step": round(f64["seconds"] * 1e3 / args.steps, 5), "dtype": "f64",
                  "roofline": roofline("fp64", f64["t_launch"])},
     }
+    if not args.no_limited:
+        log("[bench] limited 2D step: 4096x4096, minmod slopes, fp32 and fp64")
+        out["cart2d_limited"] = limited_leg(torch, wl)
     if not args.no_oversized:
         log("[bench] oversized 2D: 8192x8192, step kernel, fp32 and fp64")
         out["cart2d_8192"] = oversized_leg(torch)

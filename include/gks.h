@@ -50,6 +50,7 @@ typedef enum { GKS_TM2D = 0, GKS_EM3D = 1 } gks_model;
 typedef enum { GKS_BC_PERIODIC = 0, GKS_BC_NONREFLECT = 1, GKS_BC_PEC = 2 } gks_bc;
 typedef enum { GKS_FP64 = 0, GKS_FP32 = 1 } gks_precision;
 typedef enum { GKS_GRAD_GREEN_GAUSS = 0, GKS_GRAD_LSQ = 1 } gks_gradient;
+typedef enum { GKS_LIMITER_NONE = 0, GKS_LIMITER_MINMOD = 1 } gks_limiter;
 
 /*
  * Mesh description (host memory; copied by gks_init_mesh, not retained).
@@ -97,6 +98,14 @@ typedef struct {
  *                 across the face; it is exact for linear fields on any triangle mesh.  On
  *                 Cartesian grids both give the central difference, and both values are
  *                 accepted.  Other values: GKS_EINVAL.
+ *   limiter:      slope limiter for discontinuous data (Sec. 5, Riemann problem: the paper's
+ *                 step limits its slopes there and does not name the limiter).
+ *                 GKS_LIMITER_MINMOD: along each axis, minmod of the two one-sided
+ *                 differences of the variables that travel along that axis (E_a +/- H_b,
+ *                 E_b +/- H_a, with a and b the other axes) and of the normal components, in
+ *                 place of the central difference.  Cartesian grids only (GKS_EINVAL on a
+ *                 triangle mesh).  The limited step is nonlinear: gks_adjoint_step refuses a
+ *                 limited context (GKS_ESTATE).  Other values: GKS_EINVAL.
  */
 typedef struct {
     double c;
@@ -106,6 +115,7 @@ typedef struct {
     int32_t energy_every;
     double unstable_growth;
     int32_t gradient;
+    int32_t limiter;
 } gks_params;
 
 /* Creates a context on the current HIP device.  hip_stream: a hipStream_t (NULL = the null

@@ -138,6 +138,29 @@ __device__ __forceinline__ ConstPtr<Op> scalar_ptr_after(const Op *p, V after)
     return q;
 }
 
+// ------------------------------------------------------------------ slope limiter
+// minmod: the argument of smaller magnitude when both have the same sign, else zero (a tie
+// returns b).
+template <typename T>
+__device__ __forceinline__ T minmod(T a, T b)
+{
+    if (a > T(0) && b > T(0)) return a < b ? a : b;
+    if (a < T(0) && b < T(0)) return a > b ? a : b;
+    return T(0);
+}
+
+// Limited difference of a pair (p, q) of fields that travel along one axis as p + q and p - q:
+// with forward differences fp, fq and backward differences bp, bq (each times the cell width),
+// the limited central differences (times twice the cell width) are S + R and S - R, where
+// S = minmod(fp + fq, bp + bq) and R = minmod(fp - fq, bp - bq).
+template <typename T>
+__device__ __forceinline__ void limit_pair(T fp, T fq, T bp, T bq, T &dp, T &dq)
+{
+    const T S = minmod(fp + fq, bp + bq), Rr = minmod(fp - fq, bp - bq);
+    dp = S + Rr;
+    dq = S - Rr;
+}
+
 // ------------------------------------------------------------------ sparse face operators
 // phi = K0 w + mE KE w + mH KH w for the face orientation described by the table struct P
 // (callers pass mE, mH as the SUM of the two cells' 1/eps, 1/mu: the host halves KE, KH)

@@ -29,6 +29,7 @@ struct gks_ctx {
     int32_t nfields = 3;
     double c = 1, dt = 0, tau = 0, C[5] = {0, 0, 0, 0, 0};
     int32_t energy_every = 0;
+    int32_t limiter = 0;            // 1: minmod-limited slopes (Cartesian grids)
     double unstable_growth = 0;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -209,6 +210,7 @@ gks_status step_cart2d(gks_ctx *x, const void *Uin, void *Uout, double tn)
     a.tile_y = x->tile_y;
     a.nty = (a.ny + a.tile_y - 1) / a.tile_y;
     a.ops = (const FaceOpTM<T> *)x->d_ops;
+    a.limiter = x->limiter;
     const int64_t ns = (int64_t)x->src_cells.size();
     // dt * S_z = -dt * J_z(t^n), scaled by 1/eps of the cell in the kernels
     const double amp = ns ? -x->dt * source_pulse(x, tn) : 0.0;
@@ -248,6 +250,7 @@ gks_status step_cart3d(gks_ctx *x, const void *Uin, void *Uout, double tn)
     a.tile_z = x->tile_z;
     a.ntz = (a.nz + a.tile_z - 1) / a.tile_z;
     a.ops = (const FaceOpEM<T> *)x->d_ops;
+    a.limiter = x->limiter;
     int e = launch_cart3d_step<T>(a, x->stream);
     if (e) return hip_fail(x, e, "GKS 3D step launch");
     const int64_t ns = (int64_t)x->src_cells.size();
@@ -430,6 +433,10 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
     if (!(p->unstable_growth >= 0)) return fail(nullptr, GKS_EINVAL, "unstable_growth must be >= 0");
     if (p->gradient != GKS_GRAD_GREEN_GAUSS && p->gradient != GKS_GRAD_LSQ)
         return fail(nullptr, GKS_EINVAL, "gradient %d is neither Green-Gauss (0) nor least squares (1)", p->gradient);
+    if (p->limiter != GKS_LIMITER_NONE && p->limiter != GKS_LIMITER_MINMOD)
+        return fail(nullptr, GKS_EINVAL, "limiter %d is neither none (0) nor minmod (1)", p->limiter);
+    if (p->limiter != GKS_LIMITER_NONE && m->kind == GKS_TRI2D)
+        return fail(nullptr, GKS_EINVAL, "the slope limiter is defined on Cartesian grids only");
 
     TriGeometry tri;
     gks_ctx *x = new (std::nothrow) gks_ctx();
@@ -440,6 +447,7 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
     x->batch = m->batch;
     x->c = p->c;
     x->energy_every = p->energy_every;
+    x->limiter = p->limiter;
     x->unstable_growth = p->unstable_growth;
     x->stream = (hipStream_t)hip_stream;
     auto bail = [&](gks_status st) {
@@ -756,6 +764,8 @@ extern "C" gks_status gks_adjoint_step(gks_ctx *ctx, const void *U_n, const void
 {
     if (!ctx) return GKS_EINVAL;
     if (ctx->kind != GKS_CART2D) return fail(ctx, GKS_ESTATE, "the adjoint step exists for Cartesian 2D TM contexts only");
+    if (ctx->limiter)
+        return fail(ctx, GKS_ESTATE, "the adjoint step is that of the linear (unlimited) step; this context limits slopes");
     if (!U_n || !lam_np1 || !lam_n) return fail(ctx, GKS_EINVAL, "U_n, lam_np1 or lam_n is NULL");
     const size_t sb = state_bytes(ctx), gb = (size_t)ctx->batch * ctx->ncell * sizeof(double);
     if (ranges_overlap(lam_n, lam_np1, sb) || ranges_overlap(lam_n, U_n, sb))

@@ -57,6 +57,7 @@ struct Cart2DArgs {
     const FaceOpTM<T> *ops;   // device: x-face and y-face operators
     int32_t src_row, src_col; // one point source applied inside the step (src_row < 0: none)
     double src_amp;           // its dt * S_z = -dt * J_z(t^n) (before the 1/eps factor)
+    int32_t limiter;          // 0: central differences, 1: minmod-limited slopes
 };
 
 // Arguments of the Cartesian 3D (six-field) step kernel.
@@ -72,6 +73,7 @@ struct Cart3DArgs {
     int32_t ntx, nty, ntz;   // workgroup tiles along x, y and z
     int32_t tile_z;          // planes per z tile
     const FaceOpEM<T> *ops;  // device: x-, y- and z-face operators
+    int32_t limiter;         // 0: central differences, 1: minmod-limited slopes
 };
 
 // Triangle meshes: per cell the neighbour of each of its three face slots (-(1 + bc) on a

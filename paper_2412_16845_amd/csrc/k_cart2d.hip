@@ -62,7 +62,7 @@ __device__ __forceinline__ void load_cols(Rsrc r, uint32_t voff, uint32_t soff, 
     }
 }
 
-template <typename T, int NC, bool HAS_EPS, bool HAS_MU, bool BND>
+template <typename T, int NC, bool HAS_EPS, bool HAS_MU, bool BND, bool LIM>
 struct Strip2D {
     const Cart2DArgs<T> &a;
     Rsrc rU, rE, rM, rO;   // this batch item's fields, 1/eps, 1/mu, output fields
@@ -131,16 +131,32 @@ struct Strip2D {
         // counted exactly
         load(DN ? max(q - PF, y0 - 2) : min(q + PF, y1 + 1), Rp);
         // central differences of row q-1: [d/dx x (Ez,Hx,Hy), d/dy x (Ez,Hx,Hy)] times 2h
+        T right[NC][3], left[NC][3];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             const T rnext = from_right(Rc.u[0][f]);       // first column of the next lane
             const T lprev = from_left(Rc.u[NC - 1][f]);   // last column of the previous lane
 #pragma unroll
             for (int k = 0; k < NC; ++k) {
-                const T right = (k + 1 < NC) ? Rc.u[k + 1 < NC ? k + 1 : 0][f] : rnext;
-                const T left = (k > 0) ? Rc.u[k > 0 ? k - 1 : 0][f] : lprev;
-                Dc[k][f] = right - left;
+                right[k][f] = (k + 1 < NC) ? Rc.u[k + 1 < NC ? k + 1 : 0][f] : rnext;
+                left[k][f] = (k > 0) ? Rc.u[k > 0 ? k - 1 : 0][f] : lprev;
+                Dc[k][f] = right[k][f] - left[k][f];
                 Dc[k][3 + f] = DN ? Rs.u[k][f] - Rn.u[k][f] : Rn.u[k][f] - Rs.u[k][f];
+            }
+        }
+        if constexpr (LIM) {
+            // limited slopes: minmod of the one-sided differences of the variables that travel
+            // along each axis (x: Ez +/- Hy, with Hx normal; y: Ez +/- Hx, with Hy normal)
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                const T(&c)[3] = Rc.u[k];
+                const T(&up)[3] = DN ? Rs.u[k] : Rn.u[k];   // the row above (larger y)
+                const T(&dn)[3] = DN ? Rn.u[k] : Rs.u[k];
+                limit_pair(right[k][0] - c[0], right[k][2] - c[2], c[0] - left[k][0], c[2] - left[k][2], Dc[k][0],
+                           Dc[k][2]);
+                Dc[k][1] = T(2) * minmod(right[k][1] - c[1], c[1] - left[k][1]);
+                limit_pair(up[0] - c[0], up[1] - c[1], c[0] - dn[0], c[1] - dn[1], Dc[k][3], Dc[k][4]);
+                Dc[k][5] = T(2) * minmod(up[2] - c[2], c[2] - dn[2]);
             }
         }
         if (i < 1) return;
@@ -295,7 +311,7 @@ struct Strip2D {
     }
 };
 
-template <typename T, bool HAS_EPS, bool HAS_MU>
+template <typename T, bool HAS_EPS, bool HAS_MU, bool LIM>
 __global__ __launch_bounds__(STEP2D_BLOCK) void cart2d_step_kernel(Cart2DArgs<T> a)
 {
     constexpr int NC = cols_per_lane<T>();
@@ -325,7 +341,7 @@ __global__ __launch_bounds__(STEP2D_BLOCK) void cart2d_step_kernel(Cart2DArgs<T>
 
     const bool interior = x0 >= 0 && x0 + WAVE * NC - 1 <= a.nx - 1 && y0 - 2 >= 0 && y1 + 1 <= a.ny - 1;
     if (interior) {
-        Strip2D<T, NC, HAS_EPS, HAS_MU, false> s{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0};
+        Strip2D<T, NC, HAS_EPS, HAS_MU, false, LIM> s{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0};
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             s.vx[k] = 0;
@@ -337,7 +353,7 @@ __global__ __launch_bounds__(STEP2D_BLOCK) void cart2d_step_kernel(Cart2DArgs<T>
         s.y1 = y1;
         s.run(ty & 1);
     } else {
-        Strip2D<T, NC, HAS_EPS, HAS_MU, true> s{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0};
+        Strip2D<T, NC, HAS_EPS, HAS_MU, true, LIM> s{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0};
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             bool mirx, nrx;
@@ -360,10 +376,17 @@ int launch_cart2d_step(const Cart2DArgs<T> &a, void *stream)
     const int wpb = STEP2D_BLOCK / WAVE;
     dim3 grid((waves + wpb - 1) / wpb), block(STEP2D_BLOCK);
     hipStream_t s = (hipStream_t)stream;
-    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, true, true>), grid, block, 0, s, a);
-    else if (a.epsinv) hipLaunchKernelGGL((cart2d_step_kernel<T, true, false>), grid, block, 0, s, a);
-    else if (a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, false, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((cart2d_step_kernel<T, false, false>), grid, block, 0, s, a);
+    if (a.limiter) {
+        if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, true, true, true>), grid, block, 0, s, a);
+        else if (a.epsinv) hipLaunchKernelGGL((cart2d_step_kernel<T, true, false, true>), grid, block, 0, s, a);
+        else if (a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, false, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((cart2d_step_kernel<T, false, false, true>), grid, block, 0, s, a);
+        return (int)hipGetLastError();
+    }
+    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, true, true, false>), grid, block, 0, s, a);
+    else if (a.epsinv) hipLaunchKernelGGL((cart2d_step_kernel<T, true, false, false>), grid, block, 0, s, a);
+    else if (a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, false, true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((cart2d_step_kernel<T, false, false, false>), grid, block, 0, s, a);
     return (int)hipGetLastError();
 }
 

@@ -59,7 +59,21 @@ __device__ __forceinline__ bool side_nr(int g, int n, int bclo, int bchi)
     return (g < 0 && bclo == GKS_BC_NONREFLECT) || (g >= n && bchi == GKS_BC_NONREFLECT);
 }
 
-template <typename T, bool HAS_EPS, bool HAS_MU, bool BXY>
+// Limited differences along axis K (times twice the cell width) from the fields of the cell (c)
+// and of its neighbours above (up) and below (dn): minmod of the one-sided differences of the
+// variables that travel along K (E_a +/- H_b, E_b +/- H_a, a and b the other axes) and of the
+// normal components E_K, H_K.
+template <int K, typename T>
+__device__ __forceinline__ void limit_axis(const T (&up)[6], const T (&c)[6], const T (&dn)[6], T *out)
+{
+    constexpr int A = (K + 1) % 3, B = (K + 2) % 3;
+    limit_pair(up[A] - c[A], up[3 + B] - c[3 + B], c[A] - dn[A], c[3 + B] - dn[3 + B], out[A], out[3 + B]);
+    limit_pair(up[B] - c[B], up[3 + A] - c[3 + A], c[B] - dn[B], c[3 + A] - dn[3 + A], out[B], out[3 + A]);
+    out[K] = T(2) * minmod(up[K] - c[K], c[K] - dn[K]);
+    out[3 + K] = T(2) * minmod(up[3 + K] - c[3 + K], c[3 + K] - dn[3 + K]);
+}
+
+template <typename T, bool HAS_EPS, bool HAS_MU, bool BXY, bool LIM>
 struct March3D {
     static constexpr int R = rows3d<T>();
     const Cart3DArgs<T> &a;
@@ -121,6 +135,18 @@ struct March3D {
                 G[f] = from_right(B.u[f]) - from_left(B.u[f]);
                 G[6 + f] = uy[f] - s.u[cu][f][rowm][lane];
                 G[12 + f] = C.u[f] - A.u[f];
+            }
+            if constexpr (LIM) {
+                T xr[6], xl[6], ym[6];
+#pragma unroll
+                for (int f = 0; f < 6; ++f) {
+                    xr[f] = from_right(B.u[f]);
+                    xl[f] = from_left(B.u[f]);
+                    ym[f] = s.u[cu][f][rowm][lane];
+                }
+                limit_axis<0>(xr, B.u, xl, G);
+                limit_axis<1>(uy, B.u, ym, G + 6);
+                limit_axis<2>(C.u, B.u, A.u, G + 12);
             }
             // every face that reads the differences of a non-reflecting ghost zeroes them:
             // zero them at the source (the lane itself), so that the values neighbours receive
@@ -257,7 +283,7 @@ struct March3D {
     }
 };
 
-template <typename T, bool HAS_EPS, bool HAS_MU>
+template <typename T, bool HAS_EPS, bool HAS_MU, bool LIM>
 __global__ __launch_bounds__(WAVE * rows3d<T>()) void cart3d_step_kernel(Cart3DArgs<T> a)
 {
     constexpr int R = rows3d<T>();
@@ -292,7 +318,7 @@ __global__ __launch_bounds__(WAVE * rows3d<T>()) void cart3d_step_kernel(Cart3DA
 
     auto go = [&](auto bnd) {
         constexpr bool BXY = decltype(bnd)::value;
-        March3D<T, HAS_EPS, HAS_MU, BXY> m{a, lds, rU, rE, rM, rO, fbytes, pbytes};
+        March3D<T, HAS_EPS, HAS_MU, BXY, LIM> m{a, lds, rU, rE, rM, rO, fbytes, pbytes};
         m.vcol = (uint32_t)((int64_t)sy * a.nx + sx) * (uint32_t)sizeof(T);
         m.sgn = (mx ? ODD_X : 0u) ^ (my ? ODD_Y : 0u);
         m.nr_c = nrx || nry;
@@ -322,10 +348,17 @@ int launch_cart3d_step(const Cart3DArgs<T> &a, void *stream)
     const unsigned blocks = (unsigned)(a.ntx * a.nty * a.ntz * a.batch);
     dim3 grid(blocks), block(WAVE * rows3d<T>());
     hipStream_t s = (hipStream_t)stream;
-    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, true, true>), grid, block, 0, s, a);
-    else if (a.epsinv) hipLaunchKernelGGL((cart3d_step_kernel<T, true, false>), grid, block, 0, s, a);
-    else if (a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, false, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((cart3d_step_kernel<T, false, false>), grid, block, 0, s, a);
+    if (a.limiter) {
+        if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, true, true, true>), grid, block, 0, s, a);
+        else if (a.epsinv) hipLaunchKernelGGL((cart3d_step_kernel<T, true, false, true>), grid, block, 0, s, a);
+        else if (a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, false, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((cart3d_step_kernel<T, false, false, true>), grid, block, 0, s, a);
+        return (int)hipGetLastError();
+    }
+    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, true, true, false>), grid, block, 0, s, a);
+    else if (a.epsinv) hipLaunchKernelGGL((cart3d_step_kernel<T, true, false, false>), grid, block, 0, s, a);
+    else if (a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, false, true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((cart3d_step_kernel<T, false, false, false>), grid, block, 0, s, a);
     return (int)hipGetLastError();
 }
 

@@ -46,10 +46,11 @@ class MeshDesc(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("cfl", ctypes.c_double), ("dt", ctypes.c_double),
                 ("tau_over_dt", ctypes.c_double), ("energy_every", ctypes.c_int32),
-                ("unstable_growth", ctypes.c_double), ("gradient", ctypes.c_int32)]
+                ("unstable_growth", ctypes.c_double), ("gradient", ctypes.c_int32), ("limiter", ctypes.c_int32)]
 
 
 GRADIENT = {"green_gauss": 0, "lsq": 1}
+LIMITER = {"none": 0, "minmod": 1}
 
 
 _lib = None
@@ -110,14 +111,15 @@ class Solver:
     face_cells, face_verts)``).  Field tensors have shape (batch, nfields, *grid) with
     grid = (ny, nx) / (nz, ny, nx) / (ncells,), contiguous, on the solver's device, dtype
     float64 ('fp64') or float32 ('fp32').  gradient: 'green_gauss' (the paper's) or 'lsq'
-    (least squares; differs only on triangle meshes).
+    (least squares; differs only on triangle meshes).  limiter: 'none' or 'minmod' (limited
+    slopes for discontinuous data, Cartesian grids; the adjoint refuses a limited solver).
     """
 
     def __init__(self, kind: str = "cart2d", n: Sequence[int] = (64, 64), lo=None, hi=None,
                  bc: Sequence[str] = ("periodic",) * 4, precision: str = "fp64", batch: int = 1,
                  c: float = 1.0, cfl: float = 0.5, dt: float = 0.0, tau_over_dt: float = 0.01,
                  energy_every: int = 0, unstable_growth: float = 0.0, device=None, tri=None,
-                 gradient: str = "green_gauss"):
+                 gradient: str = "green_gauss", limiter: str = "none"):
         import torch
         L = lib()
         self.torch = torch
@@ -165,7 +167,8 @@ class Solver:
         else:
             raise ValueError(f"unknown mesh kind {kind!r}")
         grad = GRADIENT[gradient] if isinstance(gradient, str) else int(gradient)
-        p = Params(c, cfl, dt, tau_over_dt, energy_every, unstable_growth, grad)
+        lim = LIMITER[limiter] if isinstance(limiter, str) else int(limiter)
+        p = Params(c, cfl, dt, tau_over_dt, energy_every, unstable_growth, grad, lim)
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             h = ctypes.c_void_p()

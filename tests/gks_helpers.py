@@ -32,7 +32,7 @@ def oracle_source(wl):
     return (np.asarray(s["cells"]), np.asarray(s["weights"], dtype=np.float64), s["J0"], s["t0"], s["sigma_t"])
 
 
-def oracle_run(wl, nsteps, dt, b=0, U0=None, t0=0.0, mesh=None):
+def oracle_run(wl, nsteps, dt, b=0, U0=None, t0=0.0, mesh=None, limiter=0):
     """FP64 oracle run of batch item b; returns the SoA state (nfields, *grid)."""
     mesh = mesh or oracle_mesh(wl)
     model = model_of(wl)
@@ -41,7 +41,8 @@ def oracle_run(wl, nsteps, dt, b=0, U0=None, t0=0.0, mesh=None):
     U = O.from_soa(np.asarray(U0[b], dtype=np.float64).reshape(nf, -1), model)
     ei = None if wl.epsinv is None else np.asarray(wl.epsinv[b], dtype=np.float64).reshape(-1)
     mi = None if wl.muinv is None else np.asarray(wl.muinv[b], dtype=np.float64).reshape(-1)
-    out = O.run(mesh, U, nsteps, dt, wl.tau_over_dt * dt, epsinv=ei, muinv=mi, source=oracle_source(wl), t0=t0)
+    out = O.run(mesh, U, nsteps, dt, wl.tau_over_dt * dt, epsinv=ei, muinv=mi, source=oracle_source(wl), t0=t0,
+                limiter=limiter)
     return O.to_soa(out, model).reshape(U0.shape[1:])
 
 

@@ -96,14 +96,14 @@ def test_null_arguments(gks):
     assert L.gks_flux_coefficients(-1.0, 0.0, out) == -1
 
 
-def _tri_init(gks, verts, tris, fc, fv, cfl=0.5, gradient=0):
+def _tri_init(gks, verts, tris, fc, fv, cfl=0.5, gradient=0, limiter=0):
     d = gks.MeshDesc()
     d.kind, d.model, d.precision, d.batch = 2, 0, 0, 1
     arrs = [np.ascontiguousarray(verts, dtype=np.float64), np.ascontiguousarray(tris, dtype=np.int32),
             np.ascontiguousarray(fc, dtype=np.int32), np.ascontiguousarray(fv, dtype=np.int32)]
     d.nverts, d.ncells, d.nfaces = arrs[0].shape[0], arrs[1].shape[0], arrs[2].shape[0]
     d.vert_xy, d.cell_verts, d.face_cells, d.face_verts = (a.ctypes.data for a in arrs)
-    p = gks.Params(1.0, cfl, 0.0, 0.01, 0, 0.0, gradient)
+    p = gks.Params(1.0, cfl, 0.0, 0.01, 0, 0.0, gradient, limiter)
     h = ctypes.c_void_p()
     st = gks.lib().gks_init_mesh(ctypes.byref(d), ctypes.byref(p), None, ctypes.byref(h))
     msg = gks.lib().gks_last_error(None).decode()
@@ -128,6 +128,10 @@ def test_triangle_topology_is_checked(gks):
     assert st == -1 and "exceeds 0.5" in msg
     st, msg = _tri_init(gks, verts, tris, fc, fv, gradient=2)
     assert st == -1 and "least squares" in msg
+    st, msg = _tri_init(gks, verts, tris, fc, fv, limiter=1)
+    assert st == -1 and "Cartesian grids only" in msg
+    st, msg = _tri_init(gks, verts, tris, fc, fv, limiter=3)
+    assert st == -1 and "minmod" in msg
     # a valid mesh passes the host checks (and then needs a device)
     st, msg = _tri_init(gks, verts, tris, fc, fv)
     assert st in (0, -3), (st, msg)
