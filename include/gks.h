@@ -175,7 +175,8 @@ gks_status gks_run(gks_ctx *ctx, void *U, int64_t nsteps, double t0, double *ene
  *   g_epsinv += (dPhi/d epsinv)^T lam_np1           (device, double, [batch][ncells]; nullable)
  *   g_muinv  += (dPhi/d muinv)^T lam_np1            (device, double, [batch][ncells]; nullable)
  * U_n is the state the forward step started from (device, field type).  lam_n must not
- * overlap lam_np1 or U_n.  Cartesian 2D TM contexts only (GKS_ESTATE otherwise).
+ * overlap lam_np1 or U_n.  Cartesian 2D TM contexts without the slope limiter only (GKS_ESTATE
+ * otherwise: the limited step is nonlinear).
  */
 gks_status gks_adjoint_step(gks_ctx *ctx, const void *U_n, const void *lam_np1, void *lam_n,
                             double *g_epsinv, double *g_muinv, double t_n);
