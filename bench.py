@@ -23,7 +23,8 @@ One JSON line on stdout:
                  same grids, and the adjoint step's own per-launch time
 
 Helper modes for the profiles: --profile-kernel PREC runs only step kernels (for rocprofv3);
---copy-calibration runs a plain device copy of known size (counter scale factor).
+--profile-tri PREC runs 20 steps of the triangle workload; --copy-calibration runs a plain device
+copy of known size (counter scale factor).
 """
 from __future__ import annotations
 
@@ -404,6 +405,7 @@ def main():
     ap.add_argument("--no-oversized", action="store_true")
     ap.add_argument("--no-limited", action="store_true")
     ap.add_argument("--profile-kernel", choices=["fp32", "fp64"])
+    ap.add_argument("--profile-tri", choices=["fp32", "fp64"])
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -422,6 +424,19 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+        return
+
+    if args.profile_tri:
+        from paper_2412_16845_amd import inputs as I
+        from paper_2412_16845_amd.gks import Solver
+        twl = I.tri_ellipse_workload(h=C4_H, seed=0, nsteps=20)
+        ex = twl.extra
+        s = Solver("tri2d", tri=(ex["verts"], ex["tris"], ex["face_cells"], ex["face_verts"]),
+                   precision=args.profile_tri, cfl=twl.cfl, tau_over_dt=twl.tau_over_dt)
+        U = torch.tensor(twl.U0, dtype=torch.float64 if args.profile_tri == "fp64" else torch.float32, device="cuda")
+        s.run(U, 20)
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled": "tri2d " + args.profile_tri, "steps": 20}))
         return
 
     wl = workload()
