@@ -23,8 +23,9 @@ One JSON line on stdout:
                  same grids, and the adjoint step's own per-launch time
 
 Helper modes for the profiles: --profile-kernel PREC runs only step kernels (for rocprofv3);
---profile-tri PREC runs 20 steps of the triangle workload; --copy-calibration runs a plain device
-copy of known size (counter scale factor).
+--profile-tri PREC runs 20 steps of the triangle workload, --profile-3d PREC 10 steps of the 384^3
+workload, --profile-adjoint 10 adjoint steps of the 1024^2 x 8 workload; --copy-calibration runs a
+plain device copy of known size (counter scale factor).
 """
 from __future__ import annotations
 
@@ -406,6 +407,8 @@ def main():
     ap.add_argument("--no-limited", action="store_true")
     ap.add_argument("--profile-kernel", choices=["fp32", "fp64"])
     ap.add_argument("--profile-tri", choices=["fp32", "fp64"])
+    ap.add_argument("--profile-3d", choices=["fp32", "fp64"])
+    ap.add_argument("--profile-adjoint", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -437,6 +440,37 @@ def main():
         s.run(U, 20)
         torch.cuda.synchronize()
         print(json.dumps({"profiled": "tri2d " + args.profile_tri, "steps": 20}))
+        return
+
+    if args.profile_3d:
+        from paper_2412_16845_amd import inputs as I
+        from paper_2412_16845_amd.gks import Solver
+        dtype = torch.float64 if args.profile_3d == "fp64" else torch.float32
+        w3 = I.em_blocks_pec(n=C3_N, seed=0, nsteps=10)
+        s = Solver("cart3d", n=w3.n, bc=w3.bc, precision=args.profile_3d, cfl=w3.cfl, tau_over_dt=w3.tau_over_dt)
+        E = torch.tensor(w3.epsinv, dtype=dtype, device="cuda")
+        s.set_material(E)
+        U = torch.tensor(w3.U0, dtype=dtype, device="cuda")
+        s.run(U, 10)
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled": "cart3d " + args.profile_3d, "steps": 10}))
+        return
+    if args.profile_adjoint:
+        from paper_2412_16845_amd import inputs as I
+        from paper_2412_16845_amd.gks import Solver
+        wa = I.tm_batch_probe(n=ADJ_N, batch=ADJ_BATCH, seed=0, nsteps=10)
+        s = Solver("cart2d", n=wa.n, bc=wa.bc, precision="fp32", batch=wa.batch, cfl=wa.cfl,
+                   tau_over_dt=wa.tau_over_dt)
+        E = torch.tensor(wa.epsinv, dtype=torch.float32, device="cuda")
+        s.set_material(E)
+        U = torch.tensor(wa.U0, dtype=torch.float32, device="cuda")
+        lam = torch.randn_like(U)
+        out = torch.empty_like(U)
+        g = torch.zeros((wa.batch,) + s.grid, dtype=torch.float64, device="cuda")
+        for _ in range(10):
+            s.adjoint_step(U, lam, out, g)
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled": "adjoint fp32", "steps": 10}))
         return
 
     wl = workload()
