@@ -8,11 +8,12 @@
  * summing over the four discrete velocities of the lattice in the face-local frame, exactly in
  * the order the paper builds it (Sec. 3.1), with no closed forms, no blocking and no fusion.
  *
- * State: six components per cell, U = (Ex, Ey, Ez, Hx, Hy, Hz), array-of-structures
- * U[6*i + f].  The divergence-cleaning potentials of the PHM system are dropped
- * (chi = gamma = 0, as in the paper's plane-wave test, Sec. 5.1), and B is read as H.
- * Two-dimensional TM problems use components (Ez, Hx, Hy) with the D2Q4 lattice; the other
- * three stay identically zero.
+ * State: eight components per cell, U = (Ex, Ey, Ez, Hx, Hy, Hz, phi, psi) of the perfectly
+ * hyperbolic Maxwell (PHM) system (Sec. 2.1), array-of-structures U[8*i + f], with B read as
+ * H.  phi and psi are the divergence-cleaning potentials, coupled through chi and gamma; with
+ * chi = gamma = 0 (the paper's experiments) they decouple and stay zero.  Two-dimensional TM
+ * problems use components (Ez, Hx, Hy) (and psi with PHM) with the D2Q4 lattice; the others
+ * stay identically zero.
  *
  * Mesh: a general face-based finite-volume mesh (Sec. 3.1): cells with volume |Omega_i|,
  * faces with owner L, neighbour R (or a boundary code), unit normal n pointing L -> R, area
@@ -33,17 +34,20 @@
  *  - Non-reflecting boundary (Sec. 3.1, last paragraph): the ghost-side distributions are
  *    zero, i.e. the right state and its slopes vanish in the face frame.
  *  - PEC boundary (Sec. 5.5 conditions): mirror ghost in the face frame, even normal E and
- *    tangential H, odd tangential E and normal H; the slopes are mirrored.
+ *    tangential H, odd tangential E and normal H; the slopes are mirrored.  The potentials
+ *    follow the parity that keeps the PHM system invariant under the mirror: phi odd (it
+ *    tracks div E), psi even (it tracks div H).
  *  - Materials (absent from the paper): the kinetic flux uses the vacuum lattice; the cell
- *    update is scaled by M_i^{-1} = diag(1/eps_i, 1/mu_i) and the time derivative of the
+ *    update is scaled by M_i^{-1} = diag(1/eps_i, 1/mu_i, 1, 1) and the time derivative of the
  *    interface equilibrium by the face average of M^{-1}.
+ *  - Sources: the current density J only; the charge density of the phi equation is zero.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
-#define NC 6 /* components carried per cell */
+#define NC 8 /* components carried per cell */
 
 enum { BC_NONREFLECT = 1, BC_PEC = 2 };
 
@@ -67,15 +71,20 @@ typedef struct {
     double C[5];   /* time-integrated coefficients C1..C5 */
     int32_t gradient; /* 0: Green-Gauss (the paper's), 1: least squares */
     int32_t limiter;  /* 0: none, 1: minmod slopes (Cartesian meshes only) */
+    double chi;       /* PHM coupling of phi (E divergence), 0 for plain Maxwell */
+    double gamma;     /* PHM coupling of psi (H divergence), 0 for plain Maxwell */
 } orc_params;
 
 /* ---------------------------------------------------------------- physics (Sec. 2.1) */
 
-/* Directional flux F_j(U) = A_j U of the Maxwell system (Sec. 2.1, flux functions), chi=gamma=0. */
-static void flux_dir(int j, const double *U, double c, double *F)
+/* Directional flux F_j(U) = A_j U of the PHM system (Sec. 2.1, flux functions): the curl
+ * terms of Maxwell's equations, plus chi c^2 phi in E_j, gamma psi in B_j, chi E_j in phi and
+ * gamma c^2 B_j in psi. */
+static void flux_dir(int j, const double *U, double c, double chi, double gam, double *F)
 {
     const double c2 = c * c;
     const double Ex = U[0], Ey = U[1], Ez = U[2], Bx = U[3], By = U[4], Bz = U[5];
+    const double phi = U[6], psi = U[7];
     if (j == 0) {
         F[0] = 0.0;      F[1] = c2 * Bz;  F[2] = -c2 * By;
         F[3] = 0.0;      F[4] = -Ez;      F[5] = Ey;
@@ -86,6 +95,10 @@ static void flux_dir(int j, const double *U, double c, double *F)
         F[0] = c2 * By;  F[1] = -c2 * Bx; F[2] = 0.0;
         F[3] = -Ey;      F[4] = Ex;       F[5] = 0.0;
     }
+    F[j] += chi * c2 * phi;
+    F[3 + j] += gam * psi;
+    F[6] = chi * U[j];
+    F[7] = gam * c2 * U[3 + j];
 }
 
 /* ---------------------------------------------------------------- lattice (Sec. 2.2) */
@@ -101,11 +114,12 @@ static void lattice(int dim, double c, double u[4][3])
 }
 
 /* Local-equilibrium distribution g_k(V) = V/4 + sum_m F_m(V) u_k^m / (4 c^2)  (Sec. 2.2). */
-static void equilibrium(const double u[4][3], double c, const double *V, double g[4][NC])
+static void equilibrium(const double u[4][3], double c, double chi, double gam, const double *V,
+                        double g[4][NC])
 {
     double F[3][NC];
     const double w = 1.0 / (4.0 * c * c);
-    for (int m = 0; m < 3; ++m) flux_dir(m, V, c, F[m]);
+    for (int m = 0; m < 3; ++m) flux_dir(m, V, c, chi, gam, F[m]);
     for (int k = 0; k < 4; ++k)
         for (int f = 0; f < NC; ++f) {
             double s = 0.25 * V[f];
@@ -132,7 +146,8 @@ static void rotation(const double *n, double T[3][3])
     T[2][0] = -n3; T[2][1] = -n2 * n3 / q;        T[2][2] = 1.0 - n3 * n3 / q;
 }
 
-/* T = diag(T', T') acting on (E, H); forward (global -> local) and inverse (= transpose). */
+/* T = diag(T', T', 1, 1) acting on (E, H, phi, psi); forward (global -> local) and inverse
+ * (= transpose).  The potentials are scalars. */
 static void rot_fwd(const double T[3][3], const double *a, double *b)
 {
     for (int blk = 0; blk < 2; ++blk)
@@ -141,6 +156,8 @@ static void rot_fwd(const double T[3][3], const double *a, double *b)
             for (int q = 0; q < 3; ++q) s += T[r][q] * a[3 * blk + q];
             b[3 * blk + r] = s;
         }
+    b[6] = a[6];
+    b[7] = a[7];
 }
 static void rot_inv(const double T[3][3], const double *a, double *b)
 {
@@ -150,13 +167,16 @@ static void rot_inv(const double T[3][3], const double *a, double *b)
             for (int q = 0; q < 3; ++q) s += T[q][r] * a[3 * blk + q];
             b[3 * blk + r] = s;
         }
+    b[6] = a[6];
+    b[7] = a[7];
 }
 
 /* Mirror of a state in the face frame for a perfect electric conductor: the normal E and the
- * tangential H are even, the tangential E and the normal H are odd. */
+ * tangential H are even, the tangential E and the normal H are odd; phi (div E) is odd and psi
+ * (div H) even, the parities under which the mirrored PHM fields solve the same system. */
 static void pec_mirror(const double *a, double *b)
 {
-    static const double P[NC] = {+1, -1, -1, -1, +1, +1};
+    static const double P[NC] = {+1, -1, -1, -1, +1, +1, -1, +1};
     for (int f = 0; f < NC; ++f) b[f] = P[f] * a[f];
 }
 
@@ -173,17 +193,17 @@ static void gks_face_flux(int dim, const orc_params *p, const double *Ul, const 
                           double dUl[3][NC], double dUr[3][NC], double minvE, double minvH,
                           double *Fout)
 {
-    const double c = p->c;
+    const double c = p->c, chi = p->chi, gam = p->gamma;
     double u[4][3];
     lattice(dim, c, u);
 
     /* equilibria of the two reconstructed states and of their slopes */
     double gl[4][NC], gr[4][NC], dgl[3][4][NC], dgr[3][4][NC];
-    equilibrium(u, c, Ul, gl);
-    equilibrium(u, c, Ur, gr);
+    equilibrium(u, c, chi, gam, Ul, gl);
+    equilibrium(u, c, chi, gam, Ur, gr);
     for (int j = 0; j < 3; ++j) {
-        equilibrium(u, c, dUl[j], dgl[j]);
-        equilibrium(u, c, dUr[j], dgr[j]);
+        equilibrium(u, c, chi, gam, dUl[j], dgl[j]);
+        equilibrium(u, c, chi, gam, dUr[j], dgr[j]);
     }
 
     /* interface equilibrium state: <g0> = <g^l>_{>0} + <g^r>_{<0} */
@@ -203,8 +223,8 @@ static void gks_face_flux(int dim, const orc_params *p, const double *Ul, const 
             }
 
     double g0[4][NC], dg0[3][4][NC];
-    equilibrium(u, c, U0, g0);
-    for (int j = 0; j < 3; ++j) equilibrium(u, c, dU0[j], dg0[j]);
+    equilibrium(u, c, chi, gam, U0, g0);
+    for (int j = 0; j < 3; ++j) equilibrium(u, c, chi, gam, dU0[j], dg0[j]);
 
     /* time derivative from the compatibility condition <g_t + u . grad g0> = 0,
      * scaled by the face material factor */
@@ -215,7 +235,7 @@ static void gks_face_flux(int dim, const orc_params *p, const double *Ul, const 
     for (int f = 0; f < 3; ++f) Ut[f] *= minvE;
     for (int f = 3; f < 6; ++f) Ut[f] *= minvH;
     double gt[4][NC];
-    equilibrium(u, c, Ut, gt);
+    equilibrium(u, c, chi, gam, Ut, gt);
 
     /* the five moments of the time-integrated flux */
     double m1[NC] = {0}, m2[NC] = {0}, m3[NC] = {0}, m4[NC] = {0}, m5[NC] = {0};
@@ -256,7 +276,7 @@ static void ghost_state(int bc, const double *n, const double *Ui, double *Ug)
 }
 
 /* Green-Gauss cell gradients: grad U_i = (1/|Omega_i|) sum_s (U_nb - U_i)/2 n_out |l_s|,
- * the arithmetic face value form (Sec. 3.1).  grad[(i*3 + d)*6 + f]. */
+ * the arithmetic face value form (Sec. 3.1).  grad[(i*3 + d)*8 + f]. */
 static void gradients(const orc_mesh *m, const double *U, double *grad)
 {
 #pragma omp parallel for schedule(static)
@@ -290,7 +310,7 @@ static void gradients(const orc_mesh *m, const double *U, double *grad)
  * d_j = x_j - x_i.  A boundary face contributes its ghost state (the same ghost as for
  * Green-Gauss) placed at the mirror image of x_i across the face, d = 2 ((x_s - x_i) . n) n.
  * The normal equations (sum_j d_j d_j^T) g = sum_j d_j (U_j - U_i) are solved by Cramer's rule,
- * in the xy plane on 2D meshes.  grad[(i*3 + d)*6 + f]. */
+ * in the xy plane on 2D meshes.  grad[(i*3 + d)*8 + f]. */
 static void gradients_lsq(const orc_mesh *m, const double *U, double *grad)
 {
 #pragma omp parallel for schedule(static)
@@ -405,18 +425,18 @@ static int gradients_limited(const orc_mesh *m, const double *U, double *grad)
             }
             /* along axis k Maxwell's equations pair E_a with H_b and E_b with H_a (a, b the
              * other two axes) into waves E_a +/- H_b, E_b +/- H_a at the speed of light; the
-             * normal components E_k, H_k do not move.  Limit those characteristic variables. */
+             * normal components E_k, H_k pair with phi and psi (waves at chi c and gamma c under
+             * PHM; without it they do not move and the potentials are zero).  Limit those
+             * characteristic variables. */
             const int a = (k + 1) % 3, b = (k + 2) % 3;
-            const int pe[2] = {a, b}, ph[2] = {3 + b, 3 + a};
-            for (int q = 0; q < 2; ++q) {
+            const int pe[4] = {a, b, k, 3 + k}, ph[4] = {3 + b, 3 + a, 6, 7};
+            for (int q = 0; q < 4; ++q) {
                 const int e = pe[q], h = ph[q];
                 const double s = minmod(sp[e] + sp[h], sm[e] + sm[h]);
                 const double r = minmod(sp[e] - sp[h], sm[e] - sm[h]);
                 g[e] = 0.5 * (s + r);
                 g[h] = 0.5 * (s - r);
             }
-            g[k] = minmod(sp[k], sm[k]);
-            g[3 + k] = minmod(sp[3 + k], sm[3 + k]);
         }
     }
     return bad ? -1 : 0;
@@ -521,7 +541,7 @@ int orc_step(const orc_mesh *m, const orc_params *p, const double *U, double *Un
             for (int f = 0; f < NC; ++f) acc[f] += sigma * m->area[s] * flux[NC * s + f];
         }
         for (int f = 0; f < NC; ++f) {
-            const double minv = (f < 3) ? epsinv[i] : muinv[i];
+            const double minv = (f < 3) ? epsinv[i] : (f < 6) ? muinv[i] : 1.0;
             double src = 0.0;
             if (J && f < 3) src = -J[3 * i + f];
             Unew[NC * i + f] = U[NC * i + f] - p->dt / m->vol[i] * minv * acc[f] + p->dt * minv * src;
@@ -543,11 +563,11 @@ void orc_face_flux(int dim, const orc_params *p, const double *Ul, const double 
 }
 
 /* Exposes the equilibrium and the rotation for the unit tests. */
-void orc_equilibrium(int dim, double c, const double *V, double *g /*[4*6]*/)
+void orc_equilibrium(int dim, double c, double chi, double gam, const double *V, double *g /*[4*8]*/)
 {
     double u[4][3], gg[4][NC];
     lattice(dim, c, u);
-    equilibrium(u, c, V, gg);
+    equilibrium(u, c, chi, gam, V, gg);
     memcpy(g, gg, sizeof gg);
 }
 void orc_lattice(int dim, double c, double *u /*[12]*/)

@@ -12,10 +12,14 @@ Contents
   * mesh builders: Cartesian 2D/3D grids (periodic, non-reflecting or PEC sides), windows of a
     Cartesian grid (for sampled checks of large problems) and triangle meshes.
   * ``step`` / ``run``: the explicit update (Sec. 3.1), literal per-face flux in the face frame.
-  * ``energy``: W = 1/2 sum |Omega_i| (eps_i |E_i|^2 + mu_i |H_i|^2).
+  * ``energy``: W = 1/2 sum |Omega_i| (eps_i |E_i|^2 + mu_i |H_i|^2 (+ phi^2 + psi^2)).
 
 States are arrays of shape (ncells, 6) holding (Ex, Ey, Ez, Hx, Hy, Hz); 2D TM problems use
-columns 2, 3, 4 (Ez, Hx, Hy).
+columns 2, 3, 4 (Ez, Hx, Hy).  The perfectly hyperbolic Maxwell (PHM) system of Sec. 2.1 adds
+the divergence-cleaning potentials phi and psi: its states have shape (ncells, 8), columns 6
+and 7, and its couplings chi and gamma are keyword arguments of ``step`` and ``run``.  The C
+code always carries eight components; six-component states are the chi = gamma = 0 case with
+zero potentials, padded on the way in and cut on the way out.
 """
 from __future__ import annotations
 
@@ -34,6 +38,22 @@ LIB = os.path.join(HERE, "liboracle_gks.so")
 
 BC_PERIODIC, BC_NONREFLECT, BC_PEC = 0, 1, 2
 TM = (2, 3, 4)  # Ez, Hx, Hy columns of the six-component state
+TM_PHM = (2, 3, 4, 7)  # Ez, Hx, Hy, psi columns of the eight-component state
+NC = 8  # components the C code carries per cell
+
+
+def _widen(U: np.ndarray, nc: int) -> tuple:
+    """(ncells, 6 or 8) -> contiguous (ncells, 8) and the width given."""
+    U = np.asarray(U, dtype=np.float64)
+    w = U.shape[-1] if U.ndim == 2 else U.size // nc
+    if w not in (6, 8):
+        raise ValueError(f"states have 6 or 8 components per cell, not {w}")
+    U = U.reshape(nc, w)
+    if w == 8:
+        return np.ascontiguousarray(U), 8
+    V = np.zeros((nc, NC))
+    V[:, :6] = U
+    return V, 6
 
 
 # ----------------------------------------------------------------------------- build / load
@@ -56,7 +76,8 @@ class _Mesh(ctypes.Structure):
 
 class _Params(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("dt", ctypes.c_double), ("C", ctypes.c_double * 5),
-                ("gradient", ctypes.c_int32), ("limiter", ctypes.c_int32)]
+                ("gradient", ctypes.c_int32), ("limiter", ctypes.c_int32), ("chi", ctypes.c_double),
+                ("gamma", ctypes.c_double)]
 
 GRAD_GREEN_GAUSS, GRAD_LSQ = 0, 1
 LIMITER_NONE, LIMITER_MINMOD = 0, 1
@@ -74,7 +95,8 @@ def lib():
         _lib.orc_face_flux.restype = None
         _lib.orc_face_flux.argtypes = [ctypes.c_int, ctypes.POINTER(_Params)] + [ctypes.c_void_p] * 4 + \
             [ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
-        _lib.orc_equilibrium.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+        _lib.orc_equilibrium.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_void_p, ctypes.c_void_p]
         _lib.orc_lattice.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_void_p]
         _lib.orc_rotation.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         _lib.orc_gradients.argtypes = [ctypes.POINTER(_Mesh), ctypes.c_void_p, ctypes.c_void_p]
@@ -273,12 +295,17 @@ def tri_mesh(verts: np.ndarray, tris: np.ndarray, face_cells: np.ndarray, face_v
 
 # ----------------------------------------------------------------------------- the step
 def step(mesh: Mesh, U: np.ndarray, dt: float, tau: float, c: float = 1.0, epsinv=None,
-         muinv=None, J=None, C=None, gradient: int = GRAD_GREEN_GAUSS, limiter: int = LIMITER_NONE) -> np.ndarray:
-    """One explicit GKS step (Sec. 3.1).  U: (ncells, 6).  J: (ncells, 3) current density or None.
+         muinv=None, J=None, C=None, gradient: int = GRAD_GREEN_GAUSS, limiter: int = LIMITER_NONE,
+         chi: float = 0.0, gamma: float = 0.0) -> np.ndarray:
+    """One explicit GKS step (Sec. 3.1).  U: (ncells, 6), or (ncells, 8) for the PHM system with
+    couplings chi and gamma (Sec. 2.1).  J: (ncells, 3) current density or None.
     gradient: GRAD_GREEN_GAUSS (the paper's) or GRAD_LSQ (least squares over the face neighbours).
-    limiter: LIMITER_MINMOD replaces the gradients by minmod-limited slopes (Cartesian meshes)."""
+    limiter: LIMITER_MINMOD replaces the gradients by minmod-limited slopes (Cartesian meshes).
+    Returns a state of the width given."""
     nc = mesh.ncells
-    U = np.ascontiguousarray(U, dtype=np.float64).reshape(nc, 6)
+    U, width = _widen(U, nc)
+    if width == 6 and (chi != 0.0 or gamma != 0.0):
+        raise ValueError("chi or gamma nonzero: pass the eight-component PHM state")
     out = np.empty_like(U)
     ei = np.ones(nc) if epsinv is None else np.ascontiguousarray(epsinv, dtype=np.float64)
     mi = np.ones(nc) if muinv is None else np.ascontiguousarray(muinv, dtype=np.float64)
@@ -286,7 +313,7 @@ def step(mesh: Mesh, U: np.ndarray, dt: float, tau: float, c: float = 1.0, epsin
     if J is not None:
         Jp = np.ascontiguousarray(J, dtype=np.float64).reshape(nc, 3)
     prm = _Params(c, dt, (ctypes.c_double * 5)(*(C if C is not None else coefficients(dt, tau))), int(gradient),
-                  int(limiter))
+                  int(limiter), float(chi), float(gamma))
     ms = mesh._struct()
     rc = lib().orc_step(ctypes.byref(ms), ctypes.byref(prm), _ptr(U), _ptr(out), _ptr(ei), _ptr(mi),
                         _ptr(Jp) if Jp is not None else None)
@@ -294,7 +321,7 @@ def step(mesh: Mesh, U: np.ndarray, dt: float, tau: float, c: float = 1.0, epsin
         raise ValueError("the limiter needs a Cartesian mesh")
     if rc != 0:
         raise MemoryError("oracle step could not allocate its work arrays")
-    return out
+    return out if width == 8 else np.ascontiguousarray(out[:, :6])
 
 
 def gaussian_pulse(t: float, J0: float, t0: float, sigma_t: float) -> float:
@@ -304,7 +331,8 @@ def gaussian_pulse(t: float, J0: float, t0: float, sigma_t: float) -> float:
 
 def run(mesh: Mesh, U: np.ndarray, nsteps: int, dt: float, tau: float, c: float = 1.0,
         epsinv=None, muinv=None, source=None, t0: float = 0.0, energy_every: int = 0,
-        eps=None, mu=None, gradient: int = GRAD_GREEN_GAUSS, limiter: int = LIMITER_NONE):
+        eps=None, mu=None, gradient: int = GRAD_GREEN_GAUSS, limiter: int = LIMITER_NONE,
+        chi: float = 0.0, gamma: float = 0.0):
     """nsteps explicit steps from time t0; t^n = t0 + n dt.
     source: None or (cells, weights, J0, tc, sigma_t): J_z = weight * J0 exp(-((t^n-tc)/sigma_t)^2).
     Returns the final state (and the energy history when energy_every > 0)."""
@@ -317,49 +345,64 @@ def run(mesh: Mesh, U: np.ndarray, nsteps: int, dt: float, tau: float, c: float 
             cells, w, J0, tc, sg = source
             J = np.zeros((mesh.ncells, 3))
             J[np.asarray(cells), 2] = np.asarray(w) * gaussian_pulse(tn, J0, tc, sg)
-        U = step(mesh, U, dt, tau, c, epsinv, muinv, J, C, gradient, limiter)
+        U = step(mesh, U, dt, tau, c, epsinv, muinv, J, C, gradient, limiter, chi, gamma)
         if energy_every and (n + 1) % energy_every == 0:
             hist.append(energy(mesh, U, eps, mu))
     return (U, hist) if energy_every else U
 
 
 def energy(mesh: Mesh, U: np.ndarray, eps=None, mu=None) -> float:
-    """W = 1/2 sum_i |Omega_i| (eps_i |E_i|^2 + mu_i |H_i|^2)."""
-    U = np.asarray(U).reshape(mesh.ncells, 6)
+    """W = 1/2 sum_i |Omega_i| (eps_i |E_i|^2 + mu_i |H_i|^2), plus 1/2 sum_i |Omega_i| (phi_i^2 +
+    psi_i^2) for PHM states (the quadratic form the PHM system conserves in vacuum, c = 1)."""
+    U, width = _widen(U, mesh.ncells)
     e = np.ones(mesh.ncells) if eps is None else np.asarray(eps)
     m = np.ones(mesh.ncells) if mu is None else np.asarray(mu)
-    return float(0.5 * np.sum(mesh.vol * (e * np.sum(U[:, :3] ** 2, axis=1) + m * np.sum(U[:, 3:] ** 2, axis=1))))
+    return float(0.5 * np.sum(mesh.vol * (e * np.sum(U[:, :3] ** 2, axis=1) + m * np.sum(U[:, 3:6] ** 2, axis=1)
+                                          + np.sum(U[:, 6:] ** 2, axis=1))))
 
 
 def gradients(mesh: Mesh, U: np.ndarray, gradient: int = GRAD_GREEN_GAUSS, limiter: int = LIMITER_NONE) -> np.ndarray:
-    """Cell gradients (Green-Gauss, least squares, or minmod-limited slopes), shape (ncells, 3, 6)."""
-    U = np.ascontiguousarray(U, dtype=np.float64).reshape(mesh.ncells, 6)
-    g = np.empty((mesh.ncells, 3, 6))
+    """Cell gradients (Green-Gauss, least squares, or minmod-limited slopes), shape
+    (ncells, 3, width) for a state of width 6 or 8."""
+    U, width = _widen(U, mesh.ncells)
+    g = np.empty((mesh.ncells, 3, NC))
     ms = mesh._struct()
     if limiter:
         if lib().orc_gradients_limited(ctypes.byref(ms), _ptr(U), _ptr(g)) != 0:
             raise ValueError("the limiter needs a Cartesian mesh")
-        return g
-    fn = lib().orc_gradients_lsq if gradient == GRAD_LSQ else lib().orc_gradients
-    fn(ctypes.byref(ms), _ptr(U), _ptr(g))
-    return g
+    else:
+        fn = lib().orc_gradients_lsq if gradient == GRAD_LSQ else lib().orc_gradients
+        fn(ctypes.byref(ms), _ptr(U), _ptr(g))
+    return g if width == 8 else np.ascontiguousarray(g[:, :, :6])
 
 
 # ----------------------------------------------------------------------------- unit-level access
-def face_flux(dim, dt, tau, Ul, Ur, dUl, dUr, minvE=1.0, minvH=1.0, c=1.0, C=None) -> np.ndarray:
-    """Local-frame interface flux (normal along local x) for the unit tests."""
-    prm = _Params(c, dt, (ctypes.c_double * 5)(*(C if C is not None else coefficients(dt, tau))))
-    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (Ul, Ur, dUl, dUr)]
-    F = np.empty(6)
+def _pad(x, shape):
+    a = np.zeros(shape)
+    x = np.asarray(x, dtype=np.float64)
+    a[..., :x.shape[-1]] = x
+    return a
+
+
+def face_flux(dim, dt, tau, Ul, Ur, dUl, dUr, minvE=1.0, minvH=1.0, c=1.0, C=None, chi=0.0, gamma=0.0) -> np.ndarray:
+    """Local-frame interface flux (normal along local x) for the unit tests; states of width 6 or 8
+    (slopes (3, width)), the flux returned with the same width."""
+    width = np.asarray(Ul).shape[-1]
+    prm = _Params(c, dt, (ctypes.c_double * 5)(*(C if C is not None else coefficients(dt, tau))), 0, 0,
+                  float(chi), float(gamma))
+    a = [_pad(Ul, NC), _pad(Ur, NC), _pad(dUl, (3, NC)), _pad(dUr, (3, NC))]
+    F = np.empty(NC)
     lib().orc_face_flux(dim, ctypes.byref(prm), *[_ptr(x) for x in a], minvE, minvH, _ptr(F))
-    return F
+    return F[:width].copy()
 
 
-def equilibrium(dim, V, c=1.0) -> np.ndarray:
-    g = np.empty((4, 6))
-    V = np.ascontiguousarray(V, dtype=np.float64)
-    lib().orc_equilibrium(dim, c, _ptr(V), _ptr(g))
-    return g
+def equilibrium(dim, V, c=1.0, chi=0.0, gamma=0.0) -> np.ndarray:
+    """g_k(V), shape (4, width) for V of width 6 or 8."""
+    width = np.asarray(V).shape[-1]
+    g = np.empty((4, NC))
+    V = _pad(V, NC)
+    lib().orc_equilibrium(dim, c, float(chi), float(gamma), _ptr(V), _ptr(g))
+    return g[:, :width].copy()
 
 
 def lattice(dim, c=1.0) -> np.ndarray:
@@ -377,11 +420,16 @@ def rotation(n) -> np.ndarray:
 
 # ----------------------------------------------------------------------------- layout helpers
 def from_soa(fields: np.ndarray, model: str) -> np.ndarray:
-    """SoA (nfields, ncells) -> oracle state (ncells, 6); model 'tm2d' (Ez,Hx,Hy) or 'em3d'."""
+    """SoA (nfields, ncells) -> oracle state; model 'tm2d' (Ez,Hx,Hy) or 'em3d' give (ncells, 6),
+    'tm2d_phm' (Ez,Hx,Hy,psi) or 'em3d_phm' (all eight) give (ncells, 8)."""
     f = np.asarray(fields, dtype=np.float64)
     if model == "tm2d":
         U = np.zeros((f.shape[1], 6))
         U[:, list(TM)] = f.T
+        return U
+    if model == "tm2d_phm":
+        U = np.zeros((f.shape[1], 8))
+        U[:, list(TM_PHM)] = f.T
         return U
     return np.ascontiguousarray(f.T)
 
@@ -390,4 +438,6 @@ def to_soa(U: np.ndarray, model: str) -> np.ndarray:
     U = np.asarray(U)
     if model == "tm2d":
         return np.ascontiguousarray(U[:, list(TM)].T)
+    if model == "tm2d_phm":
+        return np.ascontiguousarray(U[:, list(TM_PHM)].T)
     return np.ascontiguousarray(U.T)
