@@ -21,11 +21,14 @@ One JSON line on stdout:
   adjoint        forward + adjoint step time of the differentiable workload (1024^2 x 8 maps,
                  800 steps, checkpoints every 50) beside the plain FP64 and FP32 steps of the
                  same grids, and the adjoint step's own per-launch time
+  cart2d_phm     the 4096^2 workload carried by the PHM fields (Ez, Hx, Hy, psi) with a
+                 divergence error to clean (gamma = 1): throughput and roofline
 
 Helper modes for the profiles: --profile-kernel PREC runs only step kernels (for rocprofv3);
 --profile-tri PREC runs 20 steps of the triangle workload, --profile-3d PREC 10 steps of the 384^3
-workload, --profile-adjoint 10 adjoint steps of the 1024^2 x 8 workload; --copy-calibration runs a
-plain device copy of known size (counter scale factor).
+workload, --profile-adjoint 10 adjoint steps of the 1024^2 x 8 workload, --profile-phm PREC 20 steps of
+the 4096^2 PHM workload; --copy-calibration runs a plain device copy of known size (counter scale
+factor).
 """
 from __future__ import annotations
 
@@ -49,6 +52,9 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2412_16845_amd", "csrc", "k_cart2d.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cart2d_step_4096_traffic.txt")
 # algorithmic bytes per cell-update: read Ez,Hx,Hy and 1/eps, write Ez,Hx,Hy
 BYTES_PER_CELL = {"fp32": 7 * 4, "fp64": 7 * 8}
+# with the PHM potential psi: read four fields and 1/eps, write four fields
+PHM_BYTES_PER_CELL = {"fp32": 9 * 4, "fp64": 9 * 8}
+PHM_STEPS = 300
 
 
 def log(msg):
@@ -64,7 +70,7 @@ def make(torch, wl, precision, energy_every=0, limiter="none"):
     from paper_2412_16845_amd.gks import Solver
     dtype = torch.float64 if precision == "fp64" else torch.float32
     s = Solver("cart2d", n=wl.n, bc=wl.bc, precision=precision, cfl=wl.cfl, tau_over_dt=wl.tau_over_dt,
-               energy_every=energy_every, limiter=limiter)
+               energy_every=energy_every, limiter=limiter, phm=wl.extra.get("phm"))
     ei = torch.tensor(wl.epsinv, dtype=dtype, device="cuda")
     s.set_material(ei)
     src = wl.source
@@ -267,6 +273,36 @@ def limited_leg(torch, wl):
     return out
 
 
+def phm_workload(nsteps=PHM_STEPS):
+    from paper_2412_16845_amd import inputs as I
+    return I.tm_phm_dielectric_nr(nx=N, seed=0, nsteps=nsteps, gamma=1.0)
+
+
+def phm_leg(torch):
+    """The 4096^2 dielectric workload on the PHM fields (Ez, Hx, Hy, psi), gamma = 1, with a
+    divergent Hx bump: whole-run throughput (gks_run with the energy diagnostic) and the step
+    kernel's per-launch time against its algorithmic bytes."""
+    wl = phm_workload()
+    ncell = N * N
+    out = {"workload": f"tm_phm_dielectric_nr: PHM TM fields (Ez, Hx, Hy, psi) 4096x4096, the 4096^2 recipe plus "
+                       f"a divergent Hx bump, chi = 0, gamma = 1, {PHM_STEPS} steps, energy every 100", "cells": ncell}
+    for prec in ("fp32", "fp64"):
+        s, U, ei = make(torch, wl, prec, energy_every=ENERGY_EVERY)
+        el, _ = time_run(torch, s, U, PHM_STEPS, 20)
+        if not torch.isfinite(U).all():
+            raise RuntimeError(f"PHM {prec} run produced non-finite values")
+        t_launch, _ = time_kernel(torch, s, U, launches=100)
+        alg = PHM_BYTES_PER_CELL[prec] * ncell
+        out[prec] = {"cell_updates_per_s": round(ncell * PHM_STEPS / el, 1),
+                     "ms_per_step": round(el * 1e3 / PHM_STEPS, 5),
+                     "roofline": {"bound": "hbm", "achieved": round(alg / t_launch / 1e9, 1), "peak": PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(alg / t_launch / 1e9 / PEAK_GBS, 4),
+                                  "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch}}
+        del s, U, ei
+        torch.cuda.empty_cache()
+    return out
+
+
 N_OVERSIZED = 8192
 
 
@@ -405,6 +441,8 @@ def main():
     ap.add_argument("--no-tri", action="store_true")
     ap.add_argument("--no-oversized", action="store_true")
     ap.add_argument("--no-limited", action="store_true")
+    ap.add_argument("--no-phm", action="store_true")
+    ap.add_argument("--profile-phm", choices=["fp32", "fp64"])
     ap.add_argument("--profile-kernel", choices=["fp32", "fp64"])
     ap.add_argument("--profile-tri", choices=["fp32", "fp64"])
     ap.add_argument("--profile-3d", choices=["fp32", "fp64"])
@@ -473,6 +511,16 @@ def main():
         print(json.dumps({"profiled": "adjoint fp32", "steps": 10}))
         return
 
+    if args.profile_phm:
+        s, U, _ = make(torch, phm_workload(20), args.profile_phm)
+        B = torch.empty_like(U)
+        for i in range(20):
+            s.step(U, B, t=i * s.dt)
+            U, B = B, U
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled": "phm " + args.profile_phm, "launches": 20}))
+        return
+
     wl = workload()
     if args.profile_kernel:
         s, U, _ = make(torch, wl, args.profile_kernel)
@@ -526,6 +574,9 @@ def main():
     if not args.no_oversized:
         log("[bench] oversized 2D: 8192x8192, step kernel, fp32 and fp64")
         out["cart2d_8192"] = oversized_leg(torch)
+    if not args.no_phm:
+        log(f"[bench] PHM 2D: 4096x4096 (Ez, Hx, Hy, psi), {PHM_STEPS} steps, fp32 and fp64")
+        out["cart2d_phm"] = phm_leg(torch)
     if not args.no_3d:
         log("[bench] 3D: 384^3 six fields, 500 steps, fp32 and fp64")
         out["cart3d"] = cart3d_leg(torch)

@@ -5,7 +5,7 @@
 // is a sparse linear form of the stencil values:
 //     Phi = K0 w + (1/eps_s) KE w + (1/mu_s) KH w,      Phi = (dt/h_n) * F~   (local frame)
 // with w the left/right cell values and their central half-differences along the local axes
-// (TM: 18 inputs, EM: 48 inputs).  This file evaluates the closed-form moments of the D2Q4 /
+// (TM: 18 inputs, TM with the PHM potential psi: 24, EM: 48 inputs).  This file evaluates the closed-form moments of the D2Q4 /
 // D3Q4 lattices in double precision and probes them with unit vectors to obtain K0, KE, KH.
 // The kernels carry only the structurally non-zero entries (the tables in gks_pattern.h); the
 // probe checks that every other entry is exactly zero, so a wrong table cannot go unnoticed.
@@ -63,21 +63,27 @@ void flux_coefficients(double dt, double tau, double C[5])
 }
 
 // ------------------------------------------------------------------ closed-form moments
-// Directional fluxes of the Maxwell system with chi = gamma = 0 (Sec. 2.1), six components.
-static void F1(const double *V, double c, double *o)
+// Directional fluxes of the perfectly hyperbolic Maxwell system (Sec. 2.1) on eight components
+// (Ex, Ey, Ez, Hx, Hy, Hz, phi, psi): the curl terms, plus chi c^2 phi in E_j, gamma psi in
+// H_j, chi E_j in phi and gamma c^2 H_j in psi.  chi = gamma = 0 is Maxwell's system.
+constexpr int NV = 8;
+struct Phm {
+    double chi, gam;
+};
+static void Fdir(int j, const double *V, double c, Phm q, double *o)
 {
     const double c2 = c * c;
-    o[0] = 0; o[1] = c2 * V[5]; o[2] = -c2 * V[4]; o[3] = 0; o[4] = -V[2]; o[5] = V[1];
-}
-static void F2(const double *V, double c, double *o)
-{
-    const double c2 = c * c;
-    o[0] = -c2 * V[5]; o[1] = 0; o[2] = c2 * V[3]; o[3] = V[2]; o[4] = 0; o[5] = -V[0];
-}
-static void F3(const double *V, double c, double *o)
-{
-    const double c2 = c * c;
-    o[0] = c2 * V[4]; o[1] = -c2 * V[3]; o[2] = 0; o[3] = -V[1]; o[4] = V[0]; o[5] = 0;
+    if (j == 0) {
+        o[0] = 0; o[1] = c2 * V[5]; o[2] = -c2 * V[4]; o[3] = 0; o[4] = -V[2]; o[5] = V[1];
+    } else if (j == 1) {
+        o[0] = -c2 * V[5]; o[1] = 0; o[2] = c2 * V[3]; o[3] = V[2]; o[4] = 0; o[5] = -V[0];
+    } else {
+        o[0] = c2 * V[4]; o[1] = -c2 * V[3]; o[2] = 0; o[3] = -V[1]; o[4] = V[0]; o[5] = 0;
+    }
+    o[j] += q.chi * c2 * V[6];
+    o[3 + j] += q.gam * V[7];
+    o[6] = q.chi * V[j];
+    o[7] = q.gam * c2 * V[3 + j];
 }
 
 // Closed-form GKS flux dt*F~ in the face frame (normal = local axis 1) from the reconstructed
@@ -91,28 +97,31 @@ static void F3(const double *V, double c, double *o)
 //   dt F~ = C1 F1(U0) + C2 Q(grad U0) + C3 F1(U_t) + C4 [<u1 g^l>_+ + <u1 g^r>_-]
 //           - C5 [Q+(grad U^l) + Q-(grad U^r)]
 // with U0 = <g^l>_+ + <g^r>_-, grad U0 likewise, U_t = -M_s^{-1} sum_j F_j(d_j U0).
-static void closed_flux(int dim, double c, const double C[5], const double *Ul, const double *Ur,
-                        const double sl[3][6], const double sr[3][6], double mE, double mH, double *out)
+static void closed_flux(int dim, double c, Phm ph, const double C[5], const double *Ul, const double *Ur,
+                        const double sl[3][NV], const double sr[3][NV], double mE, double mH, double *out)
 {
-    double a[6], b[6], t[6], U0[6], s0[3][6];
+    auto F1 = [&](const double *V, double, double *o) { Fdir(0, V, c, ph, o); };
+    auto F2 = [&](const double *V, double, double *o) { Fdir(1, V, c, ph, o); };
+    auto F3 = [&](const double *V, double, double *o) { Fdir(2, V, c, ph, o); };
+    double a[NV], b[NV], U0[NV], s0[3][NV];
     F1(Ul, c, a);
     F1(Ur, c, b);
-    for (int f = 0; f < 6; ++f) U0[f] = 0.5 * (Ul[f] + Ur[f]) + (a[f] - b[f]) / (2 * c);
+    for (int f = 0; f < NV; ++f) U0[f] = 0.5 * (Ul[f] + Ur[f]) + (a[f] - b[f]) / (2 * c);
     const int nd = dim;
     for (int j = 0; j < 3; ++j) {
         if (j >= nd) { std::memset(s0[j], 0, sizeof s0[j]); continue; }
         F1(sl[j], c, a);
         F1(sr[j], c, b);
-        for (int f = 0; f < 6; ++f) s0[j][f] = 0.5 * (sl[j][f] + sr[j][f]) + (a[f] - b[f]) / (2 * c);
+        for (int f = 0; f < NV; ++f) s0[j][f] = 0.5 * (sl[j][f] + sr[j][f]) + (a[f] - b[f]) / (2 * c);
     }
-    auto Q = [&](const double s[3][6], int half, double *o) {
-        double p1[6], p2[6], p3[6], q2[6], q3[6];
+    auto Q = [&](const double s[3][NV], int half, double *o) {
+        double p1[NV], p2[NV], p3[NV], q2[NV], q3[NV];
         F1(s[0], c, p1);
         F2(s[1], c, p2);
         F3(s[1], c, p3);
         F2(s[2], c, q2);
         F3(s[2], c, q3);
-        for (int f = 0; f < 6; ++f) {
+        for (int f = 0; f < NV; ++f) {
             if (half == 0) {
                 o[f] = c * c * s[0][f] + (nd == 3 ? c * (p3[f] + q2[f]) : 0.0);
             } else {
@@ -125,19 +134,20 @@ static void closed_flux(int dim, double c, const double C[5], const double *Ul, 
             }
         }
     };
-    double Ut[6] = {0}, Fj[6];
+    double Ut[NV] = {0}, Fj[NV];
     F1(s0[0], c, Fj);
-    for (int f = 0; f < 6; ++f) Ut[f] -= Fj[f];
+    for (int f = 0; f < NV; ++f) Ut[f] -= Fj[f];
     F2(s0[1], c, Fj);
-    for (int f = 0; f < 6; ++f) Ut[f] -= Fj[f];
+    for (int f = 0; f < NV; ++f) Ut[f] -= Fj[f];
     if (nd == 3) {
         F3(s0[2], c, Fj);
-        for (int f = 0; f < 6; ++f) Ut[f] -= Fj[f];
+        for (int f = 0; f < NV; ++f) Ut[f] -= Fj[f];
     }
+    // material factors on E and H; the potentials carry none
     for (int f = 0; f < 3; ++f) Ut[f] *= mE;
     for (int f = 3; f < 6; ++f) Ut[f] *= mH;
 
-    double m1[6], m2[6], m3[6], ql[6], qr[6];
+    double m1[NV], m2[NV], m3[NV], ql[NV], qr[NV];
     F1(U0, c, m1);
     Q(s0, 0, m2);
     F1(Ut, c, m3);
@@ -145,7 +155,7 @@ static void closed_flux(int dim, double c, const double C[5], const double *Ul, 
     Q(sr, -1, qr);
     F1(Ul, c, a);
     F1(Ur, c, b);
-    for (int f = 0; f < 6; ++f) {
+    for (int f = 0; f < NV; ++f) {
         const double m4 = 0.5 * c * (Ul[f] - Ur[f]) + 0.5 * (a[f] + b[f]);
         out[f] = C[0] * m1[f] + C[1] * m2[f] + C[2] * m3[f] + C[3] * m4 - C[4] * (ql[f] + qr[f]);
     }
@@ -167,6 +177,7 @@ static void face_rotation(const double n[3], double T[3][3])
     T[2][0] = -n[2]; T[2][1] = -n[1] * n[2] / q;          T[2][2] = 1.0 - n[2] * n[2] / q;
 }
 
+// diag(T', T', 1, 1) on (E, H, phi, psi): the potentials are scalars
 static void rotate_fields(const double T[3][3], const double *a, double *b, bool inverse)
 {
     for (int blk = 0; blk < 2; ++blk)
@@ -175,9 +186,18 @@ static void rotate_fields(const double T[3][3], const double *a, double *b, bool
             for (int k = 0; k < 3; ++k) s += (inverse ? T[k][r] : T[r][k]) * a[3 * blk + k];
             b[3 * blk + r] = s;
         }
+    b[6] = a[6];
+    b[7] = a[7];
 }
 
-static int tm_component(int q) { return 2 + q; }   // (Ez, Hx, Hy) inside (Ex, Ey, Ez, Hx, Hy, Hz)
+// Position of field q of a model inside (Ex, Ey, Ez, Hx, Hy, Hz, phi, psi).
+static int model_fields(int model) { return model == GKS_TM2D ? 3 : model == GKS_TM2D_PHM ? 4 : 6; }
+static int model_component(int model, int q)
+{
+    if (model == GKS_TM2D) return 2 + q;                  // Ez, Hx, Hy
+    if (model == GKS_TM2D_PHM) return q < 3 ? 2 + q : 7;  // Ez, Hx, Hy, psi
+    return q;                                             // Ex .. Hz
+}
 
 // Axis-aligned Cartesian face with normal +e_ax; inputs and outputs in the global frame:
 //   w = [UL UR dnL dt1L (dt2L) dnR dt1R (dt2R)] x fields,
@@ -185,17 +205,17 @@ static int tm_component(int q) { return 2 + q; }   // (Ez, Hx, Hy) inside (Ex, E
 // order (dt1, dt2).  Reconstruction (Sec. 3.1): U^l = U_L + (h_n/2) dU_L/dn, U^r = U_R - (h_n/2)
 // dU_R/dn; states and slopes are rotated into the face frame (d~_j U~ = sum_i T'_ji T d_i U),
 // the closed-form flux is evaluated there and rotated back.  Output phi = (dt/h_n) F (global).
-static void cart_flux_eval(int model, int ax, double c, const double C[5], const double h[3], double dfac,
+static void cart_flux_eval(int model, int ax, double c, Phm ph, const double C[5], const double h[3], double dfac,
                            const double *w, double mE, double mH, double *phi)
 {
-    const int nf = (model == GKS_TM2D) ? 3 : 6;
-    const int nd = (model == GKS_TM2D) ? 2 : 3;
+    const int nf = model_fields(model);
+    const int nd = (model == GKS_EM3D) ? 3 : 2;
     int axes[3] = {ax, 0, 0};
     for (int i = 0, k = 1; i < nd; ++i)
         if (i != ax) axes[k++] = i;
-    double UL[6] = {0}, UR[6] = {0}, gL[3][6] = {{0}}, gR[3][6] = {{0}};
+    double UL[NV] = {0}, UR[NV] = {0}, gL[3][NV] = {{0}}, gR[3][NV] = {{0}};
     for (int q = 0; q < nf; ++q) {
-        const int f = (nf == 3) ? tm_component(q) : q;
+        const int f = model_component(model, q);
         UL[f] = w[q];
         UR[f] = w[nf + q];
         for (int j = 0; j < nd; ++j) {
@@ -208,30 +228,27 @@ static void cart_flux_eval(int model, int ax, double c, const double C[5], const
     n[ax] = 1.0;
     double T[3][3];
     face_rotation(n, T);
-    double Ugl[6], Ugr[6], Ul[6], Ur[6], sl[3][6], sr[3][6];
-    for (int f = 0; f < 6; ++f) {
+    double Ugl[NV], Ugr[NV], Ul[NV], Ur[NV], sl[3][NV], sr[3][NV];
+    for (int f = 0; f < NV; ++f) {
         Ugl[f] = UL[f] + 0.5 * h[ax] * gL[ax][f];
         Ugr[f] = UR[f] - 0.5 * h[ax] * gR[ax][f];
     }
     rotate_fields(T, Ugl, Ul, false);
     rotate_fields(T, Ugr, Ur, false);
     for (int j = 0; j < 3; ++j) {
-        double al[6] = {0}, ar[6] = {0};
+        double al[NV] = {0}, ar[NV] = {0};
         for (int i = 0; i < 3; ++i)
-            for (int f = 0; f < 6; ++f) {
+            for (int f = 0; f < NV; ++f) {
                 al[f] += T[j][i] * gL[i][f];
                 ar[f] += T[j][i] * gR[i][f];
             }
         rotate_fields(T, al, sl[j], false);
         rotate_fields(T, ar, sr[j], false);
     }
-    double out[6], Fg[6];
-    closed_flux(nd, c, C, Ul, Ur, sl, sr, mE, mH, out);
+    double out[NV], Fg[NV];
+    closed_flux(nd, c, ph, C, Ul, Ur, sl, sr, mE, mH, out);
     rotate_fields(T, out, Fg, true);
-    for (int q = 0; q < nf; ++q) {
-        const int f = (nf == 3) ? tm_component(q) : q;
-        phi[q] = Fg[f] / h[ax];
-    }
+    for (int q = 0; q < nf; ++q) phi[q] = Fg[model_component(model, q)] / h[ax];
 }
 
 // Face operator on reconstructed states (triangles): inputs [Ul(3) Ur(3) s1l s2l s1r s2r] with
@@ -239,7 +256,7 @@ static void cart_flux_eval(int model, int ax, double c, const double C[5], const
 static void face_flux_eval(double c, const double C[5], const double *w, double mE, double mH, double *phi)
 {
     static const int tm[3] = {2, 3, 4};
-    double Ul[6] = {0}, Ur[6] = {0}, sl[3][6] = {{0}}, sr[3][6] = {{0}};
+    double Ul[NV] = {0}, Ur[NV] = {0}, sl[3][NV] = {{0}}, sr[3][NV] = {{0}};
     for (int q = 0; q < 3; ++q) {
         const int f = tm[q];
         Ul[f] = w[q];
@@ -249,8 +266,8 @@ static void face_flux_eval(double c, const double C[5], const double *w, double 
         sr[0][f] = w[12 + q];
         sr[1][f] = w[15 + q];
     }
-    double out[6];
-    closed_flux(2, c, C, Ul, Ur, sl, sr, mE, mH, out);
+    double out[NV];
+    closed_flux(2, c, Phm{0.0, 0.0}, C, Ul, Ur, sl, sr, mE, mH, out);
     for (int q = 0; q < 3; ++q) phi[q] = out[tm[q]];
 }
 
@@ -289,13 +306,13 @@ static bool probe(int nout, int nin, Eval ev, const Pattern &pat, double *k0, do
            compress(DH, pat.nH, pat.rH, pat.cH, kh, "KH");
 }
 
-bool cart_face_operator(int model, int axis, double c, const double C[5], const double h[3], double dfac,
-                        double *k0, double *ke, double *kh, char *err, size_t errlen)
+bool cart_face_operator(int model, int axis, double c, double chi, double gamma, const double C[5],
+                        const double h[3], double dfac, double *k0, double *ke, double *kh, char *err, size_t errlen)
 {
-    const int nf = (model == GKS_TM2D) ? 3 : 6;
-    const int nin = (model == GKS_TM2D) ? 18 : 48;
+    const int nf = model_fields(model);
+    const int nin = (model == GKS_EM3D) ? 48 : 6 * nf;
     auto ev = [&](const double *w, double mE, double mH, double *phi) {
-        cart_flux_eval(model, axis, c, C, h, dfac, w, mE, mH, phi);
+        cart_flux_eval(model, axis, c, Phm{chi, gamma}, C, h, dfac, w, mE, mH, phi);
     };
     return probe(nf, nin, ev, pattern_cart(model, axis), k0, ke, kh, err, errlen);
 }

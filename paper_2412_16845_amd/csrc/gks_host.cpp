@@ -28,6 +28,7 @@ struct gks_ctx {
     int64_t ncell = 0;
     int32_t nfields = 3;
     double c = 1, dt = 0, tau = 0, C[5] = {0, 0, 0, 0, 0};
+    double chi = 0, gamma = 0;      // PHM couplings (GKS_TM2D_PHM)
     int32_t energy_every = 0;
     int32_t limiter = 0;            // 1: minmod-limited slopes (Cartesian grids)
     double unstable_growth = 0;
@@ -38,8 +39,10 @@ struct gks_ctx {
     int32_t tile_z = 64;            // planes per workgroup tile (Cartesian 3D)
     const void *epsinv = nullptr, *muinv = nullptr;
 
-    // face operators in double precision: [orientation][...]
-    double k0[3][EM_N0], ke[3][EM_NE], kh[3][EM_NH];
+    // face operators in double precision: [orientation][...], sized for the largest tables
+    static constexpr int MAX_N0 = std::max(EM_N0, TP_N0), MAX_NE = std::max(EM_NE, TP_NE),
+                         MAX_NH = std::max(EM_NH, TP_NH);
+    double k0[3][MAX_N0], ke[3][MAX_NE], kh[3][MAX_NH];
 
     // point sources
     std::vector<int64_t> src_cells;
@@ -130,6 +133,10 @@ void pack_ops(const gks_ctx *x, std::vector<char> &buf)
         std::vector<FaceOpTM<T>> ops(2);
         for (int ax = 0; ax < 2; ++ax) fill_op(ops[ax], x->k0[ax], x->ke[ax], x->kh[ax]);
         buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
+    } else if (x->model == GKS_TM2D_PHM) {
+        std::vector<FaceOpTP<T>> ops(2);
+        for (int ax = 0; ax < 2; ++ax) fill_op(ops[ax], x->k0[ax], x->ke[ax], x->kh[ax]);
+        buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
     } else {
         std::vector<FaceOpEM<T>> ops(3);
         for (int ax = 0; ax < 3; ++ax) fill_op(ops[ax], x->k0[ax], x->ke[ax], x->kh[ax]);
@@ -209,7 +216,8 @@ gks_status step_cart2d(gks_ctx *x, const void *Uin, void *Uout, double tn)
     a.ntx = (a.nx + cart2d_tile_x(x->prec) - 1) / cart2d_tile_x(x->prec);
     a.tile_y = x->tile_y;
     a.nty = (a.ny + a.tile_y - 1) / a.tile_y;
-    a.ops = (const FaceOpTM<T> *)x->d_ops;
+    a.nfields = x->nfields;
+    a.ops = x->d_ops;
     a.limiter = x->limiter;
     const int64_t ns = (int64_t)x->src_cells.size();
     // dt * S_z = -dt * J_z(t^n), scaled by 1/eps of the cell in the kernels
@@ -388,13 +396,17 @@ gks_status launch_energy_into(gks_ctx *x, const void *U, double *dst)
 {
     const double vol = x->h[0] * x->h[1] * (x->kind == GKS_CART3D ? x->h[2] : 1.0);
     const double *cell_vol = (x->kind == GKS_TRI2D) ? x->d_area : nullptr;
+    // E components first, then H, then the potentials (weight 1)
+    const int nE = (x->model == GKS_EM3D) ? 3 : 1, nH = (x->model == GKS_EM3D) ? 3 : 2;
     int e;
     if (x->prec == GKS_FP64)
         e = launch_energy<double>((const double *)U, (const double *)x->epsinv, (const double *)x->muinv, x->ncell,
-                                  x->nfields, (int32_t)x->batch, cell_vol, vol, x->d_partial, x->nblk, dst, x->stream);
+                                  x->nfields, nE, nH, (int32_t)x->batch, cell_vol, vol, x->d_partial, x->nblk, dst,
+                                  x->stream);
     else
         e = launch_energy<float>((const float *)U, (const float *)x->epsinv, (const float *)x->muinv, x->ncell,
-                                 x->nfields, (int32_t)x->batch, cell_vol, vol, x->d_partial, x->nblk, dst, x->stream);
+                                 x->nfields, nE, nH, (int32_t)x->batch, cell_vol, vol, x->d_partial, x->nblk, dst,
+                                 x->stream);
     if (e) return hip_fail(x, e, "energy launch");
     return GKS_OK;
 }
@@ -437,6 +449,15 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
         return fail(nullptr, GKS_EINVAL, "limiter %d is neither none (0) nor minmod (1)", p->limiter);
     if (p->limiter != GKS_LIMITER_NONE && m->kind == GKS_TRI2D)
         return fail(nullptr, GKS_EINVAL, "the slope limiter is defined on Cartesian grids only");
+    if (m->model == GKS_TM2D_PHM) {
+        if (!(p->chi >= 0.0 && p->chi <= 1.0) || !(p->gamma >= 0.0 && p->gamma <= 1.0))
+            return fail(nullptr, GKS_EINVAL, "chi and gamma must lie in [0, 1] (divergence waves at most as fast as c)");
+        if (m->kind != GKS_CART2D) return fail(nullptr, GKS_EINVAL, "the PHM fields are built for Cartesian 2D grids");
+        if (p->limiter != GKS_LIMITER_NONE)
+            return fail(nullptr, GKS_EINVAL, "the slope limiter is not available with the PHM fields");
+    } else if (p->chi != 0.0 || p->gamma != 0.0) {
+        return fail(nullptr, GKS_EINVAL, "chi and gamma are PHM couplings: they must be 0 for model %d", m->model);
+    }
 
     TriGeometry tri;
     gks_ctx *x = new (std::nothrow) gks_ctx();
@@ -446,6 +467,10 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
     x->prec = m->precision;
     x->batch = m->batch;
     x->c = p->c;
+    if (m->model == GKS_TM2D_PHM) {
+        x->chi = p->chi;
+        x->gamma = p->gamma;
+    }
     x->energy_every = p->energy_every;
     x->limiter = p->limiter;
     x->unstable_growth = p->unstable_growth;
@@ -458,8 +483,9 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
 
     if (m->kind == GKS_CART2D || m->kind == GKS_CART3D) {
         const int nd = (m->kind == GKS_CART2D) ? 2 : 3;
-        if ((m->kind == GKS_CART2D && m->model != GKS_TM2D) || (m->kind == GKS_CART3D && m->model != GKS_EM3D))
-            return bail(fail(x, GKS_EINVAL, "Cartesian 2D grids carry TM2D fields and 3D grids EM3D fields"));
+        if ((m->kind == GKS_CART2D && m->model != GKS_TM2D && m->model != GKS_TM2D_PHM) ||
+            (m->kind == GKS_CART3D && m->model != GKS_EM3D))
+            return bail(fail(x, GKS_EINVAL, "Cartesian 2D grids carry TM2D (or TM2D_PHM) fields and 3D grids EM3D fields"));
         for (int d = 0; d < 3; ++d) {
             const int64_t nn = (d < nd) ? m->n[d] : 1;
             if (d < nd && (nn < 2 || nn > (1 << 30)))
@@ -480,7 +506,7 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
             if ((x->bc[2 * d] == GKS_BC_PERIODIC) != (x->bc[2 * d + 1] == GKS_BC_PERIODIC))
                 return bail(fail(x, GKS_EINVAL, "axis %d is periodic on one side only", d));
         x->ncell = x->n[0] * x->n[1] * x->n[2];
-        x->nfields = (m->model == GKS_TM2D) ? 3 : 6;
+        x->nfields = (m->model == GKS_TM2D) ? 3 : (m->model == GKS_TM2D_PHM) ? 4 : 6;
         if ((int64_t)x->nfields * x->ncell > ((int64_t)1 << 31) - 1)
             return bail(fail(x, GKS_EINVAL, "grid too large for 32-bit field indexing"));
         // the kernels address one batch item's fields with 32-bit byte offsets
@@ -524,8 +550,8 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
         // the kernels feed full central differences U(i+1) - U(i-1) = 2 h dU/dx
         const int nax = (x->kind == GKS_CART2D) ? 2 : 3;
         for (int ax = 0; ax < nax; ++ax)
-            if (!cart_face_operator(x->model, ax, x->c, x->C, x->h, 2.0, x->k0[ax], x->ke[ax], x->kh[ax], err,
-                                    sizeof err))
+            if (!cart_face_operator(x->model, ax, x->c, x->chi, x->gamma, x->C, x->h, 2.0, x->k0[ax], x->ke[ax],
+                                    x->kh[ax], err, sizeof err))
                 return bail(fail(x, GKS_EINVAL, "%s", err));
     }
 
@@ -724,7 +750,7 @@ extern "C" gks_status gks_probe_energy(gks_ctx *ctx, const void *U, const int64_
     st = ensure_out(ctx, (size_t)ctx->batch);
     if (st) return st;
     const double vol = ctx->h[0] * ctx->h[1] * (ctx->kind == GKS_CART3D ? ctx->h[2] : 1.0);
-    const int ezf = (ctx->model == GKS_TM2D) ? 0 : 2;
+    const int ezf = (ctx->model == GKS_EM3D) ? 2 : 0;
     int e = (ctx->prec == GKS_FP64)
                 ? launch_probe_energy<double>((const double *)U, ctx->n[0], ctx->n[1], ctx->n[2], ctx->nfields, ezf,
                                               (int32_t)ctx->batch, box, vol, ctx->d_partial, ctx->nblk, ctx->d_out,
@@ -749,7 +775,7 @@ extern "C" gks_status gks_probe_energy_grad(gks_ctx *ctx, const void *U, const i
     st = check_device(ctx);
     if (st) return st;
     const double vol = ctx->h[0] * ctx->h[1] * (ctx->kind == GKS_CART3D ? ctx->h[2] : 1.0);
-    const int ezf = (ctx->model == GKS_TM2D) ? 0 : 2;
+    const int ezf = (ctx->model == GKS_EM3D) ? 2 : 0;
     int e = (ctx->prec == GKS_FP64)
                 ? launch_probe_grad<double>((const double *)U, (double *)lam, ctx->n[0], ctx->n[1], ctx->n[2],
                                             ctx->nfields, ezf, (int32_t)ctx->batch, box, vol, ctx->stream)
@@ -766,6 +792,7 @@ extern "C" gks_status gks_adjoint_step(gks_ctx *ctx, const void *U_n, const void
     if (ctx->kind != GKS_CART2D) return fail(ctx, GKS_ESTATE, "the adjoint step exists for Cartesian 2D TM contexts only");
     if (ctx->limiter)
         return fail(ctx, GKS_ESTATE, "the adjoint step is that of the linear (unlimited) step; this context limits slopes");
+    if (ctx->model != GKS_TM2D) return fail(ctx, GKS_ESTATE, "the adjoint step is built for the TM fields without PHM");
     if (!U_n || !lam_np1 || !lam_n) return fail(ctx, GKS_EINVAL, "U_n, lam_np1 or lam_n is NULL");
     const size_t sb = state_bytes(ctx), gb = (size_t)ctx->batch * ctx->ncell * sizeof(double);
     if (ranges_overlap(lam_n, lam_np1, sb) || ranges_overlap(lam_n, U_n, sb))

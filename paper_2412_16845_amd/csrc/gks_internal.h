@@ -20,13 +20,15 @@ const Pattern &pattern_cart(int model, int axis);
 const Pattern &pattern_tri();
 
 constexpr int TM_N0 = 24, TM_NE = 6, TM_NH = 4;
+constexpr int TP_N0 = 42, TP_NE = 8, TP_NH = 16;
 constexpr int EM_N0 = 80, EM_NE = 12, EM_NH = 12;
 
 void flux_coefficients(double dt, double tau, double C[5]);
 // Face operator of an axis-aligned Cartesian face (normal +e_axis), global-frame inputs whose
-// differences are dfac * h * slope; output (dt/h_axis) * F.
-bool cart_face_operator(int model, int axis, double c, const double C[5], const double h[3], double dfac,
-                        double *k0, double *ke, double *kh, char *err, size_t errlen);
+// differences are dfac * h * slope; output (dt/h_axis) * F.  chi, gamma: PHM couplings.
+bool cart_face_operator(int model, int axis, double c, double chi, double gamma, const double C[5],
+                        const double h[3], double dfac, double *k0, double *ke, double *kh, char *err,
+                        size_t errlen);
 bool tri_face_operator(double c, const double C[5], double *k0, double *ke, double *kh, char *err,
                        size_t errlen);
 
@@ -38,6 +40,7 @@ struct FaceOp {
     T kh[NH];
 };
 template <typename T> using FaceOpTM = FaceOp<T, TM_N0, TM_NE, TM_NH>;
+template <typename T> using FaceOpTP = FaceOp<T, TP_N0, TP_NE, TP_NH>;
 template <typename T> using FaceOpEM = FaceOp<T, EM_N0, EM_NE, EM_NH>;
 
 
@@ -54,7 +57,8 @@ struct Cart2DArgs {
     int32_t bc[4];        // x-, x+, y-, y+
     int32_t ntx, nty;     // tiles per row / column
     int32_t tile_y;       // rows per tile
-    const FaceOpTM<T> *ops;   // device: x-face and y-face operators
+    int32_t nfields;      // 3: (Ez, Hx, Hy); 4: (Ez, Hx, Hy, psi)
+    const void *ops;      // device: x-face and y-face operators (FaceOpTM<T> or FaceOpTP<T>)
     int32_t src_row, src_col; // one point source applied inside the step (src_row < 0: none)
     double src_amp;           // its dt * S_z = -dt * J_z(t^n) (before the 1/eps factor)
     int32_t limiter;          // 0: central differences, 1: minmod-limited slopes
@@ -157,10 +161,11 @@ int cart2d_tile_x(int precision);
 int cart2d_pick_tile_y(int nx, int ny, int batch, int ncu, int precision);
 
 // Energy: partial sums per (batch, block) then a fixed-order final sum; all FP64.
+// Fields [0, nE) are E (weight eps), [nE, nE + nH) are H (weight mu), the rest potentials (1).
 template <typename T>
-int launch_energy(const T *U, const T *epsinv, const T *muinv, int64_t ncell, int32_t nfields, int32_t batch,
-                  const double *vol /*nullable: uniform*/, double uniform_vol, double *partial, int32_t nblk,
-                  double *out, void *stream);
+int launch_energy(const T *U, const T *epsinv, const T *muinv, int64_t ncell, int32_t nfields, int32_t nE,
+                  int32_t nH, int32_t batch, const double *vol /*nullable: uniform*/, double uniform_vol,
+                  double *partial, int32_t nblk, double *out, void *stream);
 template <typename T>
 int launch_probe_energy(const T *U, int64_t nx, int64_t ny, int64_t nz, int32_t nfields, int32_t ez_field,
                         int32_t batch, const int64_t box[6], double vol, double *partial, int32_t nblk, double *out,

@@ -13,6 +13,7 @@ static const Pattern &make()
 const Pattern &pattern_cart(int model, int axis)
 {
     if (model == GKS_TM2D) return axis == 0 ? make<PatTMx>() : make<PatTMy>();
+    if (model == GKS_TM2D_PHM) return axis == 0 ? make<PatTPx>() : make<PatTPy>();
     return axis == 0 ? make<PatEMx>() : (axis == 1 ? make<PatEMy>() : make<PatEMz>());
 }
 

@@ -1,6 +1,7 @@
 // Sparsity tables of the face operators (host and device), one struct per face orientation.
 // Cartesian faces take global-frame inputs
 //   TM (18): [UL UR dnL dtL dnR dtR] x (Ez, Hx, Hy)
+//   TP (24): [UL UR dnL dtL dnR dtR] x (Ez, Hx, Hy, psi)   (TM with the PHM potential psi)
 //   EM (48): [UL UR dnL dt1L dt2L dnR dt1R dt2R] x (Ex, Ey, Ez, Hx, Hy, Hz)
 // with dn the central difference along the face normal and dt1, dt2 along the other axes in
 // increasing order; rows are the global output components.  PatTri takes face-frame inputs
@@ -40,6 +41,34 @@ struct PatTMy {
     static constexpr uint8_t RH[4] = {0, 0, 0, 0};
     static constexpr uint8_t CH[4] = {6, 7, 12, 13};
     static constexpr uint32_t HROWS = 0x1u;
+};
+
+struct PatTPx {
+    static constexpr int N0 = 42;
+    static constexpr uint8_t R0[42] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3};
+    static constexpr uint8_t C0[42] = {0, 2, 4, 6, 8, 10, 13, 16, 18, 21, 1, 3, 5, 7, 9, 11, 12, 14, 17, 19, 20, 22, 0, 2, 4, 6, 8, 10, 15, 16, 18, 23, 1, 3, 5, 7, 9, 11, 14, 17, 19, 22};
+    static constexpr int NE = 8;
+    static constexpr uint8_t RE[8] = {2, 2, 2, 2, 2, 2, 2, 2};
+    static constexpr uint8_t CE[8] = {8, 10, 13, 15, 16, 18, 21, 23};
+    static constexpr uint32_t EROWS = 0x4u;
+    static constexpr int NH = 16;
+    static constexpr uint8_t RH[16] = {0, 0, 0, 0, 0, 0, 0, 0, 3, 3, 3, 3, 3, 3, 3, 3};
+    static constexpr uint8_t CH[16] = {8, 10, 13, 15, 16, 18, 21, 23, 9, 11, 12, 14, 17, 19, 20, 22};
+    static constexpr uint32_t HROWS = 0x9u;
+};
+
+struct PatTPy {
+    static constexpr int N0 = 42;
+    static constexpr uint8_t R0[42] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3};
+    static constexpr uint8_t C0[42] = {0, 1, 4, 5, 8, 9, 14, 16, 17, 22, 0, 1, 4, 5, 8, 9, 15, 16, 17, 23, 2, 3, 6, 7, 10, 11, 12, 13, 18, 19, 20, 21, 2, 3, 6, 7, 10, 11, 13, 18, 19, 21};
+    static constexpr int NE = 8;
+    static constexpr uint8_t RE[8] = {1, 1, 1, 1, 1, 1, 1, 1};
+    static constexpr uint8_t CE[8] = {8, 9, 14, 15, 16, 17, 22, 23};
+    static constexpr uint32_t EROWS = 0x2u;
+    static constexpr int NH = 16;
+    static constexpr uint8_t RH[16] = {0, 0, 0, 0, 0, 0, 0, 0, 3, 3, 3, 3, 3, 3, 3, 3};
+    static constexpr uint8_t CH[16] = {8, 9, 14, 15, 16, 17, 22, 23, 10, 11, 12, 13, 18, 19, 20, 21};
+    static constexpr uint32_t HROWS = 0x9u;
 };
 
 struct PatEMx {
@@ -101,6 +130,8 @@ struct PatTri {
 static_assert(PatTMx::N0 == TM_N0 && PatTMx::NE == TM_NE && PatTMx::NH == TM_NH, "TM table size");
 static_assert(PatTMy::N0 == TM_N0 && PatTMy::NE == TM_NE && PatTMy::NH == TM_NH, "TM table size");
 static_assert(PatTri::N0 == TM_N0 && PatTri::NE == TM_NE && PatTri::NH == TM_NH, "TM table size");
+static_assert(PatTPx::N0 == TP_N0 && PatTPx::NE == TP_NE && PatTPx::NH == TP_NH, "TP table size");
+static_assert(PatTPy::N0 == TP_N0 && PatTPy::NE == TP_NE && PatTPy::NH == TP_NH, "TP table size");
 static_assert(PatEMx::N0 == EM_N0 && PatEMx::NE == EM_NE && PatEMx::NH == EM_NH, "EM table size");
 static_assert(PatEMy::N0 == EM_N0 && PatEMy::NE == EM_NE && PatEMy::NH == EM_NH, "EM table size");
 static_assert(PatEMz::N0 == EM_N0 && PatEMz::NE == EM_NE && PatEMz::NH == EM_NH, "EM table size");

@@ -1,4 +1,7 @@
-// Fused GKS step on a 2D Cartesian grid, TM fields (Ez, Hx, Hy).
+// Fused GKS step on a 2D Cartesian grid, TM fields (Ez, Hx, Hy), or the TM fields of the
+// perfectly hyperbolic Maxwell system with the divergence-cleaning potential psi (Sec. 2.1):
+// (Ez, Hx, Hy, psi).  The field count NF is a template parameter; everything below applies
+// to both.
 //
 // One wavefront owns a strip of 64 lanes x NC adjacent columns (NC = 2 for FP32, 1 for FP64,
 // so that every lane moves 8 bytes per field and row); the two outermost columns on each side
@@ -21,8 +24,8 @@
 // Strips that touch no domain side take a path without index mapping.  On the others, ghost
 // rows/columns follow the boundary condition: non-reflecting sides give the ghost side of a
 // boundary face no distribution (zero state and slopes) and the Green-Gauss gradient the cell's
-// own value; PEC sides read mirror ghosts (Ez and the normal H odd, the tangential H even);
-// periodic sides wrap.
+// own value; PEC sides read mirror ghosts (Ez and the normal H odd, the tangential H even, psi
+// even); periodic sides wrap.
 #include "gks_device.h"
 
 namespace gks {
@@ -42,9 +45,22 @@ constexpr int cols_per_lane() { return sizeof(T) == 4 ? GKS_FP32_COLS_PER_LANE :
 template <typename T>
 constexpr int out_cols() { return WAVE * cols_per_lane<T>() - 2 * HALO; }
 
-template <typename T, int NC>
+// The two field sets: sparsity tables and operator layout of the x- and y-faces.
+template <int NF> struct Fields2D;
+template <> struct Fields2D<3> {   // Ez, Hx, Hy
+    using PX = PatTMx;
+    using PY = PatTMy;
+    template <typename T> using Op = FaceOpTM<T>;
+};
+template <> struct Fields2D<4> {   // Ez, Hx, Hy, psi
+    using PX = PatTPx;
+    using PY = PatTPy;
+    template <typename T> using Op = FaceOpTP<T>;
+};
+
+template <typename T, int NC, int NF>
 struct Row2D {
-    T u[NC][3];      // Ez, Hx, Hy per column (mirror signs applied)
+    T u[NC][NF];     // Ez, Hx, Hy (, psi) per column (mirror signs applied)
     T mE[NC], mH[NC];
     bool nr[NC];     // non-reflecting ghost (boundary strips only)
 };
@@ -62,8 +78,12 @@ __device__ __forceinline__ void load_cols(Rsrc r, uint32_t voff, uint32_t soff, 
     }
 }
 
-template <typename T, int NC, bool HAS_EPS, bool HAS_MU, bool BND, bool LIM>
+template <typename T, int NC, int NF, bool HAS_EPS, bool HAS_MU, bool BND, bool LIM>
 struct Strip2D {
+    static_assert(!LIM || NF == 3, "the limited step is built for the TM fields only");
+    using FS = Fields2D<NF>;
+    using OpT = typename FS::template Op<T>;
+    using Row = Row2D<T, NC, NF>;
     const Cart2DArgs<T> &a;
     Rsrc rU, rE, rM, rO;   // this batch item's fields, 1/eps, 1/mu, output fields
     uint32_t fbytes;       // bytes per field array
@@ -76,18 +96,19 @@ struct Strip2D {
     bool writer[NC];
     int y0, y1;
 
-    __device__ __forceinline__ void load(int gy, Row2D<T, NC> &r) const
+    __device__ __forceinline__ void load(int gy, Row &r) const
     {
         if constexpr (BND) {
             bool mir, nry;
             const int sy = map_axis(gy, a.ny, a.bc[2], a.bc[3], mir, nry);
             const uint32_t so = (uint32_t)sy * (uint32_t)a.nx * (uint32_t)sizeof(T);
-            const T sgy = mir ? T(-1) : T(1);   // y mirror: Ez and Hy odd, Hx even
+            const T sgy = mir ? T(-1) : T(1);   // y mirror: Ez and Hy odd, Hx and psi even
 #pragma unroll
             for (int k = 0; k < NC; ++k) {
                 r.u[k][0] = buf_load<T>(rU, vx[k], so) * (sgx[k] * sgy);
                 r.u[k][1] = buf_load<T>(rU, vx[k], so + fbytes) * sgx[k];
                 r.u[k][2] = buf_load<T>(rU, vx[k], so + 2 * fbytes) * sgy;
+                if constexpr (NF == 4) r.u[k][3] = buf_load<T>(rU, vx[k], so + 3 * fbytes);
                 r.mE[k] = HAS_EPS ? buf_load<T>(rE, vx[k], so) : T(1);
                 r.mH[k] = HAS_MU ? buf_load<T>(rM, vx[k], so) : T(1);
                 r.nr[k] = nry || nrx[k];
@@ -96,7 +117,7 @@ struct Strip2D {
             const uint32_t so = ((uint32_t)gy * (uint32_t)a.nx + (uint32_t)x0) * (uint32_t)sizeof(T);
             T v[NC];
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
+            for (int f = 0; f < NF; ++f) {
                 load_cols<T, NC>(rU, vlane, so + f * fbytes, v);
 #pragma unroll
                 for (int k = 0; k < NC; ++k) r.u[k][f] = v[k];
@@ -118,22 +139,22 @@ struct Strip2D {
     // window holds rows q-2s (Rs), q-s (Rc), q (Rn) with q = qs + s i; Rp receives row q+PF s.
     // fyP is the horizontal face computed one step earlier, fyN the one computed now.
     template <bool DN>
-    __device__ __forceinline__ void body(int i, int qs, Row2D<T, NC> &Rs, Row2D<T, NC> &Rc, Row2D<T, NC> &Rn,
-                                         Row2D<T, NC> &Rp, T (&Ds)[NC][6], T (&Dc)[NC][6], T (&fyP)[NC][3],
-                                         T (&fyN)[NC][3]) const
+    __device__ __forceinline__ void body(int i, int qs, Row &Rs, Row &Rc, Row &Rn, Row &Rp, T (&Ds)[NC][2 * NF],
+                                         T (&Dc)[NC][2 * NF], T (&fyP)[NC][NF], T (&fyN)[NC][NF]) const
     {
         constexpr int sd = DN ? -1 : 1;
         const int q = qs + sd * i;
+        const OpT *ops = (const OpT *)a.ops;
         // coefficients of the horizontal faces: loaded after the previous row's divergence
-        const auto opy = scalar_ptr_after(a.ops + 1, fyP[0][0]);
+        const auto opy = scalar_ptr_after(ops + 1, fyP[0][0]);
         // rows beyond the tile and its halo are not needed: re-read the last halo row instead
         // (already cached), which keeps the load unconditional so the loads in flight are
         // counted exactly
         load(DN ? max(q - PF, y0 - 2) : min(q + PF, y1 + 1), Rp);
-        // central differences of row q-1: [d/dx x (Ez,Hx,Hy), d/dy x (Ez,Hx,Hy)] times 2h
-        T right[NC][3], left[NC][3];
+        // central differences of row q-1: [d/dx x fields, d/dy x fields] times 2h
+        T right[NC][NF], left[NC][NF];
 #pragma unroll
-        for (int f = 0; f < 3; ++f) {
+        for (int f = 0; f < NF; ++f) {
             const T rnext = from_right(Rc.u[0][f]);       // first column of the next lane
             const T lprev = from_left(Rc.u[NC - 1][f]);   // last column of the previous lane
 #pragma unroll
@@ -141,7 +162,7 @@ struct Strip2D {
                 right[k][f] = (k + 1 < NC) ? Rc.u[k + 1 < NC ? k + 1 : 0][f] : rnext;
                 left[k][f] = (k > 0) ? Rc.u[k > 0 ? k - 1 : 0][f] : lprev;
                 Dc[k][f] = right[k][f] - left[k][f];
-                Dc[k][3 + f] = DN ? Rs.u[k][f] - Rn.u[k][f] : Rn.u[k][f] - Rs.u[k][f];
+                Dc[k][NF + f] = DN ? Rs.u[k][f] - Rn.u[k][f] : Rn.u[k][f] - Rs.u[k][f];
             }
         }
         if constexpr (LIM) {
@@ -149,73 +170,73 @@ struct Strip2D {
             // along each axis (x: Ez +/- Hy, with Hx normal; y: Ez +/- Hx, with Hy normal)
 #pragma unroll
             for (int k = 0; k < NC; ++k) {
-                const T(&c)[3] = Rc.u[k];
-                const T(&up)[3] = DN ? Rs.u[k] : Rn.u[k];   // the row above (larger y)
-                const T(&dn)[3] = DN ? Rn.u[k] : Rs.u[k];
+                const T(&c)[NF] = Rc.u[k];
+                const T(&up)[NF] = DN ? Rs.u[k] : Rn.u[k];   // the row above (larger y)
+                const T(&dn)[NF] = DN ? Rn.u[k] : Rs.u[k];
                 limit_pair(right[k][0] - c[0], right[k][2] - c[2], c[0] - left[k][0], c[2] - left[k][2], Dc[k][0],
                            Dc[k][2]);
                 Dc[k][1] = T(2) * minmod(right[k][1] - c[1], c[1] - left[k][1]);
-                limit_pair(up[0] - c[0], up[1] - c[1], c[0] - dn[0], c[1] - dn[1], Dc[k][3], Dc[k][4]);
-                Dc[k][5] = T(2) * minmod(up[2] - c[2], c[2] - dn[2]);
+                limit_pair(up[0] - c[0], up[1] - c[1], c[0] - dn[0], c[1] - dn[1], Dc[k][NF + 0], Dc[k][NF + 1]);
+                Dc[k][NF + 2] = T(2) * minmod(up[2] - c[2], c[2] - dn[2]);
             }
         }
         if (i < 1) return;
 
-        // horizontal face between rows q-2s and q-s: inputs [UL UR dyL dxL dyR dxR], L the
-        // lower row
+        // horizontal face between rows q-2s and q-s: inputs [UL UR dyL dxL dyR dxR] x fields,
+        // L the lower row
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            const Row2D<T, NC> &RL = DN ? Rc : Rs;
-            const Row2D<T, NC> &RR = DN ? Rs : Rc;
-            const T(&DL)[NC][6] = DN ? Dc : Ds;
-            const T(&DR)[NC][6] = DN ? Ds : Dc;
+            const Row &RL = DN ? Rc : Rs;
+            const Row &RR = DN ? Rs : Rc;
+            const T(&DL)[NC][2 * NF] = DN ? Dc : Ds;
+            const T(&DR)[NC][2 * NF] = DN ? Ds : Dc;
             const bool zl = BND && RL.nr[k], zr = BND && RR.nr[k];
-            T w[18];
+            T w[6 * NF];
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
+            for (int f = 0; f < NF; ++f) {
                 w[f] = zl ? T(0) : RL.u[k][f];
-                w[3 + f] = zr ? T(0) : RR.u[k][f];
-                w[6 + f] = zl ? T(0) : DL[k][3 + f];
-                w[9 + f] = zl ? T(0) : DL[k][f];
-                w[12 + f] = zr ? T(0) : DR[k][3 + f];
-                w[15 + f] = zr ? T(0) : DR[k][f];
+                w[NF + f] = zr ? T(0) : RR.u[k][f];
+                w[2 * NF + f] = zl ? T(0) : DL[k][NF + f];
+                w[3 * NF + f] = zl ? T(0) : DL[k][f];
+                w[4 * NF + f] = zr ? T(0) : DR[k][NF + f];
+                w[5 * NF + f] = zr ? T(0) : DR[k][f];
             }
             // face material: the two cells' values (a ghost reads its interior cell); the
             // operator applies their mean
-            apply_op<PatTMy>(w, RL.mE[k] + RR.mE[k], RL.mH[k] + RR.mH[k], opy, fyN[k]);
+            apply_op<typename FS::PY>(w, RL.mE[k] + RR.mE[k], RL.mH[k] + RR.mH[k], opy, fyN[k]);
         }
         if (i < 2) return;
         // coefficients of the vertical faces: loaded once the horizontal faces are done
-        const auto opx = scalar_ptr_after(a.ops, fyN[NC - 1][2]);
+        const auto opx = scalar_ptr_after(ops, fyN[NC - 1][2]);
 
-        // vertical faces right of each column, row q-2s: inputs [UL UR dxL dyL dxR dyR]
-        T ul[NC][3], dl[NC][6];
+        // vertical faces right of each column, row q-2s: inputs [UL UR dxL dyL dxR dyR] x fields
+        T ul[NC][NF], dl[NC][2 * NF];
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const bool z = BND && Rs.nr[k];
 #pragma unroll
-            for (int f = 0; f < 3; ++f) ul[k][f] = z ? T(0) : Rs.u[k][f];
+            for (int f = 0; f < NF; ++f) ul[k][f] = z ? T(0) : Rs.u[k][f];
 #pragma unroll
-            for (int f = 0; f < 6; ++f) dl[k][f] = z ? T(0) : Ds[k][f];
+            for (int f = 0; f < 2 * NF; ++f) dl[k][f] = z ? T(0) : Ds[k][f];
         }
-        T fx[NC][3];
+        T fx[NC][NF];
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             constexpr int last = NC - 1;
             const int kr = (k + 1 < NC) ? k + 1 : 0;
-            T v[18];
+            T v[6 * NF];
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
+            for (int f = 0; f < NF; ++f) {
                 v[f] = ul[k][f];
-                v[3 + f] = (k < last) ? ul[kr][f] : from_right(ul[0][f]);
-                v[6 + f] = dl[k][f];
-                v[9 + f] = dl[k][3 + f];
-                v[12 + f] = (k < last) ? dl[kr][f] : from_right(dl[0][f]);
-                v[15 + f] = (k < last) ? dl[kr][3 + f] : from_right(dl[0][3 + f]);
+                v[NF + f] = (k < last) ? ul[kr][f] : from_right(ul[0][f]);
+                v[2 * NF + f] = dl[k][f];
+                v[3 * NF + f] = dl[k][NF + f];
+                v[4 * NF + f] = (k < last) ? dl[kr][f] : from_right(dl[0][f]);
+                v[5 * NF + f] = (k < last) ? dl[kr][NF + f] : from_right(dl[0][NF + f]);
             }
             const T mEr = (k < last) ? Rs.mE[kr] : from_right(Rs.mE[0]);
             const T mHr = (k < last) ? Rs.mH[kr] : from_right(Rs.mH[0]);
-            apply_op<PatTMx>(v, Rs.mE[k] + mEr, Rs.mH[k] + mHr, opx, fx[k]);
+            apply_op<typename FS::PX>(v, Rs.mE[k] + mEr, Rs.mH[k] + mHr, opx, fx[k]);
         }
 
         // update: per-cell flux divergence (FP32 in FP32 mode), then the old value and the
@@ -223,7 +244,7 @@ struct Strip2D {
         // here; longer source lists by a separate scatter kernel)
         const int row = q - 2 * sd;
         const uint32_t rowc = (uint32_t)row * (uint32_t)a.nx;
-        T nv[NC][3];
+        T nv[NC][NF];
         double src[NC];
 #pragma unroll
         for (int k = 0; k < NC; ++k) src[k] = 0.0;
@@ -235,11 +256,12 @@ struct Strip2D {
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
+            for (int f = 0; f < NF; ++f) {
                 const T fl = (k > 0) ? fx[k > 0 ? k - 1 : 0][f] : from_left(fx[NC - 1][f]);
                 const T dyf = DN ? fyP[k][f] - fyN[k][f] : fyN[k][f] - fyP[k][f];   // upper - lower face
                 const T div = (fx[k][f] - fl) + dyf;
-                const double m = (f == 0) ? (double)Rs.mE[k] : (double)Rs.mH[k];
+                // 1/eps scales Ez, 1/mu scales H; psi carries no material factor
+                const double m = (f == 0) ? (double)Rs.mE[k] : (f < 3) ? (double)Rs.mH[k] : 1.0;
                 const double add = (f == 0) ? src[k] : 0.0;
                 nv[k][f] = (T)((double)Rs.u[k][f] + m * (add - (double)div));
             }
@@ -249,7 +271,7 @@ struct Strip2D {
             if (writer[0]) {
                 const uint32_t so = (rowc + (uint32_t)x0) * (uint32_t)sizeof(T);
 #pragma unroll
-                for (int f = 0; f < 3; ++f) {
+                for (int f = 0; f < NF; ++f) {
                     if constexpr (NC == 2) buf_store_f2(make_float2(nv[0][f], nv[1][f]), rO, vlane, so + f * fbytes);
                     else buf_store(nv[0][f], rO, vlane, so + f * fbytes);
                 }
@@ -262,7 +284,7 @@ struct Strip2D {
                 if (writer[k]) {
                     const uint32_t vo = (uint32_t)(gx0 + k) * (uint32_t)sizeof(T);
 #pragma unroll
-                    for (int f = 0; f < 3; ++f) buf_store(nv[k][f], rO, vo, so + f * fbytes);
+                    for (int f = 0; f < NF; ++f) buf_store(nv[k][f], rO, vo, so + f * fbytes);
                 }
         }
     }
@@ -272,13 +294,13 @@ struct Strip2D {
     __device__ __forceinline__ void run() const
     {
         constexpr int sd = DN ? -1 : 1;
-        Row2D<T, NC> R0, R1, R2, R3, R4, R5;
-        T D0[NC][6], D1[NC][6];
-        T F0[NC][3], F1[NC][3];
+        Row R0, R1, R2, R3, R4, R5;
+        T D0[NC][2 * NF], D1[NC][2 * NF];
+        T F0[NC][NF], F1[NC][NF];
 #pragma unroll
         for (int k = 0; k < NC; ++k)
 #pragma unroll
-            for (int f = 0; f < 3; ++f) F0[k][f] = F1[k][f] = T(0);
+            for (int f = 0; f < NF; ++f) F0[k][f] = F1[k][f] = T(0);
         const int qs = DN ? y1 - 1 : y0;       // window head of the first step
         load(qs - 2 * sd, R0);
         load(qs - sd, R1);
@@ -311,7 +333,7 @@ struct Strip2D {
     }
 };
 
-template <typename T, bool HAS_EPS, bool HAS_MU, bool LIM>
+template <typename T, int NF, bool HAS_EPS, bool HAS_MU, bool LIM>
 __global__ __launch_bounds__(STEP2D_BLOCK) void cart2d_step_kernel(Cart2DArgs<T> a)
 {
     constexpr int NC = cols_per_lane<T>();
@@ -328,8 +350,8 @@ __global__ __launch_bounds__(STEP2D_BLOCK) void cart2d_step_kernel(Cart2DArgs<T>
 
     const int64_t ncell = (int64_t)a.nx * a.ny;
     const uint32_t fbytes = (uint32_t)(ncell * (int64_t)sizeof(T));
-    const Rsrc rU = make_rsrc(a.U + (int64_t)b * 3 * ncell, 3ull * fbytes);
-    const Rsrc rO = make_rsrc(a.Unew + (int64_t)b * 3 * ncell, 3ull * fbytes);
+    const Rsrc rU = make_rsrc(a.U + (int64_t)b * NF * ncell, (uint64_t)NF * fbytes);
+    const Rsrc rO = make_rsrc(a.Unew + (int64_t)b * NF * ncell, (uint64_t)NF * fbytes);
     const Rsrc rE = make_rsrc(HAS_EPS ? a.epsinv + (int64_t)b * ncell : a.U, fbytes);
     const Rsrc rM = make_rsrc(HAS_MU ? a.muinv + (int64_t)b * ncell : a.U, fbytes);
 
@@ -341,7 +363,7 @@ __global__ __launch_bounds__(STEP2D_BLOCK) void cart2d_step_kernel(Cart2DArgs<T>
 
     const bool interior = x0 >= 0 && x0 + WAVE * NC - 1 <= a.nx - 1 && y0 - 2 >= 0 && y1 + 1 <= a.ny - 1;
     if (interior) {
-        Strip2D<T, NC, HAS_EPS, HAS_MU, false, LIM> s{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0};
+        Strip2D<T, NC, NF, HAS_EPS, HAS_MU, false, LIM> s{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0};
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             s.vx[k] = 0;
@@ -353,13 +375,13 @@ __global__ __launch_bounds__(STEP2D_BLOCK) void cart2d_step_kernel(Cart2DArgs<T>
         s.y1 = y1;
         s.run(ty & 1);
     } else {
-        Strip2D<T, NC, HAS_EPS, HAS_MU, true, LIM> s{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0};
+        Strip2D<T, NC, NF, HAS_EPS, HAS_MU, true, LIM> s{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0};
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             bool mirx, nrx;
             const int sx = map_axis(gx0 + k, a.nx, a.bc[0], a.bc[1], mirx, nrx);
             s.vx[k] = (uint32_t)sx * (uint32_t)sizeof(T);
-            s.sgx[k] = mirx ? T(-1) : T(1);   // x mirror: Ez and Hx odd, Hy even
+            s.sgx[k] = mirx ? T(-1) : T(1);   // x mirror: Ez and Hx odd, Hy and psi even
             s.nrx[k] = nrx;
             s.writer[k] = NC * lane + k >= HALO && NC * lane + k < WAVE * NC - HALO && gx0 + k < a.nx;
         }
@@ -376,17 +398,26 @@ int launch_cart2d_step(const Cart2DArgs<T> &a, void *stream)
     const int wpb = STEP2D_BLOCK / WAVE;
     dim3 grid((waves + wpb - 1) / wpb), block(STEP2D_BLOCK);
     hipStream_t s = (hipStream_t)stream;
-    if (a.limiter) {
-        if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, true, true, true>), grid, block, 0, s, a);
-        else if (a.epsinv) hipLaunchKernelGGL((cart2d_step_kernel<T, true, false, true>), grid, block, 0, s, a);
-        else if (a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, false, true, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((cart2d_step_kernel<T, false, false, true>), grid, block, 0, s, a);
+    if (a.nfields == 4) {   // TM with psi (never limited: the host refuses that combination)
+        if (a.limiter) return (int)hipErrorInvalidValue;
+        if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, 4, true, true, false>), grid, block, 0, s, a);
+        else if (a.epsinv) hipLaunchKernelGGL((cart2d_step_kernel<T, 4, true, false, false>), grid, block, 0, s, a);
+        else if (a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, 4, false, true, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((cart2d_step_kernel<T, 4, false, false, false>), grid, block, 0, s, a);
         return (int)hipGetLastError();
     }
-    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, true, true, false>), grid, block, 0, s, a);
-    else if (a.epsinv) hipLaunchKernelGGL((cart2d_step_kernel<T, true, false, false>), grid, block, 0, s, a);
-    else if (a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, false, true, false>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((cart2d_step_kernel<T, false, false, false>), grid, block, 0, s, a);
+    if (a.nfields != 3) return (int)hipErrorInvalidValue;
+    if (a.limiter) {
+        if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, 3, true, true, true>), grid, block, 0, s, a);
+        else if (a.epsinv) hipLaunchKernelGGL((cart2d_step_kernel<T, 3, true, false, true>), grid, block, 0, s, a);
+        else if (a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, 3, false, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((cart2d_step_kernel<T, 3, false, false, true>), grid, block, 0, s, a);
+        return (int)hipGetLastError();
+    }
+    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, 3, true, true, false>), grid, block, 0, s, a);
+    else if (a.epsinv) hipLaunchKernelGGL((cart2d_step_kernel<T, 3, true, false, false>), grid, block, 0, s, a);
+    else if (a.muinv) hipLaunchKernelGGL((cart2d_step_kernel<T, 3, false, true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((cart2d_step_kernel<T, 3, false, false, false>), grid, block, 0, s, a);
     return (int)hipGetLastError();
 }
 

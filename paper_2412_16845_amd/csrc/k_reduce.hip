@@ -1,5 +1,5 @@
 // Diagnostics of the GKS state (double precision, deterministic order) and small helpers:
-//   energy        W = 1/2 sum_i |Omega_i| (eps_i |E_i|^2 + mu_i |H_i|^2) per batch item
+//   energy        W = 1/2 sum_i |Omega_i| (eps_i |E_i|^2 + mu_i |H_i|^2 + |potentials|^2) per batch item
 //   probe energy  sum over a box of cells of |Omega| Ez^2, and its gradient 2 |Omega| Ez
 //   source        explicit point-source scatter for long source lists
 // Sums run in two passes: fixed per-block partial sums, then one block per batch item adds the
@@ -26,25 +26,26 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
 
 template <typename T>
 __global__ __launch_bounds__(RBLOCK) void energy_partial_kernel(const T *U, const T *epsinv, const T *muinv,
-                                                                int64_t ncell, int32_t nfields, const double *vol,
-                                                                double uvol, double *partial, int32_t nblk)
+                                                                int64_t ncell, int32_t nfields, int32_t nE, int32_t nH,
+                                                                const double *vol, double uvol, double *partial,
+                                                                int32_t nblk)
 {
     __shared__ double lds[RBLOCK / WAVE];
     const int b = blockIdx.y;
     const T *Ub = U + (int64_t)b * nfields * ncell;
-    const int nE = (nfields == 3) ? 1 : 3;   // TM: Ez | Hx Hy; EM: Ex Ey Ez | Hx Hy Hz
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * RBLOCK + threadIdx.x; i < ncell; i += (int64_t)nblk * RBLOCK) {
-        double e2 = 0.0, h2 = 0.0;
+        double e2 = 0.0, h2 = 0.0, p2 = 0.0;
         for (int f = 0; f < nfields; ++f) {
             const double v = (double)Ub[(int64_t)f * ncell + i];
             if (f < nE) e2 += v * v;
-            else h2 += v * v;
+            else if (f < nE + nH) h2 += v * v;
+            else p2 += v * v;
         }
         const double eps = epsinv ? 1.0 / (double)epsinv[(int64_t)b * ncell + i] : 1.0;
         const double mu = muinv ? 1.0 / (double)muinv[(int64_t)b * ncell + i] : 1.0;
         const double w = vol ? vol[i] : uvol;
-        acc += 0.5 * w * (eps * e2 + mu * h2);
+        acc += 0.5 * w * (eps * e2 + mu * h2 + p2);
     }
     const double s = block_sum(acc, lds);
     if (threadIdx.x == 0) partial[(int64_t)b * nblk + blockIdx.x] = s;
@@ -61,12 +62,13 @@ __global__ __launch_bounds__(RBLOCK) void final_sum_kernel(const double *partial
 }
 
 template <typename T>
-int launch_energy(const T *U, const T *epsinv, const T *muinv, int64_t ncell, int32_t nfields, int32_t batch,
-                  const double *vol, double uniform_vol, double *partial, int32_t nblk, double *out, void *stream)
+int launch_energy(const T *U, const T *epsinv, const T *muinv, int64_t ncell, int32_t nfields, int32_t nE, int32_t nH,
+                  int32_t batch, const double *vol, double uniform_vol, double *partial, int32_t nblk, double *out,
+                  void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(energy_partial_kernel<T>, dim3(nblk, batch), dim3(RBLOCK), 0, s, U, epsinv, muinv, ncell,
-                       nfields, vol, uniform_vol, partial, nblk);
+                       nfields, nE, nH, vol, uniform_vol, partial, nblk);
     hipLaunchKernelGGL(final_sum_kernel, dim3(batch), dim3(RBLOCK), 0, s, partial, nblk, out);
     return (int)hipGetLastError();
 }
@@ -164,8 +166,8 @@ int launch_source_scatter(T *U, const T *epsinv, int64_t ncell, int64_t fstride,
 }
 
 #define GKS_INST(T)                                                                                                  \
-    template int launch_energy<T>(const T *, const T *, const T *, int64_t, int32_t, int32_t, const double *, double, \
-                                  double *, int32_t, double *, void *);                                            \
+    template int launch_energy<T>(const T *, const T *, const T *, int64_t, int32_t, int32_t, int32_t, int32_t,    \
+                                  const double *, double, double *, int32_t, double *, void *);                    \
     template int launch_probe_energy<T>(const T *, int64_t, int64_t, int64_t, int32_t, int32_t, int32_t,            \
                                         const int64_t[6], double, double *, int32_t, double *, void *);             \
     template int launch_probe_grad<T>(const T *, T *, int64_t, int64_t, int64_t, int32_t, int32_t, int32_t,         \

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "libgks.so")
 
 GKS_CART2D, GKS_CART3D, GKS_TRI2D = 0, 1, 2
-GKS_TM2D, GKS_EM3D = 0, 1
+GKS_TM2D, GKS_EM3D, GKS_TM2D_PHM = 0, 1, 2
 BC = {"periodic": 0, "nonreflecting": 1, "pec": 2}
 PRECISION = {"fp64": 0, "fp32": 1}
 STATUS = {0: "GKS_OK", -1: "GKS_EINVAL", -2: "GKS_ENOMEM", -3: "GKS_EDEVICE", -4: "GKS_EUNSTABLE",
@@ -46,7 +46,8 @@ class MeshDesc(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("cfl", ctypes.c_double), ("dt", ctypes.c_double),
                 ("tau_over_dt", ctypes.c_double), ("energy_every", ctypes.c_int32),
-                ("unstable_growth", ctypes.c_double), ("gradient", ctypes.c_int32), ("limiter", ctypes.c_int32)]
+                ("unstable_growth", ctypes.c_double), ("gradient", ctypes.c_int32), ("limiter", ctypes.c_int32),
+                ("chi", ctypes.c_double), ("gamma", ctypes.c_double)]
 
 
 GRADIENT = {"green_gauss": 0, "lsq": 1}
@@ -113,13 +114,15 @@ class Solver:
     float64 ('fp64') or float32 ('fp32').  gradient: 'green_gauss' (the paper's) or 'lsq'
     (least squares; differs only on triangle meshes).  limiter: 'none' or 'minmod' (limited
     slopes for discontinuous data, Cartesian grids; the adjoint refuses a limited solver).
+    phm: None, or (chi, gamma) for the perfectly hyperbolic Maxwell system on a 'cart2d' grid:
+    the fields become (Ez, Hx, Hy, psi), with divergence errors of H carried off at gamma c.
     """
 
     def __init__(self, kind: str = "cart2d", n: Sequence[int] = (64, 64), lo=None, hi=None,
                  bc: Sequence[str] = ("periodic",) * 4, precision: str = "fp64", batch: int = 1,
                  c: float = 1.0, cfl: float = 0.5, dt: float = 0.0, tau_over_dt: float = 0.01,
                  energy_every: int = 0, unstable_growth: float = 0.0, device=None, tri=None,
-                 gradient: str = "green_gauss", limiter: str = "none"):
+                 gradient: str = "green_gauss", limiter: str = "none", phm=None):
         import torch
         L = lib()
         self.torch = torch
@@ -136,6 +139,10 @@ class Solver:
             nd = 2 if kind == "cart2d" else 3
             d.kind = GKS_CART2D if nd == 2 else GKS_CART3D
             d.model = GKS_TM2D if nd == 2 else GKS_EM3D
+            if phm is not None:
+                if nd != 2:
+                    raise ValueError("the PHM fields are built for 'cart2d' grids")
+                d.model = GKS_TM2D_PHM
             n = list(n) + [1] * (3 - len(n))
             lo = list(lo) if lo is not None else [0.0] * nd
             hi = list(hi) if hi is not None else [1.0] * nd
@@ -146,7 +153,7 @@ class Solver:
             bcs = list(bc) + ["periodic"] * (6 - len(bc))
             for i in range(6):
                 d.bc[i] = BC[bcs[i]] if isinstance(bcs[i], str) else int(bcs[i])
-            self.nfields = 3 if nd == 2 else 6
+            self.nfields = (4 if phm is not None else 3) if nd == 2 else 6
             self.grid = (int(n[1]), int(n[0])) if nd == 2 else (int(n[2]), int(n[1]), int(n[0]))
             self.n = tuple(int(v) for v in n[:nd])
         elif kind == "tri2d":
@@ -164,11 +171,15 @@ class Solver:
             d.face_verts = face_verts.ctypes.data
             self.nfields = 3
             self.grid = (int(tris.shape[0]),)
+            if phm is not None:
+                d.model = GKS_TM2D_PHM   # refused by the library: PHM fields are Cartesian 2D only
         else:
             raise ValueError(f"unknown mesh kind {kind!r}")
         grad = GRADIENT[gradient] if isinstance(gradient, str) else int(gradient)
         lim = LIMITER[limiter] if isinstance(limiter, str) else int(limiter)
-        p = Params(c, cfl, dt, tau_over_dt, energy_every, unstable_growth, grad, lim)
+        chi, gamma = (0.0, 0.0) if phm is None else (float(phm[0]), float(phm[1]))
+        self.phm = None if phm is None else (chi, gamma)
+        p = Params(c, cfl, dt, tau_over_dt, energy_every, unstable_growth, grad, lim, chi, gamma)
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             h = ctypes.c_void_p()

@@ -138,6 +138,22 @@ def tm_dielectric_nr(nx=4096, ny=None, seed=0, nsteps=1000, cfl=0.5, tau_over_dt
                     (1.0 / eps)[None], None, cfl, tau_over_dt, nsteps, source=src)
 
 
+def tm_phm_dielectric_nr(nx=4096, ny=None, seed=0, nsteps=1000, cfl=0.5, tau_over_dt=0.01, ncircles=64,
+                         chi=0.0, gamma=1.0, hbump=0.5, pulse: Optional[float] = 1.0, bc=(NONREFLECT,) * 4) -> Workload:
+    """The dielectric workload of tm_dielectric_nr carried by the PHM fields (Ez, Hx, Hy, psi):
+    the same inclusions, point source and initial Ez pulse, plus a divergence error to clean,
+    an Hx Gaussian bump of amplitude hbump (w = 0.05 at (0.65, 0.35)), and psi = 0.  The PHM
+    couplings (chi, gamma) travel in extra["phm"]."""
+    base = tm_dielectric_nr(nx, ny, seed, nsteps, cfl, tau_over_dt, ncircles, pulse, bc)
+    ny = base.n[1]
+    x, y = centres_2d(nx, ny)
+    U = np.zeros((1, 4, ny, nx))
+    U[:, :3] = base.U0
+    U[0, 1] += hbump * gaussian(x, y, 0.65, 0.35, 0.05)
+    return Workload("tm_phm_dielectric_nr", "cart2d", base.n, base.lo, base.hi, base.bc, U, base.epsinv, None, cfl,
+                    tau_over_dt, nsteps, source=base.source, extra={"phm": (float(chi), float(gamma))})
+
+
 def em_blocks_pec(n=384, seed=0, nsteps=500, cfl=1.0 / 3.0, tau_over_dt=0.01, nboxes=32, w=0.05) -> Workload:
     """384^3 style 3D workload: dielectric blocks (sides in [0.05, 0.25], eps in [1, 6]), PEC on
     z = 0, 1, non-reflecting x, y sides; Ez = Gaussian in (x, y), uniform in z; H = 0."""

@@ -13,7 +13,14 @@ BCODE = {I.PERIODIC: O.BC_PERIODIC, I.NONREFLECT: O.BC_NONREFLECT, I.PEC: O.BC_P
 
 
 def model_of(wl):
-    return "tm2d" if wl.kind in ("cart2d", "tri2d") else "em3d"
+    if wl.kind in ("cart2d", "tri2d"):
+        return "tm2d_phm" if wl.U0.shape[1] == 4 else "tm2d"
+    return "em3d"
+
+
+def phm_of(wl):
+    """(chi, gamma) of a PHM workload, (0, 0) otherwise."""
+    return wl.extra.get("phm", (0.0, 0.0))
 
 
 def oracle_mesh(wl):
@@ -41,8 +48,9 @@ def oracle_run(wl, nsteps, dt, b=0, U0=None, t0=0.0, mesh=None, limiter=0):
     U = O.from_soa(np.asarray(U0[b], dtype=np.float64).reshape(nf, -1), model)
     ei = None if wl.epsinv is None else np.asarray(wl.epsinv[b], dtype=np.float64).reshape(-1)
     mi = None if wl.muinv is None else np.asarray(wl.muinv[b], dtype=np.float64).reshape(-1)
+    chi, gamma = phm_of(wl)
     out = O.run(mesh, U, nsteps, dt, wl.tau_over_dt * dt, epsinv=ei, muinv=mi, source=oracle_source(wl), t0=t0,
-                limiter=limiter)
+                limiter=limiter, chi=chi, gamma=gamma)
     return O.to_soa(out, model).reshape(U0.shape[1:])
 
 
@@ -67,8 +75,10 @@ def window_check_2d(wl, U_start, U_end, nsteps, dt, t0, centres, half=None, b=0)
         mesh = O.cart_window((nx, ny, 1), (wl.lo[0], wl.lo[1], 0.0), (wl.hi[0], wl.hi[1], 1.0), bc,
                              (x0, y0, 0), (x1, y1, 1), 2)
         sub = np.asarray(U_start[b][:, y0:y1, x0:x1], dtype=np.float64)
-        U = O.from_soa(sub.reshape(3, -1), "tm2d")
+        nf, model = sub.shape[0], model_of(wl)
+        U = O.from_soa(sub.reshape(nf, -1), model)
         ei = None if wl.epsinv is None else np.ascontiguousarray(wl.epsinv[b][y0:y1, x0:x1]).reshape(-1)
+        mi = None if wl.muinv is None else np.ascontiguousarray(wl.muinv[b][y0:y1, x0:x1]).reshape(-1)
         src = None
         if wl.source is not None:
             cells, wts = [], []
@@ -79,8 +89,10 @@ def window_check_2d(wl, U_start, U_end, nsteps, dt, t0, centres, half=None, b=0)
                     wts.append(w)
             if cells:
                 src = (np.array(cells), np.array(wts), wl.source["J0"], wl.source["t0"], wl.source["sigma_t"])
-        out = O.run(mesh, U, nsteps, dt, wl.tau_over_dt * dt, epsinv=ei, source=src, t0=t0)
-        ref = O.to_soa(out, "tm2d").reshape(3, y1 - y0, x1 - x0)
+        chi, gamma = phm_of(wl)
+        out = O.run(mesh, U, nsteps, dt, wl.tau_over_dt * dt, epsinv=ei, muinv=mi, source=src, t0=t0, chi=chi,
+                    gamma=gamma)
+        ref = O.to_soa(out, model).reshape(nf, y1 - y0, x1 - x0)
         # trusted core: away from cut sides (domain sides are exact)
         lx = 0 if x0 == 0 else margin
         hx = (x1 - x0) if x1 == nx else (x1 - x0) - margin

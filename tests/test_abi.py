@@ -51,7 +51,7 @@ def _init(gks, **over):
         d.lo[i], d.hi[i] = 0.0, 1.0
     p = gks.Params(1.0, 0.5, 0.0, 0.01, 0, 0.0)
     for k, v in over.items():
-        if k in ("c", "cfl", "dt", "tau_over_dt", "energy_every", "unstable_growth"):
+        if k in ("c", "cfl", "dt", "tau_over_dt", "energy_every", "unstable_growth", "limiter", "chi", "gamma"):
             setattr(p, k, v)
         elif k == "n":
             for i, x in enumerate(v):
@@ -80,6 +80,11 @@ def _init(gks, **over):
     ({"tau_over_dt": -1.0}, "tau_over_dt"),
     ({"kind": 1}, "Cartesian"),
     ({"kind": 9}, "kind"),
+    ({"gamma": 0.5}, "PHM couplings"),                        # TM2D takes no PHM couplings
+    ({"model": 2, "gamma": 1.5}, "[0, 1]"),                   # divergence waves faster than c
+    ({"model": 2, "chi": -0.1}, "[0, 1]"),
+    ({"model": 2, "limiter": 1}, "not available with the PHM"),
+    ({"model": 2, "kind": 1, "n": (8, 8, 8)}, "Cartesian 2D"),
 ])
 def test_init_rejects_bad_arguments(gks, over, needle):
     st, msg = _init(gks, **over)
@@ -96,9 +101,9 @@ def test_null_arguments(gks):
     assert L.gks_flux_coefficients(-1.0, 0.0, out) == -1
 
 
-def _tri_init(gks, verts, tris, fc, fv, cfl=0.5, gradient=0, limiter=0):
+def _tri_init(gks, verts, tris, fc, fv, cfl=0.5, gradient=0, limiter=0, model=0):
     d = gks.MeshDesc()
-    d.kind, d.model, d.precision, d.batch = 2, 0, 0, 1
+    d.kind, d.model, d.precision, d.batch = 2, model, 0, 1
     arrs = [np.ascontiguousarray(verts, dtype=np.float64), np.ascontiguousarray(tris, dtype=np.int32),
             np.ascontiguousarray(fc, dtype=np.int32), np.ascontiguousarray(fv, dtype=np.int32)]
     d.nverts, d.ncells, d.nfaces = arrs[0].shape[0], arrs[1].shape[0], arrs[2].shape[0]
@@ -132,6 +137,8 @@ def test_triangle_topology_is_checked(gks):
     assert st == -1 and "Cartesian grids only" in msg
     st, msg = _tri_init(gks, verts, tris, fc, fv, limiter=3)
     assert st == -1 and "minmod" in msg
+    st, msg = _tri_init(gks, verts, tris, fc, fv, model=2)
+    assert st == -1 and "Cartesian 2D" in msg
     # a valid mesh passes the host checks (and then needs a device)
     st, msg = _tri_init(gks, verts, tris, fc, fv)
     assert st in (0, -3), (st, msg)
