@@ -23,6 +23,7 @@ One JSON line on stdout:
                  same grids, and the adjoint step's own per-launch time
   cart2d_phm     the 4096^2 workload carried by the PHM fields (Ez, Hx, Hy, psi) with a
                  divergence error to clean (gamma = 1): throughput and roofline
+  cart3d_phm     the 384^3 workload on the eight PHM fields (chi = gamma = 1)
 
 Helper modes for the profiles: --profile-kernel PREC runs only step kernels (for rocprofv3);
 --profile-tri PREC runs 20 steps of the triangle workload, --profile-3d PREC 10 steps of the 384^3
@@ -378,6 +379,54 @@ def cart3d_leg(torch):
     return out
 
 
+C3_PHM_STEPS = 60
+# 3D with the PHM potentials: read eight fields and 1/eps, write eight fields
+C3_PHM_BYTES_PER_CELL = {"fp32": 17 * 4, "fp64": 17 * 8}
+# two flops per multiply-add of the three face operators a cell owns (168 + 36 + 36 structural
+# non-zeros each), 24 differences and the eight-field update
+C3_PHM_FLOPS_PER_CELL = 2 * 3 * (168 + 72) + 24 + 8 * 4
+
+
+def cart3d_phm_leg(torch):
+    """The 3D workload on the eight PHM fields: 384^3, dielectric blocks, PEC z walls,
+    non-reflecting x/y sides, divergent Ex and Hy bumps, chi = gamma = 1, nu = 1/3."""
+    from paper_2412_16845_amd import inputs as I
+    from paper_2412_16845_amd.gks import Solver
+    wl = I.em_phm_blocks_pec(n=C3_N, seed=0, nsteps=C3_PHM_STEPS)
+    ncell = C3_N ** 3
+    out = {"workload": f"em_phm_blocks_pec: 3D PHM fields (Ex .. Hz, phi, psi) {C3_N}^3, the 384^3 recipe plus "
+                       f"divergent Ex and Hy bumps, chi = gamma = 1, {C3_PHM_STEPS} steps"}
+    for prec in ("fp32", "fp64"):
+        dtype = torch.float64 if prec == "fp64" else torch.float32
+        s = Solver("cart3d", n=wl.n, bc=wl.bc, precision=prec, cfl=wl.cfl, tau_over_dt=wl.tau_over_dt,
+                   phm=wl.extra["phm"])
+        E = torch.tensor(wl.epsinv, dtype=dtype, device="cuda")
+        s.set_material(E)
+        U = torch.tensor(wl.U0, dtype=dtype, device="cuda")
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s.stream)
+        s.run(U, C3_PHM_STEPS)
+        b.record(s.stream)
+        torch.cuda.synchronize()
+        t_run = a.elapsed_time(b) / 1e3
+        if not torch.isfinite(U).all():
+            raise RuntimeError(f"3D PHM {prec} run produced non-finite values")
+        t_launch, _ = time_kernel(torch, s, U, launches=20)
+        alg = C3_PHM_BYTES_PER_CELL[prec] * ncell
+        out[prec] = {"value": round(ncell * C3_PHM_STEPS / t_run, 1), "unit": "cell-updates/s",
+                     "ms_per_step": round(t_run * 1e3 / C3_PHM_STEPS, 4),
+                     "roofline": {"bound": "hbm", "achieved": round(alg / t_launch / 1e9, 1), "peak": PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(alg / t_launch / 1e9 / PEAK_GBS, 4),
+                                  "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch},
+                     "vector_alu": {"flops_per_cell": C3_PHM_FLOPS_PER_CELL,
+                                    "achieved_tflops": round(C3_PHM_FLOPS_PER_CELL * ncell / t_launch / 1e12, 2),
+                                    "peak_tflops_non_packed": 78.6}}
+        del s, E, U
+        torch.cuda.empty_cache()
+    return out
+
+
 C4_H, C4_STEPS = 6.8e-4, 2000
 
 
@@ -577,6 +626,8 @@ def main():
     if not args.no_phm:
         log(f"[bench] PHM 2D: 4096x4096 (Ez, Hx, Hy, psi), {PHM_STEPS} steps, fp32 and fp64")
         out["cart2d_phm"] = phm_leg(torch)
+        log(f"[bench] PHM 3D: 384^3 (eight fields), {C3_PHM_STEPS} steps, fp32 and fp64")
+        out["cart3d_phm"] = cart3d_phm_leg(torch)
     if not args.no_3d:
         log("[bench] 3D: 384^3 six fields, 500 steps, fp32 and fp64")
         out["cart3d"] = cart3d_leg(torch)

@@ -15,8 +15,8 @@
  *     created on; "host" pointers are ordinary CPU memory.
  *   - Field arrays are structure-of-arrays, [batch][field][cell], x fastest on Cartesian
  *     grids (cell = ix + nx*(iy + ny*iz)).  Fields: TM2D (Ez, Hx, Hy); TM2D_PHM (Ez, Hx, Hy,
- *     psi); EM3D (Ex, Ey, Ez, Hx, Hy, Hz).  Units have c = eps0 = mu0 = 1 (Sec. 5), so H and B
- *     coincide in vacuum.
+ *     psi); EM3D (Ex, Ey, Ez, Hx, Hy, Hz); EM3D_PHM (Ex, Ey, Ez, Hx, Hy, Hz, phi, psi).  Units
+ *     have c = eps0 = mu0 = 1 (Sec. 5), so H and B coincide in vacuum.
  *   - The element type is double for GKS_FP64 contexts and float for GKS_FP32 contexts
  *     (in FP32 the flux arithmetic is single precision and the per-cell sum of face fluxes
  *     and its addition to the old value are double precision, rounded once on store).
@@ -47,11 +47,14 @@ typedef enum {
 } gks_status;
 
 typedef enum { GKS_CART2D = 0, GKS_CART3D = 1, GKS_TRI2D = 2 } gks_mesh_kind;
-/* GKS_TM2D_PHM: the TM fields of the perfectly hyperbolic Maxwell system (Sec. 2.1) with the
- * divergence-cleaning potential psi (dpsi/dt + gamma c^2 div H = 0, dH/dt += -gamma grad psi).
- * Its other potential phi follows div E, which TM fields do not have, so phi stays zero and
- * is not stored. */
-typedef enum { GKS_TM2D = 0, GKS_EM3D = 1, GKS_TM2D_PHM = 2 } gks_model;
+/* The perfectly hyperbolic Maxwell (PHM) system (Sec. 2.1) adds the divergence-cleaning
+ * potentials phi phi and psi, coupled through chi and gamma (gks_params), to the fields:
+ *   GKS_TM2D_PHM: the TM fields with psi (dpsi/dt + gamma c^2 div H = 0, dH/dt += -gamma
+ *   grad psi): (Ez, Hx, Hy, psi).  phi follows div E, which TM fields do not have, so it stays
+ *   zero and is not stored.
+ *   GKS_EM3D_PHM: all eight, (Ex, Ey, Ez, Hx, Hy, Hz, phi, psi), with dphi/dt + chi div E = 0
+ *   and dE/dt += -chi c^2 grad phi. */
+typedef enum { GKS_TM2D = 0, GKS_EM3D = 1, GKS_TM2D_PHM = 2, GKS_EM3D_PHM = 3 } gks_model;
 typedef enum { GKS_BC_PERIODIC = 0, GKS_BC_NONREFLECT = 1, GKS_BC_PEC = 2 } gks_bc;
 typedef enum { GKS_FP64 = 0, GKS_FP32 = 1 } gks_precision;
 typedef enum { GKS_GRAD_GREEN_GAUSS = 0, GKS_GRAD_LSQ = 1 } gks_gradient;
@@ -59,7 +62,8 @@ typedef enum { GKS_LIMITER_NONE = 0, GKS_LIMITER_MINMOD = 1 } gks_limiter;
 
 /*
  * Mesh description (host memory; copied by gks_init_mesh, not retained).
- *   Cartesian (GKS_CART2D with GKS_TM2D or GKS_TM2D_PHM, GKS_CART3D with GKS_EM3D): n[3] cells per axis
+ *   Cartesian (GKS_CART2D with GKS_TM2D or GKS_TM2D_PHM, GKS_CART3D with GKS_EM3D or GKS_EM3D_PHM):
+ *   n[3] cells per axis
  *   (n[2] = 1 in 2D), box [lo, hi], bc[6] = x-, x+, y-, y+, z-, z+ sides (the z entries are
  *   ignored in 2D).  A periodic axis must be periodic on both sides.
  *   Triangles (GKS_TRI2D with GKS_TM2D): nverts vertices vert_xy[2*v], ncells triangles
@@ -110,10 +114,10 @@ typedef struct {
  *                 E_b +/- H_a, with a and b the other axes) and of the normal components, in
  *                 place of the central difference.  Cartesian grids only (GKS_EINVAL on a
  *                 triangle mesh).  The limited step is nonlinear: gks_adjoint_step refuses a
- *                 limited context (GKS_ESTATE).  Not available with GKS_TM2D_PHM
+ *                 limited context (GKS_ESTATE).  Not available with the PHM models
  *                 (GKS_EINVAL).  Other values: GKS_EINVAL.
  *   chi, gamma:   couplings of the PHM potentials phi and psi (Sec. 2.1); divergence errors
- *                 of E and H travel at chi c and gamma c.  GKS_TM2D_PHM only: both in [0, 1],
+ *                 of E and H travel at chi c and gamma c.  PHM models only: both in [0, 1],
  *                 so that no wave outruns the lattice speed c (chi has no effect on TM fields).
  *                 Other models: both must be 0 (GKS_EINVAL otherwise).  The potentials carry
  *                 no material factor: 1/eps scales E and 1/mu scales H only.
@@ -195,8 +199,8 @@ gks_status gks_adjoint_step(gks_ctx *ctx, const void *U_n, const void *lam_np1, 
                             double *g_epsinv, double *g_muinv, double t_n);
 
 /* Energy W = 1/2 sum_i |Omega_i| (eps_i |E_i|^2 + mu_i |H_i|^2) of each batch item (plus
- * 1/2 sum_i |Omega_i| psi_i^2 with GKS_TM2D_PHM), summed in double precision in a fixed order;
- * out_host: host, [batch].  Synchronises the stream. */
+ * 1/2 sum_i |Omega_i| (phi_i^2 + psi_i^2) with the PHM models), summed in double precision in
+ * a fixed order; out_host: host, [batch].  Synchronises the stream. */
 gks_status gks_energy(gks_ctx *ctx, const void *U, double *out_host);
 
 /* Probe-box field energy sum_{cells in box} |Omega| Ez^2 of each batch item (Cartesian only;

@@ -191,12 +191,16 @@ static void rotate_fields(const double T[3][3], const double *a, double *b, bool
 }
 
 // Position of field q of a model inside (Ex, Ey, Ez, Hx, Hy, Hz, phi, psi).
-static int model_fields(int model) { return model == GKS_TM2D ? 3 : model == GKS_TM2D_PHM ? 4 : 6; }
+static int model_fields(int model)
+{
+    return model == GKS_TM2D ? 3 : model == GKS_TM2D_PHM ? 4 : model == GKS_EM3D ? 6 : 8;
+}
+static bool model_3d(int model) { return model == GKS_EM3D || model == GKS_EM3D_PHM; }
 static int model_component(int model, int q)
 {
     if (model == GKS_TM2D) return 2 + q;                  // Ez, Hx, Hy
     if (model == GKS_TM2D_PHM) return q < 3 ? 2 + q : 7;  // Ez, Hx, Hy, psi
-    return q;                                             // Ex .. Hz
+    return q;                                             // Ex .. Hz (, phi, psi)
 }
 
 // Axis-aligned Cartesian face with normal +e_ax; inputs and outputs in the global frame:
@@ -209,7 +213,7 @@ static void cart_flux_eval(int model, int ax, double c, Phm ph, const double C[5
                            const double *w, double mE, double mH, double *phi)
 {
     const int nf = model_fields(model);
-    const int nd = (model == GKS_EM3D) ? 3 : 2;
+    const int nd = model_3d(model) ? 3 : 2;
     int axes[3] = {ax, 0, 0};
     for (int i = 0, k = 1; i < nd; ++i)
         if (i != ax) axes[k++] = i;
@@ -310,7 +314,7 @@ bool cart_face_operator(int model, int axis, double c, double chi, double gamma,
                         const double h[3], double dfac, double *k0, double *ke, double *kh, char *err, size_t errlen)
 {
     const int nf = model_fields(model);
-    const int nin = (model == GKS_EM3D) ? 48 : 6 * nf;
+    const int nin = (model_3d(model) ? 8 : 6) * nf;
     auto ev = [&](const double *w, double mE, double mH, double *phi) {
         cart_flux_eval(model, axis, c, Phm{chi, gamma}, C, h, dfac, w, mE, mH, phi);
     };

@@ -40,8 +40,9 @@ struct gks_ctx {
     const void *epsinv = nullptr, *muinv = nullptr;
 
     // face operators in double precision: [orientation][...], sized for the largest tables
-    static constexpr int MAX_N0 = std::max(EM_N0, TP_N0), MAX_NE = std::max(EM_NE, TP_NE),
-                         MAX_NH = std::max(EM_NH, TP_NH);
+    static constexpr int MAX_N0 = std::max(std::max(EM_N0, TP_N0), EP_N0),
+                         MAX_NE = std::max(std::max(EM_NE, TP_NE), EP_NE),
+                         MAX_NH = std::max(std::max(EM_NH, TP_NH), EP_NH);
     double k0[3][MAX_N0], ke[3][MAX_NE], kh[3][MAX_NH];
 
     // point sources
@@ -137,6 +138,10 @@ void pack_ops(const gks_ctx *x, std::vector<char> &buf)
         std::vector<FaceOpTP<T>> ops(2);
         for (int ax = 0; ax < 2; ++ax) fill_op(ops[ax], x->k0[ax], x->ke[ax], x->kh[ax]);
         buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
+    } else if (x->model == GKS_EM3D_PHM) {
+        std::vector<FaceOpEP<T>> ops(3);
+        for (int ax = 0; ax < 3; ++ax) fill_op(ops[ax], x->k0[ax], x->ke[ax], x->kh[ax]);
+        buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
     } else {
         std::vector<FaceOpEM<T>> ops(3);
         for (int ax = 0; ax < 3; ++ax) fill_op(ops[ax], x->k0[ax], x->ke[ax], x->kh[ax]);
@@ -171,12 +176,12 @@ int gks::cart2d_pick_tile_y(int nx, int ny, int batch, int ncu, int precision)
     return std::max(1, std::min(16, ny));
 }
 
-int gks::cart3d_pick_tile_z(int nx, int ny, int nz, int batch, int ncu, int precision)
+int gks::cart3d_pick_tile_z(int nx, int ny, int nz, int batch, int ncu, int precision, int nfields)
 {
     // One workgroup per compute unit at a time (its LDS tile takes most of the unit): the step
     // takes about (rounds of workgroups) x (planes per tile + the three planes the march reads
     // beyond its tile).
-    const int tx = cart3d_tile_x(precision), ty = cart3d_tile_y(precision);
+    const int tx = cart3d_tile_x(precision), ty = cart3d_tile_y(precision, nfields);
     const int64_t per_z = (int64_t)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * batch;
     double best = 1e300;
     int pick = nz;
@@ -252,12 +257,13 @@ gks_status step_cart3d(gks_ctx *x, const void *Uin, void *Uout, double tn)
     a.nz = (int32_t)x->n[2];
     a.batch = (int32_t)x->batch;
     for (int i = 0; i < 6; ++i) a.bc[i] = x->bc[i];
-    const int tx = cart3d_tile_x(x->prec), ty = cart3d_tile_y(x->prec);
+    const int tx = cart3d_tile_x(x->prec), ty = cart3d_tile_y(x->prec, x->nfields);
     a.ntx = (a.nx + tx - 1) / tx;
     a.nty = (a.ny + ty - 1) / ty;
     a.tile_z = x->tile_z;
     a.ntz = (a.nz + a.tile_z - 1) / a.tile_z;
-    a.ops = (const FaceOpEM<T> *)x->d_ops;
+    a.nfields = x->nfields;
+    a.ops = x->d_ops;
     a.limiter = x->limiter;
     int e = launch_cart3d_step<T>(a, x->stream);
     if (e) return hip_fail(x, e, "GKS 3D step launch");
@@ -397,7 +403,8 @@ gks_status launch_energy_into(gks_ctx *x, const void *U, double *dst)
     const double vol = x->h[0] * x->h[1] * (x->kind == GKS_CART3D ? x->h[2] : 1.0);
     const double *cell_vol = (x->kind == GKS_TRI2D) ? x->d_area : nullptr;
     // E components first, then H, then the potentials (weight 1)
-    const int nE = (x->model == GKS_EM3D) ? 3 : 1, nH = (x->model == GKS_EM3D) ? 3 : 2;
+    const bool em = x->model == GKS_EM3D || x->model == GKS_EM3D_PHM;
+    const int nE = em ? 3 : 1, nH = em ? 3 : 2;
     int e;
     if (x->prec == GKS_FP64)
         e = launch_energy<double>((const double *)U, (const double *)x->epsinv, (const double *)x->muinv, x->ncell,
@@ -449,10 +456,11 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
         return fail(nullptr, GKS_EINVAL, "limiter %d is neither none (0) nor minmod (1)", p->limiter);
     if (p->limiter != GKS_LIMITER_NONE && m->kind == GKS_TRI2D)
         return fail(nullptr, GKS_EINVAL, "the slope limiter is defined on Cartesian grids only");
-    if (m->model == GKS_TM2D_PHM) {
+    const bool phm = m->model == GKS_TM2D_PHM || m->model == GKS_EM3D_PHM;
+    if (phm) {
         if (!(p->chi >= 0.0 && p->chi <= 1.0) || !(p->gamma >= 0.0 && p->gamma <= 1.0))
             return fail(nullptr, GKS_EINVAL, "chi and gamma must lie in [0, 1] (divergence waves at most as fast as c)");
-        if (m->kind != GKS_CART2D) return fail(nullptr, GKS_EINVAL, "the PHM fields are built for Cartesian 2D grids");
+        if (m->kind == GKS_TRI2D) return fail(nullptr, GKS_EINVAL, "the PHM fields are built for Cartesian 2D and 3D grids");
         if (p->limiter != GKS_LIMITER_NONE)
             return fail(nullptr, GKS_EINVAL, "the slope limiter is not available with the PHM fields");
     } else if (p->chi != 0.0 || p->gamma != 0.0) {
@@ -467,7 +475,7 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
     x->prec = m->precision;
     x->batch = m->batch;
     x->c = p->c;
-    if (m->model == GKS_TM2D_PHM) {
+    if (phm) {
         x->chi = p->chi;
         x->gamma = p->gamma;
     }
@@ -484,8 +492,9 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
     if (m->kind == GKS_CART2D || m->kind == GKS_CART3D) {
         const int nd = (m->kind == GKS_CART2D) ? 2 : 3;
         if ((m->kind == GKS_CART2D && m->model != GKS_TM2D && m->model != GKS_TM2D_PHM) ||
-            (m->kind == GKS_CART3D && m->model != GKS_EM3D))
-            return bail(fail(x, GKS_EINVAL, "Cartesian 2D grids carry TM2D (or TM2D_PHM) fields and 3D grids EM3D fields"));
+            (m->kind == GKS_CART3D && m->model != GKS_EM3D && m->model != GKS_EM3D_PHM))
+            return bail(fail(x, GKS_EINVAL,
+                             "Cartesian 2D grids carry TM2D (or TM2D_PHM) fields and 3D grids EM3D (or EM3D_PHM) fields"));
         for (int d = 0; d < 3; ++d) {
             const int64_t nn = (d < nd) ? m->n[d] : 1;
             if (d < nd && (nn < 2 || nn > (1 << 30)))
@@ -506,7 +515,7 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
             if ((x->bc[2 * d] == GKS_BC_PERIODIC) != (x->bc[2 * d + 1] == GKS_BC_PERIODIC))
                 return bail(fail(x, GKS_EINVAL, "axis %d is periodic on one side only", d));
         x->ncell = x->n[0] * x->n[1] * x->n[2];
-        x->nfields = (m->model == GKS_TM2D) ? 3 : (m->model == GKS_TM2D_PHM) ? 4 : 6;
+        x->nfields = (m->model == GKS_TM2D) ? 3 : (m->model == GKS_TM2D_PHM) ? 4 : (m->model == GKS_EM3D) ? 6 : 8;
         if ((int64_t)x->nfields * x->ncell > ((int64_t)1 << 31) - 1)
             return bail(fail(x, GKS_EINVAL, "grid too large for 32-bit field indexing"));
         // the kernels address one batch item's fields with 32-bit byte offsets
@@ -564,7 +573,8 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
     if (x->kind == GKS_CART2D)
         x->tile_y = cart2d_pick_tile_y((int)x->n[0], (int)x->n[1], (int)x->batch, x->ncu, x->prec);
     if (x->kind == GKS_CART3D)
-        x->tile_z = cart3d_pick_tile_z((int)x->n[0], (int)x->n[1], (int)x->n[2], (int)x->batch, x->ncu, x->prec);
+        x->tile_z = cart3d_pick_tile_z((int)x->n[0], (int)x->n[1], (int)x->n[2], (int)x->batch, x->ncu, x->prec,
+                                       x->nfields);
     if (x->kind == GKS_TRI2D) {
         gks_status st = (x->prec == GKS_FP64) ? upload_tri<double>(x, tri) : upload_tri<float>(x, tri);
         if (st) return bail(st);
@@ -750,7 +760,7 @@ extern "C" gks_status gks_probe_energy(gks_ctx *ctx, const void *U, const int64_
     st = ensure_out(ctx, (size_t)ctx->batch);
     if (st) return st;
     const double vol = ctx->h[0] * ctx->h[1] * (ctx->kind == GKS_CART3D ? ctx->h[2] : 1.0);
-    const int ezf = (ctx->model == GKS_EM3D) ? 2 : 0;
+    const int ezf = (ctx->model == GKS_EM3D || ctx->model == GKS_EM3D_PHM) ? 2 : 0;
     int e = (ctx->prec == GKS_FP64)
                 ? launch_probe_energy<double>((const double *)U, ctx->n[0], ctx->n[1], ctx->n[2], ctx->nfields, ezf,
                                               (int32_t)ctx->batch, box, vol, ctx->d_partial, ctx->nblk, ctx->d_out,
@@ -775,7 +785,7 @@ extern "C" gks_status gks_probe_energy_grad(gks_ctx *ctx, const void *U, const i
     st = check_device(ctx);
     if (st) return st;
     const double vol = ctx->h[0] * ctx->h[1] * (ctx->kind == GKS_CART3D ? ctx->h[2] : 1.0);
-    const int ezf = (ctx->model == GKS_EM3D) ? 2 : 0;
+    const int ezf = (ctx->model == GKS_EM3D || ctx->model == GKS_EM3D_PHM) ? 2 : 0;
     int e = (ctx->prec == GKS_FP64)
                 ? launch_probe_grad<double>((const double *)U, (double *)lam, ctx->n[0], ctx->n[1], ctx->n[2],
                                             ctx->nfields, ezf, (int32_t)ctx->batch, box, vol, ctx->stream)

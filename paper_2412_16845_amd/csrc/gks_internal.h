@@ -22,6 +22,7 @@ const Pattern &pattern_tri();
 constexpr int TM_N0 = 24, TM_NE = 6, TM_NH = 4;
 constexpr int TP_N0 = 42, TP_NE = 8, TP_NH = 16;
 constexpr int EM_N0 = 80, EM_NE = 12, EM_NH = 12;
+constexpr int EP_N0 = 168, EP_NE = 36, EP_NH = 36;
 
 void flux_coefficients(double dt, double tau, double C[5]);
 // Face operator of an axis-aligned Cartesian face (normal +e_axis), global-frame inputs whose
@@ -42,6 +43,7 @@ struct FaceOp {
 template <typename T> using FaceOpTM = FaceOp<T, TM_N0, TM_NE, TM_NH>;
 template <typename T> using FaceOpTP = FaceOp<T, TP_N0, TP_NE, TP_NH>;
 template <typename T> using FaceOpEM = FaceOp<T, EM_N0, EM_NE, EM_NH>;
+template <typename T> using FaceOpEP = FaceOp<T, EP_N0, EP_NE, EP_NH>;
 
 
 
@@ -76,7 +78,8 @@ struct Cart3DArgs {
     int32_t bc[6];        // x-, x+, y-, y+, z-, z+
     int32_t ntx, nty, ntz;   // workgroup tiles along x, y and z
     int32_t tile_z;          // planes per z tile
-    const FaceOpEM<T> *ops;  // device: x-, y- and z-face operators
+    int32_t nfields;         // 6: (Ex .. Hz); 8: (Ex .. Hz, phi, psi)
+    const void *ops;         // device: x-, y- and z-face operators (FaceOpEM<T> or FaceOpEP<T>)
     int32_t limiter;         // 0: central differences, 1: minmod-limited slopes
 };
 
@@ -148,11 +151,11 @@ template <typename T> int launch_source_scatter(T *U, const T *epsinv, int64_t n
                                                 int32_t batch, int32_t field, const int64_t *cells,
                                                 const double *weight, double amp, int32_t n, void *stream);
 template <typename T> int launch_cart3d_step(const Cart3DArgs<T> &a, void *stream);
-// Output columns / rows per 3D workgroup tile (depend on the element size).
+// Output columns / rows per 3D workgroup tile (depend on the element size and field count).
 int cart3d_tile_x(int precision);
-int cart3d_tile_y(int precision);
+int cart3d_tile_y(int precision, int nfields);
 // Planes per 3D z tile for an nx x ny x nz x batch grid on ncu compute units.
-int cart3d_pick_tile_z(int nx, int ny, int nz, int batch, int ncu, int precision);
+int cart3d_pick_tile_z(int nx, int ny, int nz, int batch, int ncu, int precision, int nfields);
 // Columns written per wave strip (depends on the element size).
 int cart2d_tile_x(int precision);
 // Rows per wave tile for an nx x ny x batch grid on a device with ncu compute units: the

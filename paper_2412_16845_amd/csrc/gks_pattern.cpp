@@ -14,6 +14,7 @@ const Pattern &pattern_cart(int model, int axis)
 {
     if (model == GKS_TM2D) return axis == 0 ? make<PatTMx>() : make<PatTMy>();
     if (model == GKS_TM2D_PHM) return axis == 0 ? make<PatTPx>() : make<PatTPy>();
+    if (model == GKS_EM3D_PHM) return axis == 0 ? make<PatEPx>() : (axis == 1 ? make<PatEPy>() : make<PatEPz>());
     return axis == 0 ? make<PatEMx>() : (axis == 1 ? make<PatEMy>() : make<PatEMz>());
 }
 

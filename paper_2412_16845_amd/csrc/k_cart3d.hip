@@ -1,4 +1,7 @@
-// Fused GKS step on a 3D Cartesian grid, six fields (Ex, Ey, Ez, Hx, Hy, Hz).
+// Fused GKS step on a 3D Cartesian grid, six fields (Ex, Ey, Ez, Hx, Hy, Hz), or the eight of
+// the perfectly hyperbolic Maxwell system with its divergence-cleaning potentials (Ex .. Hz,
+// phi, psi; Sec. 2.1).  The field count NF is a template parameter; everything below applies to
+// both.
 //
 // A workgroup owns a tile of 64 columns (x) by ROWS rows (y) and marches it through a range of
 // z planes.  Wave w holds row w of the tile, one column per lane; the two outermost columns and
@@ -21,7 +24,7 @@
 // materials and the y fluxes are single-buffered, each slot's reads ordered before the next
 // plane's write by a barrier.
 // Boundaries follow the 2D kernel: ghost cells read the wrapped (periodic), mirrored (PEC:
-// tangential E and normal H odd) or clamped (non-reflecting) cell; the ghost side of a
+// tangential E, normal H and phi odd) or clamped (non-reflecting) cell; the ghost side of a
 // non-reflecting boundary face carries no distribution (zero state and slopes).
 #include "gks_device.h"
 
@@ -29,30 +32,53 @@ namespace gks {
 
 namespace {
 
-template <typename T> constexpr int rows3d() { return sizeof(T) == 4 ? 16 : 8; }
+// Rows (waves) per workgroup: the LDS tile below must fit the compute unit's 160 KiB.
+template <typename T, int NF> constexpr int rows3d()
+{
+    return NF == 6 ? (sizeof(T) == 4 ? 16 : 8) : (sizeof(T) == 4 ? 12 : 7);
+}
 constexpr int OUT_X3 = WAVE - 4;
 
-// Fields that change sign under a PEC mirror across an x-, y- or z-wall (tangential E, normal H).
-constexpr uint32_t ODD_X = (1u << 1) | (1u << 2) | (1u << 3);
-constexpr uint32_t ODD_Y = (1u << 0) | (1u << 2) | (1u << 4);
-constexpr uint32_t ODD_Z = (1u << 0) | (1u << 1) | (1u << 5);
+// Fields that change sign under a PEC mirror across an x-, y- or z-wall (tangential E, normal H,
+// and phi, which follows div E; psi is even).
+constexpr uint32_t ODD_X = (1u << 1) | (1u << 2) | (1u << 3) | (1u << 6);
+constexpr uint32_t ODD_Y = (1u << 0) | (1u << 2) | (1u << 4) | (1u << 6);
+constexpr uint32_t ODD_Z = (1u << 0) | (1u << 1) | (1u << 5) | (1u << 6);
 
-template <typename T>
+// Face operators of the two field sets.
+template <int NF> struct Fields3D;
+template <> struct Fields3D<6> {
+    using PX = PatEMx;
+    using PY = PatEMy;
+    using PZ = PatEMz;
+    template <typename T> using Op = FaceOpEM<T>;
+};
+template <> struct Fields3D<8> {
+    using PX = PatEPx;
+    using PY = PatEPy;
+    using PZ = PatEPz;
+    template <typename T> using Op = FaceOpEP<T>;
+};
+
+template <typename T, int NF>
 struct Plane3 {
-    T u[6];
+    T u[NF];
     T mE, mH;
 };
 
-template <typename T>
+template <typename T, int NF>
 struct Lds3 {
-    static constexpr int R = rows3d<T>();
+    static constexpr int R = rows3d<T, NF>();
     // fields of the current plane: double-buffered by plane parity in fp32 (one barrier per plane
     // fewer); single in fp64, whose registers cannot also hold the next plane's fields that long
     static constexpr int NU = sizeof(T) == 4 ? 2 : 1;
-    T u[NU][6][R][WAVE];
-    T g[20][R][WAVE];     // differences [x(6) y(6) z(6)] and mE, mH
-    T p[6][R][WAVE];      // flux of the face above each cell (y)
+    T u[NU][NF][R][WAVE];
+    T g[3 * NF + 2][R][WAVE];   // differences [x(NF) y(NF) z(NF)] and mE, mH
+    T p[NF][R][WAVE];           // flux of the face above each cell (y)
 };
+static_assert(sizeof(Lds3<float, 6>) <= 160 * 1024 && sizeof(Lds3<double, 6>) <= 160 * 1024 &&
+                  sizeof(Lds3<float, 8>) <= 160 * 1024 && sizeof(Lds3<double, 8>) <= 160 * 1024,
+              "LDS tile above 160 KiB");
 
 __device__ __forceinline__ bool side_nr(int g, int n, int bclo, int bchi)
 {
@@ -73,11 +99,14 @@ __device__ __forceinline__ void limit_axis(const T (&up)[6], const T (&c)[6], co
     out[3 + K] = T(2) * minmod(up[3 + K] - c[3 + K], c[3 + K] - dn[3 + K]);
 }
 
-template <typename T, bool HAS_EPS, bool HAS_MU, bool BXY, bool LIM>
+template <typename T, int NF, bool HAS_EPS, bool HAS_MU, bool BXY, bool LIM>
 struct March3D {
-    static constexpr int R = rows3d<T>();
+    static_assert(!LIM || NF == 6, "the limited step is built for the six Maxwell fields only");
+    static constexpr int R = rows3d<T, NF>();
+    using OpT = typename Fields3D<NF>::template Op<T>;
+    using Plane = Plane3<T, NF>;
     const Cart3DArgs<T> &a;
-    Lds3<T> &s;
+    Lds3<T, NF> &s;
     Rsrc rU, rE, rM, rO;
     uint32_t fbytes, pbytes;   // bytes per field, per plane
     uint32_t vcol;             // byte offset of the cell this lane reads, inside a plane
@@ -87,23 +116,23 @@ struct March3D {
     int lane, row, rowp, rowm, z0, z1;
     bool need_g, need_yf, need_all;   // wave roles by row
 
-    __device__ __forceinline__ void load(int gz, Plane3<T> &p) const
+    __device__ __forceinline__ void load(int gz, Plane &p) const
     {
         bool mz, nrz;
         const int sz = map_axis(gz, a.nz, a.bc[4], a.bc[5], mz, nrz);
         const uint32_t so = (uint32_t)sz * pbytes;
 #pragma unroll
-        for (int f = 0; f < 6; ++f) p.u[f] = buf_load<T>(rU, vcol, so + f * fbytes);
+        for (int f = 0; f < NF; ++f) p.u[f] = buf_load<T>(rU, vcol, so + f * fbytes);
         p.mE = HAS_EPS ? buf_load<T>(rE, vcol, so) : T(1);
         p.mH = HAS_MU ? buf_load<T>(rM, vcol, so) : T(1);
         if constexpr (BXY) {
 #pragma unroll
-            for (int f = 0; f < 6; ++f)
+            for (int f = 0; f < NF; ++f)
                 if ((sgn >> f) & 1u) p.u[f] = -p.u[f];
         }
         if (mz) {   // uniform: a mirrored ghost plane
 #pragma unroll
-            for (int f = 0; f < 6; ++f)
+            for (int f = 0; f < NF; ++f)
                 if ((ODD_Z >> f) & 1u) p.u[f] = -p.u[f];
         }
     }
@@ -113,161 +142,164 @@ struct March3D {
     // One march step with central plane q: A = q-1, B = q, C = q+1 (loaded), D receives q+2.
     // Gp / G: differences of planes q-1 / q.  acc: on entry the x and y divergence of plane
     // q-1 minus the flux of the z face below it; on exit the same for plane q.
-    __device__ __forceinline__ void step(int q, Plane3<T> &A, Plane3<T> &B, Plane3<T> &C, Plane3<T> &D,
-                                         T (&Gp)[18], T (&G)[18], T (&acc)[6]) const
+    __device__ __forceinline__ void step(int q, Plane &A, Plane &B, Plane &C, Plane &D, T (&Gp)[3 * NF],
+                                         T (&G)[3 * NF], T (&acc)[NF]) const
     {
+        const OpT *ops = (const OpT *)a.ops;
         // plane q+2 (beyond the range: re-read the last halo plane, already cached, so that the
         // load stays unconditional)
         load(min(q + 2, z1 + 1), D);
-        constexpr int NU = Lds3<T>::NU;
+        constexpr int NU = Lds3<T, NF>::NU;
         if constexpr (NU == 1) {
 #pragma unroll
-            for (int f = 0; f < 6; ++f) s.u[0][f][row][lane] = B.u[f];
+            for (int f = 0; f < NF; ++f) s.u[0][f][row][lane] = B.u[f];
             __syncthreads();
         }
         // (double-buffered: the fields of plane q were shared at the end of the previous step)
         const int cu = NU == 2 ? (q & 1) : 0;
-        T uy[6];   // fields of the row above (plane q)
+        T uy[NF];   // fields of the row above (plane q)
         if (need_g) {
 #pragma unroll
-            for (int f = 0; f < 6; ++f) {
+            for (int f = 0; f < NF; ++f) {
                 uy[f] = s.u[cu][f][rowp][lane];
                 G[f] = from_right(B.u[f]) - from_left(B.u[f]);
-                G[6 + f] = uy[f] - s.u[cu][f][rowm][lane];
-                G[12 + f] = C.u[f] - A.u[f];
+                G[NF + f] = uy[f] - s.u[cu][f][rowm][lane];
+                G[2 * NF + f] = C.u[f] - A.u[f];
             }
             if constexpr (LIM) {
                 T xr[6], xl[6], ym[6];
 #pragma unroll
-                for (int f = 0; f < 6; ++f) {
+                for (int f = 0; f < NF; ++f) {
                     xr[f] = from_right(B.u[f]);
                     xl[f] = from_left(B.u[f]);
                     ym[f] = s.u[cu][f][rowm][lane];
                 }
                 limit_axis<0>(xr, B.u, xl, G);
-                limit_axis<1>(uy, B.u, ym, G + 6);
-                limit_axis<2>(C.u, B.u, A.u, G + 12);
+                limit_axis<1>(uy, B.u, ym, G + NF);
+                limit_axis<2>(C.u, B.u, A.u, G + 2 * NF);
             }
             // every face that reads the differences of a non-reflecting ghost zeroes them:
             // zero them at the source (the lane itself), so that the values neighbours receive
             // by DPP or LDS need no select on the receiving side
             if constexpr (BXY) {
 #pragma unroll
-                for (int k = 0; k < 18; ++k) G[k] = nr_c ? T(0) : G[k];
+                for (int k = 0; k < 3 * NF; ++k) G[k] = nr_c ? T(0) : G[k];
             }
         }
         // face below plane q, then the update of plane q-1, whose divergence it completes
         if (q >= z0 && need_all) {
-            // inputs [UL UR dzL dxL dyL dzR dxR dyR], L plane q-1
+            // inputs [UL UR dzL dxL dyL dzR dxR dyR] x fields, L plane q-1
             const bool zl = plane_nr(q - 1) || (BXY && nr_c), zr = plane_nr(q) || (BXY && nr_c);
-            const auto opz = scalar_ptr_after(a.ops + 2, G[17]);
-            T w[48], Z[6];
+            const auto opz = scalar_ptr_after(ops + 2, G[3 * NF - 1]);
+            T w[8 * NF], Z[NF];
 #pragma unroll
-            for (int f = 0; f < 6; ++f) {
+            for (int f = 0; f < NF; ++f) {
                 w[f] = zl ? T(0) : A.u[f];
-                w[6 + f] = zr ? T(0) : B.u[f];
-                w[12 + f] = zl ? T(0) : Gp[12 + f];
-                w[18 + f] = zl ? T(0) : Gp[f];
-                w[24 + f] = zl ? T(0) : Gp[6 + f];
-                w[30 + f] = zr ? T(0) : G[12 + f];
-                w[36 + f] = zr ? T(0) : G[f];
-                w[42 + f] = zr ? T(0) : G[6 + f];
+                w[NF + f] = zr ? T(0) : B.u[f];
+                w[2 * NF + f] = zl ? T(0) : Gp[2 * NF + f];
+                w[3 * NF + f] = zl ? T(0) : Gp[f];
+                w[4 * NF + f] = zl ? T(0) : Gp[NF + f];
+                w[5 * NF + f] = zr ? T(0) : G[2 * NF + f];
+                w[6 * NF + f] = zr ? T(0) : G[f];
+                w[7 * NF + f] = zr ? T(0) : G[NF + f];
             }
-            apply_op<PatEMz>(w, A.mE + B.mE, A.mH + B.mH, opz, Z);
+            apply_op<typename Fields3D<NF>::PZ>(w, A.mE + B.mE, A.mH + B.mH, opz, Z);
             if (q - 1 >= z0) {
                 const uint32_t so = (uint32_t)(q - 1) * pbytes;
 #pragma unroll
-                for (int f = 0; f < 6; ++f) {
+                for (int f = 0; f < NF; ++f) {
                     const T div = acc[f] + Z[f];
-                    const double m = (f < 3) ? (double)A.mE : (double)A.mH;
+                    // 1/eps scales E, 1/mu scales H; the potentials carry no material factor
+                    const double m = (f < 3) ? (double)A.mE : (f < 6) ? (double)A.mH : 1.0;
                     const T nv = (T)((double)A.u[f] - m * (double)div);
                     if (writer) buf_store(nv, rO, vcol, so + f * fbytes);
                 }
             }
 #pragma unroll
-            for (int f = 0; f < 6; ++f) acc[f] = -Z[f];
+            for (int f = 0; f < NF; ++f) acc[f] = -Z[f];
         }
         if (need_g) {
 #pragma unroll
-            for (int k = 0; k < 18; ++k) s.g[k][row][lane] = G[k];
-            s.g[18][row][lane] = B.mE;
-            s.g[19][row][lane] = B.mH;
+            for (int k = 0; k < 3 * NF; ++k) s.g[k][row][lane] = G[k];
+            s.g[3 * NF][row][lane] = B.mE;
+            s.g[3 * NF + 1][row][lane] = B.mH;
         }
         __syncthreads();
         const bool outp = q >= z0 && q < z1;
-        T px[6], py[6];
+        T px[NF], py[NF];
         // this cell's fields as a face side: zero on a non-reflecting ghost (the DPP moves
         // below then read them unconditionally: a move under a partial lane mask would read the
         // masked lanes as zero)
-        T su[6];
+        T su[NF];
 #pragma unroll
-        for (int f = 0; f < 6; ++f) su[f] = (BXY && nr_c) ? T(0) : B.u[f];
+        for (int f = 0; f < NF; ++f) su[f] = (BXY && nr_c) ? T(0) : B.u[f];
         if (outp && need_yf) {
-            // face above: inputs [UL UR dyL dxL dzL dyR dxR dzR], L this row, R the row above
+            // face above: inputs [UL UR dyL dxL dzL dyR dxR dzR] x fields, L this row, R the row above
             const bool zr = BXY && nr_y;
-            const auto opy = scalar_ptr(a.ops + 1);
-            T w[48];
+            const auto opy = scalar_ptr(ops + 1);
+            T w[8 * NF];
 #pragma unroll
-            for (int f = 0; f < 6; ++f) {
+            for (int f = 0; f < NF; ++f) {
                 w[f] = su[f];
-                w[6 + f] = zr ? T(0) : uy[f];
-                w[12 + f] = G[6 + f];
-                w[18 + f] = G[f];
-                w[24 + f] = G[12 + f];
-                w[30 + f] = s.g[6 + f][rowp][lane];
-                w[36 + f] = s.g[f][rowp][lane];
-                w[42 + f] = s.g[12 + f][rowp][lane];
+                w[NF + f] = zr ? T(0) : uy[f];
+                w[2 * NF + f] = G[NF + f];
+                w[3 * NF + f] = G[f];
+                w[4 * NF + f] = G[2 * NF + f];
+                w[5 * NF + f] = s.g[NF + f][rowp][lane];
+                w[6 * NF + f] = s.g[f][rowp][lane];
+                w[7 * NF + f] = s.g[2 * NF + f][rowp][lane];
             }
-            apply_op<PatEMy>(w, B.mE + s.g[18][rowp][lane], B.mH + s.g[19][rowp][lane], opy, py);
+            apply_op<typename Fields3D<NF>::PY>(w, B.mE + s.g[3 * NF][rowp][lane], B.mH + s.g[3 * NF + 1][rowp][lane],
+                                                opy, py);
 #pragma unroll
-            for (int f = 0; f < 6; ++f) s.p[f][row][lane] = py[f];
+            for (int f = 0; f < NF; ++f) s.p[f][row][lane] = py[f];
         }
         if (outp && need_all) {
-            // face to the right: inputs [UL UR dxL dyL dzL dxR dyR dzR], R the next lane
-            const auto opx = scalar_ptr_after(a.ops, py[5]);
-            T w[48];
+            // face to the right: inputs [UL UR dxL dyL dzL dxR dyR dzR] x fields, R the next lane
+            const auto opx = scalar_ptr_after(ops, py[NF - 1]);
+            T w[8 * NF];
 #pragma unroll
-            for (int f = 0; f < 6; ++f) {
+            for (int f = 0; f < NF; ++f) {
                 w[f] = su[f];
-                w[6 + f] = from_right(su[f]);
-                w[12 + f] = G[f];
-                w[18 + f] = G[6 + f];
-                w[24 + f] = G[12 + f];
-                w[30 + f] = from_right(G[f]);
-                w[36 + f] = from_right(G[6 + f]);
-                w[42 + f] = from_right(G[12 + f]);
+                w[NF + f] = from_right(su[f]);
+                w[2 * NF + f] = G[f];
+                w[3 * NF + f] = G[NF + f];
+                w[4 * NF + f] = G[2 * NF + f];
+                w[5 * NF + f] = from_right(G[f]);
+                w[6 * NF + f] = from_right(G[NF + f]);
+                w[7 * NF + f] = from_right(G[2 * NF + f]);
             }
-            apply_op<PatEMx>(w, B.mE + from_right(B.mE), B.mH + from_right(B.mH), opx, px);
+            apply_op<typename Fields3D<NF>::PX>(w, B.mE + from_right(B.mE), B.mH + from_right(B.mH), opx, px);
         }
         if constexpr (NU == 2) {
             // share the fields of plane q+1 in the other buffer (its last readers, in the
             // previous step, are all past this step's first barrier); the barrier below
             // publishes them with the y fluxes
 #pragma unroll
-            for (int f = 0; f < 6; ++f) s.u[cu ^ 1][f][row][lane] = C.u[f];
+            for (int f = 0; f < NF; ++f) s.u[cu ^ 1][f][row][lane] = C.u[f];
         }
         __syncthreads();
         if (outp && need_all) {
 #pragma unroll
-            for (int f = 0; f < 6; ++f) acc[f] += (px[f] - from_left(px[f])) + (py[f] - s.p[f][rowm][lane]);
+            for (int f = 0; f < NF; ++f) acc[f] += (px[f] - from_left(px[f])) + (py[f] - s.p[f][rowm][lane]);
         }
     }
 
     __device__ __forceinline__ void run() const
     {
-        Plane3<T> P0, P1, P2, P3;
-        T G0[18], G1[18], acc[6];
+        Plane P0, P1, P2, P3;
+        T G0[3 * NF], G1[3 * NF], acc[NF];
 #pragma unroll
-        for (int k = 0; k < 18; ++k) G0[k] = G1[k] = T(0);
+        for (int k = 0; k < 3 * NF; ++k) G0[k] = G1[k] = T(0);
 #pragma unroll
-        for (int f = 0; f < 6; ++f) acc[f] = T(0);
+        for (int f = 0; f < NF; ++f) acc[f] = T(0);
         const int qs = z0 - 1;
         load(qs - 1, P0);
         load(qs, P1);
         load(qs + 1, P2);
-        if constexpr (Lds3<T>::NU == 2) {
+        if constexpr (Lds3<T, NF>::NU == 2) {
 #pragma unroll
-            for (int f = 0; f < 6; ++f) s.u[qs & 1][f][row][lane] = P1.u[f];
+            for (int f = 0; f < NF; ++f) s.u[qs & 1][f][row][lane] = P1.u[f];
             __syncthreads();
         }
         const int n = z1 - z0 + 2;   // central planes z0-1 .. z1
@@ -283,11 +315,11 @@ struct March3D {
     }
 };
 
-template <typename T, bool HAS_EPS, bool HAS_MU, bool LIM>
-__global__ __launch_bounds__(WAVE * rows3d<T>()) void cart3d_step_kernel(Cart3DArgs<T> a)
+template <typename T, int NF, bool HAS_EPS, bool HAS_MU, bool LIM>
+__global__ __launch_bounds__((WAVE * rows3d<T, NF>())) void cart3d_step_kernel(Cart3DArgs<T> a)
 {
-    constexpr int R = rows3d<T>();
-    __shared__ Lds3<T> lds;
+    constexpr int R = rows3d<T, NF>();
+    __shared__ Lds3<T, NF> lds;
     const int lane = threadIdx.x & (WAVE - 1);
     const int row = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     int t = xcd_logical_block();
@@ -301,8 +333,8 @@ __global__ __launch_bounds__(WAVE * rows3d<T>()) void cart3d_step_kernel(Cart3DA
     const int64_t ncell = (int64_t)a.nx * a.ny * a.nz;
     const uint32_t fbytes = (uint32_t)(ncell * (int64_t)sizeof(T));
     const uint32_t pbytes = (uint32_t)((int64_t)a.nx * a.ny * (int64_t)sizeof(T));
-    const Rsrc rU = make_rsrc(a.U + (int64_t)b * 6 * ncell, 6ull * fbytes);
-    const Rsrc rO = make_rsrc(a.Unew + (int64_t)b * 6 * ncell, 6ull * fbytes);
+    const Rsrc rU = make_rsrc(a.U + (int64_t)b * NF * ncell, (uint64_t)NF * fbytes);
+    const Rsrc rO = make_rsrc(a.Unew + (int64_t)b * NF * ncell, (uint64_t)NF * fbytes);
     const Rsrc rE = make_rsrc(a.epsinv ? a.epsinv + (int64_t)b * ncell : a.U, fbytes);
     const Rsrc rM = make_rsrc(a.muinv ? a.muinv + (int64_t)b * ncell : a.U, fbytes);
 
@@ -318,7 +350,7 @@ __global__ __launch_bounds__(WAVE * rows3d<T>()) void cart3d_step_kernel(Cart3DA
 
     auto go = [&](auto bnd) {
         constexpr bool BXY = decltype(bnd)::value;
-        March3D<T, HAS_EPS, HAS_MU, BXY, LIM> m{a, lds, rU, rE, rM, rO, fbytes, pbytes};
+        March3D<T, NF, HAS_EPS, HAS_MU, BXY, LIM> m{a, lds, rU, rE, rM, rO, fbytes, pbytes};
         m.vcol = (uint32_t)((int64_t)sy * a.nx + sx) * (uint32_t)sizeof(T);
         m.sgn = (mx ? ODD_X : 0u) ^ (my ? ODD_Y : 0u);
         m.nr_c = nrx || nry;
@@ -346,19 +378,30 @@ template <typename T>
 int launch_cart3d_step(const Cart3DArgs<T> &a, void *stream)
 {
     const unsigned blocks = (unsigned)(a.ntx * a.nty * a.ntz * a.batch);
-    dim3 grid(blocks), block(WAVE * rows3d<T>());
+    dim3 grid(blocks);
     hipStream_t s = (hipStream_t)stream;
-    if (a.limiter) {
-        if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, true, true, true>), grid, block, 0, s, a);
-        else if (a.epsinv) hipLaunchKernelGGL((cart3d_step_kernel<T, true, false, true>), grid, block, 0, s, a);
-        else if (a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, false, true, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((cart3d_step_kernel<T, false, false, true>), grid, block, 0, s, a);
+    if (a.nfields == 8) {   // with the PHM potentials (never limited: the host refuses that)
+        if (a.limiter) return (int)hipErrorInvalidValue;
+        dim3 block(WAVE * rows3d<T, 8>());
+        if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, 8, true, true, false>), grid, block, 0, s, a);
+        else if (a.epsinv) hipLaunchKernelGGL((cart3d_step_kernel<T, 8, true, false, false>), grid, block, 0, s, a);
+        else if (a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, 8, false, true, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((cart3d_step_kernel<T, 8, false, false, false>), grid, block, 0, s, a);
         return (int)hipGetLastError();
     }
-    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, true, true, false>), grid, block, 0, s, a);
-    else if (a.epsinv) hipLaunchKernelGGL((cart3d_step_kernel<T, true, false, false>), grid, block, 0, s, a);
-    else if (a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, false, true, false>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((cart3d_step_kernel<T, false, false, false>), grid, block, 0, s, a);
+    if (a.nfields != 6) return (int)hipErrorInvalidValue;
+    dim3 block(WAVE * rows3d<T, 6>());
+    if (a.limiter) {
+        if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, 6, true, true, true>), grid, block, 0, s, a);
+        else if (a.epsinv) hipLaunchKernelGGL((cart3d_step_kernel<T, 6, true, false, true>), grid, block, 0, s, a);
+        else if (a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, 6, false, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((cart3d_step_kernel<T, 6, false, false, true>), grid, block, 0, s, a);
+        return (int)hipGetLastError();
+    }
+    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, 6, true, true, false>), grid, block, 0, s, a);
+    else if (a.epsinv) hipLaunchKernelGGL((cart3d_step_kernel<T, 6, true, false, false>), grid, block, 0, s, a);
+    else if (a.muinv) hipLaunchKernelGGL((cart3d_step_kernel<T, 6, false, true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((cart3d_step_kernel<T, 6, false, false, false>), grid, block, 0, s, a);
     return (int)hipGetLastError();
 }
 
@@ -366,6 +409,10 @@ template int launch_cart3d_step<float>(const Cart3DArgs<float> &, void *);
 template int launch_cart3d_step<double>(const Cart3DArgs<double> &, void *);
 
 int cart3d_tile_x(int) { return OUT_X3; }
-int cart3d_tile_y(int precision) { return precision == GKS_FP64 ? rows3d<double>() - 4 : rows3d<float>() - 4; }
+int cart3d_tile_y(int precision, int nfields)
+{
+    if (nfields == 8) return precision == GKS_FP64 ? rows3d<double, 8>() - 4 : rows3d<float, 8>() - 4;
+    return precision == GKS_FP64 ? rows3d<double, 6>() - 4 : rows3d<float, 6>() - 4;
+}
 
 }  // namespace gks

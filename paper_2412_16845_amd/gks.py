@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "libgks.so")
 
 GKS_CART2D, GKS_CART3D, GKS_TRI2D = 0, 1, 2
-GKS_TM2D, GKS_EM3D, GKS_TM2D_PHM = 0, 1, 2
+GKS_TM2D, GKS_EM3D, GKS_TM2D_PHM, GKS_EM3D_PHM = 0, 1, 2, 3
 BC = {"periodic": 0, "nonreflecting": 1, "pec": 2}
 PRECISION = {"fp64": 0, "fp32": 1}
 STATUS = {0: "GKS_OK", -1: "GKS_EINVAL", -2: "GKS_ENOMEM", -3: "GKS_EDEVICE", -4: "GKS_EUNSTABLE",
@@ -114,8 +114,9 @@ class Solver:
     float64 ('fp64') or float32 ('fp32').  gradient: 'green_gauss' (the paper's) or 'lsq'
     (least squares; differs only on triangle meshes).  limiter: 'none' or 'minmod' (limited
     slopes for discontinuous data, Cartesian grids; the adjoint refuses a limited solver).
-    phm: None, or (chi, gamma) for the perfectly hyperbolic Maxwell system on a 'cart2d' grid:
-    the fields become (Ez, Hx, Hy, psi), with divergence errors of H carried off at gamma c.
+    phm: None, or (chi, gamma) for the perfectly hyperbolic Maxwell system on a Cartesian grid:
+    the fields become (Ez, Hx, Hy, psi) in 2D and (Ex, Ey, Ez, Hx, Hy, Hz, phi, psi) in 3D, with
+    divergence errors of E and H carried off at chi c and gamma c.
     """
 
     def __init__(self, kind: str = "cart2d", n: Sequence[int] = (64, 64), lo=None, hi=None,
@@ -140,9 +141,7 @@ class Solver:
             d.kind = GKS_CART2D if nd == 2 else GKS_CART3D
             d.model = GKS_TM2D if nd == 2 else GKS_EM3D
             if phm is not None:
-                if nd != 2:
-                    raise ValueError("the PHM fields are built for 'cart2d' grids")
-                d.model = GKS_TM2D_PHM
+                d.model = GKS_TM2D_PHM if nd == 2 else GKS_EM3D_PHM
             n = list(n) + [1] * (3 - len(n))
             lo = list(lo) if lo is not None else [0.0] * nd
             hi = list(hi) if hi is not None else [1.0] * nd
@@ -153,7 +152,7 @@ class Solver:
             bcs = list(bc) + ["periodic"] * (6 - len(bc))
             for i in range(6):
                 d.bc[i] = BC[bcs[i]] if isinstance(bcs[i], str) else int(bcs[i])
-            self.nfields = (4 if phm is not None else 3) if nd == 2 else 6
+            self.nfields = (4 if phm is not None else 3) if nd == 2 else (8 if phm is not None else 6)
             self.grid = (int(n[1]), int(n[0])) if nd == 2 else (int(n[2]), int(n[1]), int(n[0]))
             self.n = tuple(int(v) for v in n[:nd])
         elif kind == "tri2d":

@@ -172,6 +172,24 @@ def em_blocks_pec(n=384, seed=0, nsteps=500, cfl=1.0 / 3.0, tau_over_dt=0.01, nb
                     (1.0 / eps)[None], None, cfl, tau_over_dt, nsteps)
 
 
+def em_phm_blocks_pec(n=384, seed=0, nsteps=500, cfl=1.0 / 3.0, tau_over_dt=0.01, nboxes=32, w=0.05, chi=1.0,
+                      gamma=1.0, bump=0.5, bc=None) -> Workload:
+    """The 3D workload of em_blocks_pec carried by the PHM fields (Ex, Ey, Ez, Hx, Hy, Hz, phi,
+    psi), plus divergence errors to clean: an Ex and an Hy Gaussian bump of amplitude `bump`
+    (w = 0.05 at (0.3, 0.6, 0.5) and (0.65, 0.35, 0.4)); phi = psi = 0.  The couplings travel in
+    extra["phm"]."""
+    base = em_blocks_pec(n, seed, nsteps, cfl, tau_over_dt, nboxes, w)
+    nx, ny, nz = base.n
+    x, y, z = np.meshgrid(*((np.arange(m) + 0.5) / m for m in (nx, ny, nz)), indexing="ij")
+    g = lambda c: np.exp(-((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) / (2 * 0.05 ** 2)).transpose(2, 1, 0)
+    U = np.zeros((1, 8, nz, ny, nx))
+    U[:, :6] = base.U0
+    U[0, 0] += bump * g((0.3, 0.6, 0.5))
+    U[0, 4] += bump * g((0.65, 0.35, 0.4))
+    return Workload("em_phm_blocks_pec", "cart3d", base.n, base.lo, base.hi, base.bc if bc is None else tuple(bc), U,
+                    base.epsinv, None, cfl, tau_over_dt, nsteps, extra={"phm": (float(chi), float(gamma))})
+
+
 def tm_batch_probe(n=1024, batch=8, seed=0, nsteps=800, cfl=0.5, tau_over_dt=0.01, ncircles=16,
                    w=0.05) -> Workload:
     """Batch of dielectric maps (16 discs, radii [0.03, 0.1], eps [1, 4]); Ez Gaussian at

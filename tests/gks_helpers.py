@@ -15,7 +15,7 @@ BCODE = {I.PERIODIC: O.BC_PERIODIC, I.NONREFLECT: O.BC_NONREFLECT, I.PEC: O.BC_P
 def model_of(wl):
     if wl.kind in ("cart2d", "tri2d"):
         return "tm2d_phm" if wl.U0.shape[1] == 4 else "tm2d"
-    return "em3d"
+    return "em3d_phm" if wl.U0.shape[1] == 8 else "em3d"
 
 
 def phm_of(wl):
@@ -118,12 +118,14 @@ def window_check_3d(wl, U_start, U_end, nsteps, dt, t0, centres, half=None, b=0)
         mesh = O.cart_window(tuple(n), tuple(wl.lo), tuple(wl.hi), bc, tuple(lo), tuple(hi), 3)
         sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
         sub = np.asarray(U_start[b][(slice(None),) + sl], dtype=np.float64)
-        U = O.from_soa(sub.reshape(6, -1), "em3d")
+        nf, model = sub.shape[0], model_of(wl)
+        U = O.from_soa(sub.reshape(nf, -1), model)
         ei = None if wl.epsinv is None else np.ascontiguousarray(wl.epsinv[b][sl], dtype=np.float64).reshape(-1)
         mi = None if wl.muinv is None else np.ascontiguousarray(wl.muinv[b][sl], dtype=np.float64).reshape(-1)
-        out = O.run(mesh, U, nsteps, dt, wl.tau_over_dt * dt, epsinv=ei, muinv=mi, t0=t0)
+        chi, gamma = phm_of(wl)
+        out = O.run(mesh, U, nsteps, dt, wl.tau_over_dt * dt, epsinv=ei, muinv=mi, t0=t0, chi=chi, gamma=gamma)
         m = [hi[d] - lo[d] for d in range(3)]
-        ref = O.to_soa(out, "em3d").reshape(6, m[2], m[1], m[0])
+        ref = O.to_soa(out, model).reshape(nf, m[2], m[1], m[0])
         core = []
         for d in range(3):
             a = 0 if lo[d] == 0 else margin

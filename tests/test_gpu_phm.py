@@ -1,5 +1,5 @@
-"""GPU parity of the 2D step with the PHM divergence-cleaning potential psi (fields Ez, Hx, Hy,
-psi; Sec. 2.1) against the FP64 oracle's eight-component PHM step, through the C ABI.
+"""GPU parity of the steps with the PHM divergence-cleaning potentials (Sec. 2.1): 2D (Ez, Hx, Hy,
+psi) and 3D (Ex .. Hz, phi, psi), against the FP64 oracle's eight-component step, through the C ABI.
 
 Tolerances as for the TM step: relative L2 over all fields, cells and batch items, FP64 1e-12,
 FP32 1e-5.
@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2412_16845_amd import inputs as I
-from tests.gks_helpers import oracle_run, rel_l2, window_check_2d
+from tests.gks_helpers import oracle_run, rel_l2, window_check_2d, window_check_3d
 
 pytestmark = pytest.mark.gpu
 
@@ -146,4 +146,96 @@ def test_phm_full_size_sampled(torch, precision):
     g, o = window_check_2d(wl, A, B, K, s.dt, (wl.nsteps - K) * s.dt, centres)
     err = rel_l2(g, o)
     print(f"PHM 4096^2 {precision} sampled windows: rel L2 = {err:.3e} over {g.size} values")
+    assert err <= TOL[precision]
+
+
+# ---------------------------------------------------------------------------- 3D: all eight fields
+N3, P3, R3 = I.NONREFLECT, I.PEC, I.PERIODIC
+
+
+def setup3(torch, wl, precision):
+    from paper_2412_16845_amd.gks import Solver
+    s = Solver("cart3d", n=wl.n, lo=wl.lo, hi=wl.hi, bc=wl.bc, precision=precision, batch=wl.batch, cfl=wl.cfl,
+               tau_over_dt=wl.tau_over_dt, phm=wl.extra["phm"])
+    ei = None if wl.epsinv is None else to_dev(torch, wl.epsinv, precision)
+    mi = None if wl.muinv is None else to_dev(torch, wl.muinv, precision)
+    s.set_material(ei, mi)
+    if wl.source is not None:
+        src = wl.source
+        s.set_point_source(src["cells"], src["weights"], src["J0"], src["t0"], src["sigma_t"])
+    return s, to_dev(torch, wl.U0, precision)
+
+
+def random3(n, bc, seed, batch=1, mu=False, tau_hat=0.01, nsteps=6, phm=(0.7, 0.9), source=None):
+    """Random normal values in all eight components, random 1/eps in [0.25, 1], 1/mu in [0.5, 1]."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = n
+    U = rng.standard_normal((batch, 8, nz, ny, nx))
+    ei = rng.uniform(0.25, 1.0, (batch, nz, ny, nx))
+    mi = rng.uniform(0.5, 1.0, (batch, nz, ny, nx)) if mu else None
+    return I.Workload("phm3d", "cart3d", tuple(n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), tuple(bc), U, ei, mi, 1.0 / 3.0,
+                      tau_hat, nsteps, source=source, extra={"phm": phm})
+
+
+CASES3 = {
+    # the 3D workload's recipe at a small size, with divergence errors in E and H
+    "blocks_pec_small": lambda: I.em_phm_blocks_pec(n=(26, 22, 18), seed=1, nsteps=20, chi=1.0, gamma=1.0),
+    "mixed_two_xtiles": lambda: random3((75, 14, 9), (R3, R3, P3, P3, N3, N3), seed=2, mu=True),
+    "periodic_tau_inf": lambda: random3((20, 16, 12), (R3,) * 6, seed=4, tau_hat=np.inf, phm=(1.0, 0.5)),
+    "pec_box_source_batch2": lambda: random3(
+        (16, 15, 14), (P3,) * 6, seed=5, batch=2, mu=True,
+        source={"cells": [7 + 16 * (8 + 15 * 6)], "weights": [1.0], "J0": 3.0, "t0": 0.01, "sigma_t": 0.02}),
+    "mixed_nr_pec_periodic": lambda: random3((13, 27, 11), (N3, P3, R3, R3, P3, N3), seed=7, mu=True, tau_hat=1.0),
+    "minimum_2x2x2": lambda: random3((2, 2, 2), (P3, N3, R3, R3, N3, P3), seed=8, batch=2, mu=True),
+    "thin_2x3x40": lambda: random3((2, 3, 40), (N3, N3, P3, P3, R3, R3), seed=9),
+    "thin_70x2x3": lambda: random3((70, 2, 3), (R3, R3, N3, P3, P3, N3), seed=10, mu=True),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES3))
+def test_phm3d_parity(torch, name, precision):
+    wl = CASES3[name]()
+    s, U = setup3(torch, wl, precision)
+    assert s.nfields == 8
+    s.run(U, wl.nsteps)
+    ref = np.stack([oracle_run(wl, wl.nsteps, s.dt, b=b) for b in range(wl.batch)])
+    err = rel_l2(U.cpu().numpy(), ref)
+    print(f"PHM 3D {name} {precision}: rel L2 = {err:.3e}")
+    assert err <= TOL[precision]
+
+
+def test_phm3d_without_couplings_is_the_maxwell_step(torch):
+    wl = I.em_phm_blocks_pec(n=(30, 20, 16), seed=2, nsteps=10, chi=0.0, gamma=0.0)
+    s, U = setup3(torch, wl, "fp64")
+    s.run(U, wl.nsteps)
+    from paper_2412_16845_amd.gks import Solver
+    t = Solver("cart3d", n=wl.n, bc=wl.bc, precision="fp64", cfl=wl.cfl, tau_over_dt=wl.tau_over_dt)
+    E = to_dev(torch, wl.epsinv, "fp64")
+    t.set_material(E)
+    V = to_dev(torch, wl.U0[:, :6], "fp64")
+    t.run(V, wl.nsteps)
+    assert torch.count_nonzero(U[:, 6:]).item() == 0
+    assert rel_l2(U[:, :6].cpu().numpy(), V.cpu().numpy()) <= 1e-13
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_phm3d_full_size_sampled(torch, precision):
+    """The 384^3 PHM workload (dielectric blocks, PEC z walls, NR x/y sides, divergent Ex and Hy
+    bumps, chi = gamma = 1), 60 steps in the benchmark's launch configuration; the last 3 steps
+    are re-done by the oracle on windows around sampled cells."""
+    wl = I.em_phm_blocks_pec(n=384, seed=0, nsteps=60)
+    s, U = setup3(torch, wl, precision)
+    K = 3
+    s.run(U, wl.nsteps - K)
+    start = U.cpu().numpy()
+    s.run(U, K, t0=(wl.nsteps - K) * s.dt)
+    end = U.cpu().numpy()
+    assert np.isfinite(end).all()
+    n = 384
+    centres = [(0, 0, 0), (n - 1, n - 1, n - 1), (n // 2, n // 2, 0), (int(0.3 * n), int(0.6 * n), n // 2),
+               (int(0.65 * n), int(0.35 * n), int(0.4 * n)), (150, 200, 100)]
+    g, o = window_check_3d(wl, start, end, K, s.dt, (wl.nsteps - K) * s.dt, centres)
+    err = rel_l2(g, o)
+    print(f"PHM 384^3 {precision} sampled windows: rel L2 = {err:.3e} over {g.size} values")
     assert err <= TOL[precision]
