@@ -24,6 +24,7 @@ One JSON line on stdout:
   cart2d_phm     the 4096^2 workload carried by the PHM fields (Ez, Hx, Hy, psi) with a
                  divergence error to clean (gamma = 1): throughput and roofline
   cart3d_phm     the 384^3 workload on the eight PHM fields (chi = gamma = 1)
+  tri2d_phm      the ~4M-triangle workload on the PHM fields (Ez, Hx, Hy, psi), gamma = 1
 
 Helper modes for the profiles: --profile-kernel PREC runs only step kernels (for rocprofv3);
 --profile-tri PREC runs 20 steps of the triangle workload, --profile-3d PREC 10 steps of the 384^3
@@ -430,15 +431,15 @@ def cart3d_phm_leg(torch):
 C4_H, C4_STEPS = 6.8e-4, 2000
 
 
-def tri_bytes_per_cell(prec):
-    """Compulsory bytes per cell-update of the triangle step with its stored geometry (vacuum):
-    gradient kernel: fields, 3 neighbour ids, 3 gradient weight vectors, write 6 gradients;
-    face/update kernel: fields, 6 gradients, 3 neighbour ids, 19 geometry values (3 x normal,
-    |l|/|Omega|, midpoint minus the neighbour's centroid; 2 midpoint offsets), write fields
-    (the neighbours' fields and gradients are gathered from cache)."""
+def tri_bytes_per_cell(prec, nf=3):
+    """Compulsory bytes per cell-update of the triangle step with its stored geometry (vacuum),
+    nf fields: gradient kernel: fields, 3 neighbour ids, 3 gradient weight vectors, write 2 nf
+    gradients; face/update kernel: fields, 2 nf gradients, 3 neighbour ids, 19 geometry values
+    (3 x normal, |l|/|Omega|, midpoint minus the neighbour's centroid; 2 midpoint offsets), write
+    fields (the neighbours' fields and gradients are gathered from cache)."""
     e = 8 if prec == "fp64" else 4
-    grad = 3 * e + 3 * 4 + 6 * e + 6 * e
-    step = 3 * e + 6 * e + 3 * 4 + 19 * e + 3 * e
+    grad = nf * e + 3 * 4 + 6 * e + 2 * nf * e
+    step = nf * e + 2 * nf * e + 3 * 4 + 19 * e + nf * e
     return grad + step
 
 
@@ -471,6 +472,49 @@ def tri_leg(torch):
         alg = tri_bytes_per_cell(prec) * ncell
         out[prec] = {"value": round(ncell * C4_STEPS / t_run, 1), "unit": "cell-updates/s",
                      "ms_per_step": round(t_run * 1e3 / C4_STEPS, 5), "dt": s.dt,
+                     "roofline": {"bound": "hbm", "achieved": round(alg / t_launch / 1e9, 1), "peak": PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(alg / t_launch / 1e9 / PEAK_GBS, 4),
+                                  "algorithmic_bytes_per_launch": alg, "step_seconds_per_launch": t_launch}}
+        del s, U
+        torch.cuda.empty_cache()
+    return out
+
+
+TRI_PHM_STEPS = 500
+
+
+def tri_phm_leg(torch):
+    """The triangle workload on the PHM fields (Ez, Hx, Hy, psi), gamma = 1, with a divergent Hx
+    bump (amplitude 0.5, w = 0.05 at (0.8, 0.2)), 500 steps, FP32 and FP64."""
+    from paper_2412_16845_amd import inputs as I
+    from paper_2412_16845_amd.gks import Solver
+    wl = I.tri_ellipse_workload(h=C4_H, seed=0, nsteps=TRI_PHM_STEPS)
+    ex = wl.extra
+    mesh4 = (ex["verts"], ex["tris"], ex["face_cells"], ex["face_verts"])
+    ncell = mesh4[1].shape[0]
+    cen = ex["verts"][ex["tris"]].mean(axis=1)
+    U0 = np.zeros((1, 4, ncell))
+    U0[:, :3] = wl.U0
+    U0[0, 1] += 0.5 * np.exp(-((cen[:, 0] - 0.8) ** 2 + (cen[:, 1] - 0.2) ** 2) / (2 * 0.05 ** 2))
+    out = {"workload": f"tri_ellipse on the PHM fields (Ez, Hx, Hy, psi): {ncell} triangles, the triangle recipe "
+                       f"plus a divergent Hx bump, chi = 0, gamma = 1, {TRI_PHM_STEPS} steps", "cells": ncell}
+    for prec in ("fp32", "fp64"):
+        dtype = torch.float64 if prec == "fp64" else torch.float32
+        s = Solver("tri2d", tri=mesh4, precision=prec, cfl=wl.cfl, tau_over_dt=wl.tau_over_dt, phm=(0.0, 1.0))
+        U = torch.tensor(U0, dtype=dtype, device="cuda")
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s.stream)
+        s.run(U, TRI_PHM_STEPS)
+        b.record(s.stream)
+        torch.cuda.synchronize()
+        t_run = a.elapsed_time(b) / 1e3
+        if not torch.isfinite(U).all():
+            raise RuntimeError(f"triangle PHM {prec} run produced non-finite values")
+        t_launch, _ = time_kernel(torch, s, U, launches=100)
+        alg = tri_bytes_per_cell(prec, 4) * ncell
+        out[prec] = {"value": round(ncell * TRI_PHM_STEPS / t_run, 1), "unit": "cell-updates/s",
+                     "ms_per_step": round(t_run * 1e3 / TRI_PHM_STEPS, 5),
                      "roofline": {"bound": "hbm", "achieved": round(alg / t_launch / 1e9, 1), "peak": PEAK_GBS,
                                   "unit": "GB/s", "frac": round(alg / t_launch / 1e9 / PEAK_GBS, 4),
                                   "algorithmic_bytes_per_launch": alg, "step_seconds_per_launch": t_launch}}
@@ -628,6 +672,9 @@ def main():
         out["cart2d_phm"] = phm_leg(torch)
         log(f"[bench] PHM 3D: 384^3 (eight fields), {C3_PHM_STEPS} steps, fp32 and fp64")
         out["cart3d_phm"] = cart3d_phm_leg(torch)
+        if not args.no_tri:
+            log(f"[bench] PHM triangles: ~4M cells (Ez, Hx, Hy, psi), {TRI_PHM_STEPS} steps, fp32 and fp64")
+            out["tri2d_phm"] = tri_phm_leg(torch)
     if not args.no_3d:
         log("[bench] 3D: 384^3 six fields, 500 steps, fp32 and fp64")
         out["cart3d"] = cart3d_leg(torch)

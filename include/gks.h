@@ -66,7 +66,7 @@ typedef enum { GKS_LIMITER_NONE = 0, GKS_LIMITER_MINMOD = 1 } gks_limiter;
  *   n[3] cells per axis
  *   (n[2] = 1 in 2D), box [lo, hi], bc[6] = x-, x+, y-, y+, z-, z+ sides (the z entries are
  *   ignored in 2D).  A periodic axis must be periodic on both sides.
- *   Triangles (GKS_TRI2D with GKS_TM2D): nverts vertices vert_xy[2*v], ncells triangles
+ *   Triangles (GKS_TRI2D with GKS_TM2D or GKS_TM2D_PHM): nverts vertices vert_xy[2*v], ncells triangles
  *   cell_verts[3*c], nfaces edges face_cells[2*s] = (owner, neighbour) with neighbour < 0
  *   meaning a boundary edge of type -(1 + gks_bc) (non-reflecting or PEC), and
  *   face_verts[2*s] = the edge's two vertices.  Every cell must be a side of exactly three

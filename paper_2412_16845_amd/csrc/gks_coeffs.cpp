@@ -255,24 +255,26 @@ static void cart_flux_eval(int model, int ax, double c, Phm ph, const double C[5
     for (int q = 0; q < nf; ++q) phi[q] = Fg[model_component(model, q)] / h[ax];
 }
 
-// Face operator on reconstructed states (triangles): inputs [Ul(3) Ur(3) s1l s2l s1r s2r] with
-// physical slopes; output dt * F~ (the caller scales by |l_s|/|Omega_i|).
-static void face_flux_eval(double c, const double C[5], const double *w, double mE, double mH, double *phi)
+// Face operator on reconstructed states (triangles): inputs [Ul Ur s1l s2l s1r s2r] x the
+// model's fields in the face frame (TM: Ez, Hn, Ht; with PHM also psi), physical slopes;
+// output dt * F~ (the caller scales by |l_s|/|Omega_i|).
+static void face_flux_eval(int model, double c, Phm ph, const double C[5], const double *w, double mE, double mH,
+                           double *phi)
 {
-    static const int tm[3] = {2, 3, 4};
+    const int nf = model_fields(model);
     double Ul[NV] = {0}, Ur[NV] = {0}, sl[3][NV] = {{0}}, sr[3][NV] = {{0}};
-    for (int q = 0; q < 3; ++q) {
-        const int f = tm[q];
+    for (int q = 0; q < nf; ++q) {
+        const int f = model_component(model, q);
         Ul[f] = w[q];
-        Ur[f] = w[3 + q];
-        sl[0][f] = w[6 + q];
-        sl[1][f] = w[9 + q];
-        sr[0][f] = w[12 + q];
-        sr[1][f] = w[15 + q];
+        Ur[f] = w[nf + q];
+        sl[0][f] = w[2 * nf + q];
+        sl[1][f] = w[3 * nf + q];
+        sr[0][f] = w[4 * nf + q];
+        sr[1][f] = w[5 * nf + q];
     }
     double out[NV];
-    closed_flux(2, c, Phm{0.0, 0.0}, C, Ul, Ur, sl, sr, mE, mH, out);
-    for (int q = 0; q < 3; ++q) phi[q] = out[tm[q]];
+    closed_flux(2, c, ph, C, Ul, Ur, sl, sr, mE, mH, out);
+    for (int q = 0; q < nf; ++q) phi[q] = out[model_component(model, q)];
 }
 
 // Probe a linear evaluator into dense K0/KE/KH and compress to the pattern tables.
@@ -321,10 +323,14 @@ bool cart_face_operator(int model, int axis, double c, double chi, double gamma,
     return probe(nf, nin, ev, pattern_cart(model, axis), k0, ke, kh, err, errlen);
 }
 
-bool tri_face_operator(double c, const double C[5], double *k0, double *ke, double *kh, char *err, size_t errlen)
+bool tri_face_operator(int model, double c, double chi, double gamma, const double C[5], double *k0, double *ke,
+                       double *kh, char *err, size_t errlen)
 {
-    auto ev = [&](const double *w, double mE, double mH, double *phi) { face_flux_eval(c, C, w, mE, mH, phi); };
-    return probe(3, 18, ev, pattern_tri(), k0, ke, kh, err, errlen);
+    const int nf = model_fields(model);
+    auto ev = [&](const double *w, double mE, double mH, double *phi) {
+        face_flux_eval(model, c, Phm{chi, gamma}, C, w, mE, mH, phi);
+    };
+    return probe(nf, 6 * nf, ev, pattern_tri(model), k0, ke, kh, err, errlen);
 }
 
 }  // namespace gks

@@ -126,7 +126,11 @@ void fill_op(FaceOp<T, N0, NE, NH> &o, const double *k0, const double *ke, const
 template <typename T>
 void pack_ops(const gks_ctx *x, std::vector<char> &buf)
 {
-    if (x->kind == GKS_TRI2D) {
+    if (x->kind == GKS_TRI2D && x->model == GKS_TM2D_PHM) {
+        std::vector<FaceOpTP<T>> ops(1);
+        fill_op(ops[0], x->k0[0], x->ke[0], x->kh[0]);
+        buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
+    } else if (x->kind == GKS_TRI2D) {
         std::vector<FaceOpTM<T>> ops(1);
         fill_op(ops[0], x->k0[0], x->ke[0], x->kh[0]);
         buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
@@ -289,9 +293,10 @@ gks_status step_tri(gks_ctx *x, const void *Uin, void *Uout, double tn)
     a.grad = (T *)x->d_grad;
     a.ncell = (int32_t)x->ncell;
     a.batch = (int32_t)x->batch;
+    a.nfields = x->nfields;
     a.nb = x->d_tri_nb;
     a.geo = (const T *)x->d_tri_geo;
-    a.op = (const FaceOpTM<T> *)x->d_ops;
+    a.op = x->d_ops;
     int e = launch_tri_step<T>(a, x->stream);
     if (e) return hip_fail(x, e, "triangle step launch");
     const int64_t ns = (int64_t)x->src_cells.size();
@@ -313,7 +318,7 @@ gks_status upload_tri(gks_ctx *x, const TriGeometry &g)
     if (hipMalloc((void **)&x->d_tri_nb, 3 * nc * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&x->d_tri_geo, geo.size() * sizeof(T)) != hipSuccess ||
         hipMalloc((void **)&x->d_area, nc * sizeof(double)) != hipSuccess ||
-        hipMalloc(&x->d_grad, (size_t)x->batch * 6 * nc * sizeof(T)) != hipSuccess)
+        hipMalloc(&x->d_grad, (size_t)x->batch * 2 * x->nfields * nc * sizeof(T)) != hipSuccess)
         return fail(x, GKS_ENOMEM, "cannot allocate the triangle mesh arrays");
     int e = hipMemcpy(x->d_tri_nb, g.nb.data(), 3 * nc * sizeof(int32_t), hipMemcpyHostToDevice);
     if (!e) e = hipMemcpy(x->d_tri_geo, geo.data(), geo.size() * sizeof(T), hipMemcpyHostToDevice);
@@ -460,7 +465,8 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
     if (phm) {
         if (!(p->chi >= 0.0 && p->chi <= 1.0) || !(p->gamma >= 0.0 && p->gamma <= 1.0))
             return fail(nullptr, GKS_EINVAL, "chi and gamma must lie in [0, 1] (divergence waves at most as fast as c)");
-        if (m->kind == GKS_TRI2D) return fail(nullptr, GKS_EINVAL, "the PHM fields are built for Cartesian 2D and 3D grids");
+        if (m->kind == GKS_TRI2D && m->model != GKS_TM2D_PHM)
+            return fail(nullptr, GKS_EINVAL, "triangle meshes carry TM2D or TM2D_PHM fields");
         if (p->limiter != GKS_LIMITER_NONE)
             return fail(nullptr, GKS_EINVAL, "the slope limiter is not available with the PHM fields");
     } else if (p->chi != 0.0 || p->gamma != 0.0) {
@@ -529,13 +535,14 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
         if (nu > 0.5 * (1 + 1e-12))
             return bail(fail(x, GKS_EINVAL, "Courant number c dt / h = %g exceeds the stability limit 0.5", nu));
     } else if (m->kind == GKS_TRI2D) {
-        if (m->model != GKS_TM2D) return bail(fail(x, GKS_EINVAL, "triangle meshes carry TM2D fields"));
+        if (m->model != GKS_TM2D && m->model != GKS_TM2D_PHM)
+            return bail(fail(x, GKS_EINVAL, "triangle meshes carry TM2D or TM2D_PHM fields"));
         char err[256];
         if (!build_tri_geometry(m, p->gradient, tri, err, sizeof err)) return bail(fail(x, GKS_EINVAL, "%s", err));
         x->ncell = m->ncells;
         x->n[0] = m->ncells;
-        x->nfields = 3;
-        if ((int64_t)3 * x->ncell * ((m->precision == GKS_FP64) ? 8 : 4) > (int64_t)0xFFFFFFFF)
+        x->nfields = (m->model == GKS_TM2D_PHM) ? 4 : 3;
+        if ((int64_t)x->nfields * x->ncell * ((m->precision == GKS_FP64) ? 8 : 4) > (int64_t)0xFFFFFFFF)
             return bail(fail(x, GKS_EINVAL, "mesh too large: one batch item's fields exceed 4 GiB"));
         // the step is stable for c dt <= 0.5 x (smallest inradius 2|Omega|/perimeter)
         x->dt = (p->dt > 0) ? p->dt : p->cfl * tri.rmin / p->c;
@@ -553,7 +560,7 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
     // face operators: local frames of the x-, y- (and z-) faces
     char err[256];
     if (x->kind == GKS_TRI2D &&
-        !tri_face_operator(x->c, x->C, x->k0[0], x->ke[0], x->kh[0], err, sizeof err))
+        !tri_face_operator(x->model, x->c, x->chi, x->gamma, x->C, x->k0[0], x->ke[0], x->kh[0], err, sizeof err))
         return bail(fail(x, GKS_EINVAL, "%s", err));
     if (x->kind == GKS_CART2D || x->kind == GKS_CART3D) {
         // the kernels feed full central differences U(i+1) - U(i-1) = 2 h dU/dx

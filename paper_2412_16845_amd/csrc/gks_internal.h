@@ -17,7 +17,7 @@ struct Pattern {
     const uint8_t *r0, *c0, *rE, *cE, *rH, *cH;
 };
 const Pattern &pattern_cart(int model, int axis);
-const Pattern &pattern_tri();
+const Pattern &pattern_tri(int model);
 
 constexpr int TM_N0 = 24, TM_NE = 6, TM_NH = 4;
 constexpr int TP_N0 = 42, TP_NE = 8, TP_NH = 16;
@@ -30,8 +30,8 @@ void flux_coefficients(double dt, double tau, double C[5]);
 bool cart_face_operator(int model, int axis, double c, double chi, double gamma, const double C[5],
                         const double h[3], double dfac, double *k0, double *ke, double *kh, char *err,
                         size_t errlen);
-bool tri_face_operator(double c, const double C[5], double *k0, double *ke, double *kh, char *err,
-                       size_t errlen);
+bool tri_face_operator(int model, double c, double chi, double gamma, const double C[5], double *k0, double *ke,
+                       double *kh, char *err, size_t errlen);
 
 // Coefficients of one face orientation, in the storage precision T.
 template <typename T, int N0, int NE, int NH>
@@ -113,11 +113,12 @@ struct TriArgs {
     T *Unew;
     const T *epsinv;      // nullable: vacuum
     const T *muinv;       // nullable: vacuum
-    T *grad;              // scratch [batch][ncell][6]: d/dx (Ez Hx Hy), d/dy (Ez Hx Hy) per cell
+    T *grad;              // scratch [batch][ncell][2 nfields]: d/dx (fields), d/dy (fields) per cell
     int32_t ncell, batch;
+    int32_t nfields;      // 3: (Ez, Hx, Hy); 4: (Ez, Hx, Hy, psi)
     const int32_t *nb;    // device [3][ncell]
     const T *geo;         // device [TRI_GEO_ROWS][ncell]
-    const FaceOpTM<T> *op;   // device: the face operator (face-frame inputs, PatTri)
+    const void *op;       // device: the face operator (face-frame inputs; FaceOpTM<T> or FaceOpTP<T>)
 };
 template <typename T> int launch_tri_step(const TriArgs<T> &a, void *stream);
 

@@ -170,6 +170,10 @@ struct PatTri {
     static constexpr uint32_t HROWS = 0x1u;
 };
 
+// Triangle faces with the PHM potential psi: face-frame inputs [Ul Ur s1l s2l s1r s2r] x (Ez, Hn,
+// Ht, psi) have the sparsity of the Cartesian x-face table (as PatTri has that of PatTMx).
+using PatTriP = PatTPx;
+
 static_assert(PatTMx::N0 == TM_N0 && PatTMx::NE == TM_NE && PatTMx::NH == TM_NH, "TM table size");
 static_assert(PatTMy::N0 == TM_N0 && PatTMy::NE == TM_NE && PatTMy::NH == TM_NH, "TM table size");
 static_assert(PatTri::N0 == TM_N0 && PatTri::NE == TM_NE && PatTri::NH == TM_NH, "TM table size");

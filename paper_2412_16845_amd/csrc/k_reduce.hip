@@ -24,28 +24,47 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
     return s;   // valid on thread 0
 }
 
-template <typename T>
+// Fields [0, NE) are E, [NE, NE + NH) are H, the rest the PHM potentials.  Each thread takes
+// four cells a block-stride apart per iteration, so that four cells' loads are in flight
+// before any is used; the per-thread order of the sum is fixed.
+template <typename T, int NF, int NE, int NH>
 __global__ __launch_bounds__(RBLOCK) void energy_partial_kernel(const T *U, const T *epsinv, const T *muinv,
-                                                                int64_t ncell, int32_t nfields, int32_t nE, int32_t nH,
-                                                                const double *vol, double uvol, double *partial,
-                                                                int32_t nblk)
+                                                                int64_t ncell, const double *vol, double uvol,
+                                                                double *partial, int32_t nblk)
 {
+    constexpr int UN = 4;
     __shared__ double lds[RBLOCK / WAVE];
     const int b = blockIdx.y;
-    const T *Ub = U + (int64_t)b * nfields * ncell;
+    const T *Ub = U + (int64_t)b * NF * ncell;
+    const T *eb = epsinv ? epsinv + (int64_t)b * ncell : nullptr;
+    const T *mb = muinv ? muinv + (int64_t)b * ncell : nullptr;
+    const int64_t stride = (int64_t)nblk * RBLOCK;
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * RBLOCK + threadIdx.x; i < ncell; i += (int64_t)nblk * RBLOCK) {
-        double e2 = 0.0, h2 = 0.0, p2 = 0.0;
-        for (int f = 0; f < nfields; ++f) {
-            const double v = (double)Ub[(int64_t)f * ncell + i];
-            if (f < nE) e2 += v * v;
-            else if (f < nE + nH) h2 += v * v;
-            else p2 += v * v;
+    for (int64_t i0 = (int64_t)blockIdx.x * RBLOCK + threadIdx.x; i0 < ncell; i0 += UN * stride) {
+        T v[UN][NF], e[UN], m[UN];
+#pragma unroll
+        for (int k = 0; k < UN; ++k) {
+            const int64_t i = min(i0 + k * stride, ncell - 1);   // clamped reads; the sum skips them
+#pragma unroll
+            for (int f = 0; f < NF; ++f) v[k][f] = Ub[(int64_t)f * ncell + i];
+            e[k] = eb ? eb[i] : T(1);
+            m[k] = mb ? mb[i] : T(1);
         }
-        const double eps = epsinv ? 1.0 / (double)epsinv[(int64_t)b * ncell + i] : 1.0;
-        const double mu = muinv ? 1.0 / (double)muinv[(int64_t)b * ncell + i] : 1.0;
-        const double w = vol ? vol[i] : uvol;
-        acc += 0.5 * w * (eps * e2 + mu * h2 + p2);
+#pragma unroll
+        for (int k = 0; k < UN; ++k) {
+            const int64_t i = i0 + k * stride;
+            if (i >= ncell) break;
+            double e2 = 0.0, h2 = 0.0, p2 = 0.0;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const double x = (double)v[k][f];
+                if (f < NE) e2 += x * x;
+                else if (f < NE + NH) h2 += x * x;
+                else p2 += x * x;
+            }
+            const double w = vol ? vol[i] : uvol;
+            acc += 0.5 * w * (e2 / (double)e[k] + h2 / (double)m[k] + p2);
+        }
     }
     const double s = block_sum(acc, lds);
     if (threadIdx.x == 0) partial[(int64_t)b * nblk + blockIdx.x] = s;
@@ -67,8 +86,21 @@ int launch_energy(const T *U, const T *epsinv, const T *muinv, int64_t ncell, in
                   void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(energy_partial_kernel<T>, dim3(nblk, batch), dim3(RBLOCK), 0, s, U, epsinv, muinv, ncell,
-                       nfields, nE, nH, vol, uniform_vol, partial, nblk);
+    const dim3 grid(nblk, batch), block(RBLOCK);
+    if (nfields == 3 && nE == 1 && nH == 2)
+        hipLaunchKernelGGL((energy_partial_kernel<T, 3, 1, 2>), grid, block, 0, s, U, epsinv, muinv, ncell, vol,
+                           uniform_vol, partial, nblk);
+    else if (nfields == 4 && nE == 1 && nH == 2)
+        hipLaunchKernelGGL((energy_partial_kernel<T, 4, 1, 2>), grid, block, 0, s, U, epsinv, muinv, ncell, vol,
+                           uniform_vol, partial, nblk);
+    else if (nfields == 6 && nE == 3 && nH == 3)
+        hipLaunchKernelGGL((energy_partial_kernel<T, 6, 3, 3>), grid, block, 0, s, U, epsinv, muinv, ncell, vol,
+                           uniform_vol, partial, nblk);
+    else if (nfields == 8 && nE == 3 && nH == 3)
+        hipLaunchKernelGGL((energy_partial_kernel<T, 8, 3, 3>), grid, block, 0, s, U, epsinv, muinv, ncell, vol,
+                           uniform_vol, partial, nblk);
+    else
+        return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL(final_sum_kernel, dim3(batch), dim3(RBLOCK), 0, s, partial, nblk, out);
     return (int)hipGetLastError();
 }

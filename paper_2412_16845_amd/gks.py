@@ -114,9 +114,9 @@ class Solver:
     float64 ('fp64') or float32 ('fp32').  gradient: 'green_gauss' (the paper's) or 'lsq'
     (least squares; differs only on triangle meshes).  limiter: 'none' or 'minmod' (limited
     slopes for discontinuous data, Cartesian grids; the adjoint refuses a limited solver).
-    phm: None, or (chi, gamma) for the perfectly hyperbolic Maxwell system on a Cartesian grid:
-    the fields become (Ez, Hx, Hy, psi) in 2D and (Ex, Ey, Ez, Hx, Hy, Hz, phi, psi) in 3D, with
-    divergence errors of E and H carried off at chi c and gamma c.
+    phm: None, or (chi, gamma) for the perfectly hyperbolic Maxwell system: the fields become
+    (Ez, Hx, Hy, psi) in 2D (Cartesian or triangles) and (Ex, Ey, Ez, Hx, Hy, Hz, phi, psi) in
+    3D, with divergence errors of E and H carried off at chi c and gamma c.
     """
 
     def __init__(self, kind: str = "cart2d", n: Sequence[int] = (64, 64), lo=None, hi=None,
@@ -171,7 +171,8 @@ class Solver:
             self.nfields = 3
             self.grid = (int(tris.shape[0]),)
             if phm is not None:
-                d.model = GKS_TM2D_PHM   # refused by the library: PHM fields are Cartesian 2D only
+                d.model = GKS_TM2D_PHM
+                self.nfields = 4
         else:
             raise ValueError(f"unknown mesh kind {kind!r}")
         grad = GRADIENT[gradient] if isinstance(gradient, str) else int(gradient)

@@ -137,8 +137,10 @@ def test_triangle_topology_is_checked(gks):
     assert st == -1 and "Cartesian grids only" in msg
     st, msg = _tri_init(gks, verts, tris, fc, fv, limiter=3)
     assert st == -1 and "minmod" in msg
-    st, msg = _tri_init(gks, verts, tris, fc, fv, model=2)
-    assert st == -1 and "Cartesian 2D" in msg
+    st, msg = _tri_init(gks, verts, tris, fc, fv, model=3)
+    assert st == -1 and "TM2D or TM2D_PHM" in msg
+    st, msg = _tri_init(gks, verts, tris, fc, fv, model=2)      # TM with psi: passes the host checks
+    assert st in (0, -3), (st, msg)
     # a valid mesh passes the host checks (and then needs a device)
     st, msg = _tri_init(gks, verts, tris, fc, fv)
     assert st in (0, -3), (st, msg)
