@@ -293,6 +293,32 @@ def tri_mesh(verts: np.ndarray, tris: np.ndarray, face_cells: np.ndarray, face_v
     return Mesh(2, vol, L, R, n3, length, dL, dR, cen)
 
 
+def tet_mesh(verts: np.ndarray, tets: np.ndarray, face_cells: np.ndarray, face_verts: np.ndarray) -> Mesh:
+    """Tetrahedral mesh: geometry computed here from the vertices (cell volumes and centroids,
+    face areas, unit normals and centroids).  face_cells[s] = (owner, neighbour or -(1+bc));
+    the normal points owner -> neighbour."""
+    v = np.asarray(verts, dtype=np.float64)
+    t = np.asarray(tets, dtype=np.int64)
+    a, b, c, d = (v[t[:, k]] for k in range(4))
+    vol = np.abs(np.einsum("ij,ij->i", np.cross(b - a, c - a), d - a)) / 6.0
+    cen = (a + b + c + d) / 4.0
+    fc = np.asarray(face_cells, dtype=np.int64)
+    fv = np.asarray(face_verts, dtype=np.int64)
+    p, q, r = v[fv[:, 0]], v[fv[:, 1]], v[fv[:, 2]]
+    cr = np.cross(q - p, r - p)
+    area = 0.5 * np.linalg.norm(cr, axis=1)
+    nrm = cr / (2.0 * area[:, None])
+    mid = (p + q + r) / 3.0
+    L, R = fc[:, 0], fc[:, 1]
+    flip = np.einsum("ij,ij->i", nrm, mid - cen[L]) < 0
+    nrm[flip] *= -1.0
+    dL = mid - cen[L]
+    dR = np.zeros_like(dL)
+    inner = R >= 0
+    dR[inner] = mid[inner] - cen[R[inner]]
+    return Mesh(3, vol, L, R, nrm, area, dL, dR, cen)
+
+
 # ----------------------------------------------------------------------------- the step
 def step(mesh: Mesh, U: np.ndarray, dt: float, tau: float, c: float = 1.0, epsinv=None,
          muinv=None, J=None, C=None, gradient: int = GRAD_GREEN_GAUSS, limiter: int = LIMITER_NONE,

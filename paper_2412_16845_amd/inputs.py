@@ -350,6 +350,86 @@ def _tri_ellipse_mesh(h, seed=0, centre=(0.5, 0.5), axes=(0.2, 0.1)):
     return verts, tri, face_cells, face_verts
 
 
+def _morton3(q):
+    """Morton (Z-order) key of integer coordinates q (n, 3), 10 bits each."""
+    key = np.zeros(q.shape[0], dtype=np.int64)
+    for bit in range(10):
+        for d in range(3):
+            key |= ((q[:, d] >> bit) & 1).astype(np.int64) << (3 * bit + d)
+    return key
+
+
+def tet_box_mesh(n, seed=0, jitter=0.15, sphere=None, bc=(NONREFLECT,) * 6):
+    """Tetrahedral mesh of the unit cube: n^3 cubes (n = (nx, ny, nz) or one int), each split
+    into the six tetrahedra around its main diagonal (a conforming subdivision), vertices
+    jittered by U[-jitter h, jitter h] (boundary vertices only along their side, edges and
+    corners not at all).  sphere = (centre, radius): tetrahedra with centroid inside are removed
+    and the faces left open become PEC walls.  bc: the box sides x-, x+, y-, y+, z-, z+
+    (non-reflecting or PEC).  Cells in Morton order of their centroids.
+    Returns verts (nv, 3), tets (nc, 4), face_cells (nf, 2) = (owner, neighbour or -(1 + bc)) with
+    the owner the lower cell index, face_verts (nf, 3)."""
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else n
+    rng = np.random.default_rng(seed)
+    gi, gj, gk = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(nz + 1), indexing="ij")
+    vid = lambda i, j, k: (i * (ny + 1) + j) * (nz + 1) + k
+    g = np.stack([gi.ravel(), gj.ravel(), gk.ravel()], axis=1)
+    h = np.array([1.0 / nx, 1.0 / ny, 1.0 / nz])
+    verts = g * h
+    top = np.array([nx, ny, nz])
+    free = (g > 0) & (g < top)                     # a coordinate may move only off its side planes
+    verts = verts + free * rng.uniform(-jitter, jitter, verts.shape) * h
+    ci, cj, ck = (a.ravel() for a in np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij"))
+    tets = []
+    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        p0 = np.stack([ci, cj, ck], axis=1)
+        path = [p0]
+        cur = p0.copy()
+        for d in perm:
+            cur = cur.copy()
+            cur[:, d] += 1
+            path.append(cur)
+        tets.append(np.stack([vid(q[:, 0], q[:, 1], q[:, 2]) for q in path], axis=1))
+    tets = np.concatenate(tets)
+    cen = verts[tets].mean(axis=1)
+    if sphere is not None:
+        (cx, cy, cz), rad = sphere
+        keep = (cen[:, 0] - cx) ** 2 + (cen[:, 1] - cy) ** 2 + (cen[:, 2] - cz) ** 2 >= rad * rad
+        tets, cen = tets[keep], cen[keep]
+    order = np.argsort(_morton3(np.minimum((cen * 1024).astype(np.int64), 1023)), kind="stable")
+    tets, cen = tets[order], cen[order]
+    nc = tets.shape[0]
+    # faces: the four vertex triples of every tetrahedron, matched by their sorted vertex ids
+    tri = np.concatenate([tets[:, [1, 2, 3]], tets[:, [0, 2, 3]], tets[:, [0, 1, 3]], tets[:, [0, 1, 2]]])
+    owner = np.tile(np.arange(nc), 4)
+    st = np.sort(tri, axis=1).astype(np.int64)
+    assert verts.shape[0] < (1 << 21)
+    key = (st[:, 0] << 42) | (st[:, 1] << 21) | st[:, 2]
+    uniq, inv, cnt = np.unique(key, return_inverse=True, return_counts=True)
+    inv = inv.ravel()
+    nf = uniq.shape[0]
+    order_f = np.argsort(inv, kind="stable")
+    first = np.zeros(nf, dtype=np.int64)
+    np.cumsum(cnt[:-1], out=first[1:])
+    cA = owner[order_f[first]]
+    cB = np.where(cnt == 2, owner[order_f[np.minimum(first + 1, len(order_f) - 1)]], -1)
+    fv = tri[order_f[first]]
+    L = np.where(cB >= 0, np.minimum(cA, cB), cA)
+    Rn = np.where(cB >= 0, np.maximum(cA, cB), -1)
+    # boundary faces: a box side if all three vertices lie on it, otherwise the sphere (PEC)
+    bnd = Rn < 0
+    P = verts[fv[bnd]]
+    num = {NONREFLECT: 1, PEC: 2}                   # boundary codes of the face list
+    code = np.full(int(bnd.sum()), -(1 + num[PEC]))
+    for d in range(3):
+        for side, val in ((0, 0.0), (1, 1.0)):
+            on = np.all(np.abs(P[:, :, d] - val) < 1e-12, axis=1)
+            code[on] = -(1 + num[bc[2 * d + side]])
+    Rn[bnd] = code
+    face_cells = np.stack([L, Rn], axis=1)
+    fo = np.lexsort((Rn < 0, L))                   # faces ordered by owner
+    return verts, tets.astype(np.int32), face_cells[fo].astype(np.int32), fv[fo].astype(np.int32)
+
+
 def tri_ellipse_workload(h=6.8e-4, seed=0, nsteps=2000, cfl=0.5, tau_over_dt=0.01, w=0.05, eps_discs=0,
                          batch=1) -> Workload:
     """2D TM on the square with an elliptical PEC hole (non-reflecting outer square): Ez
