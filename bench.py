@@ -25,6 +25,7 @@ One JSON line on stdout:
                  divergence error to clean (gamma = 1): throughput and roofline
   cart3d_phm     the 384^3 workload on the eight PHM fields (chi = gamma = 1)
   tri2d_phm      the ~4M-triangle workload on the PHM fields (Ez, Hx, Hy, psi), gamma = 1
+  tet3d          the tetrahedral workload (1.5M cells around a PEC sphere), FP32 and FP64
 
 Helper modes for the profiles: --profile-kernel PREC runs only step kernels (for rocprofv3);
 --profile-tri PREC runs 20 steps of the triangle workload, --profile-3d PREC 10 steps of the 384^3
@@ -481,6 +482,57 @@ def tri_leg(torch):
 
 
 TRI_PHM_STEPS = 500
+C5_TET_N, TET_STEPS = 64, 300
+
+
+def tet_bytes_per_cell(prec):
+    """Compulsory bytes per cell-update of the tetrahedral step (vacuum; about two faces per
+    cell): gradient kernel: 6 fields, 4 neighbour ids, 12 weights, write 18 gradients; face
+    kernel (per cell: two faces): 2 x (2 cell ids, 12 geometry values, write 6 fluxes) and the
+    cell's fields and gradients once; update kernel: 4 face slots, the fluxes once (two faces x 6),
+    1/|Omega|, 6 fields, write 6 fields.  Gathered neighbours and face fluxes are counted once."""
+    e = 8 if prec == "fp64" else 4
+    grad = 6 * e + 4 * 4 + 12 * e + 18 * e
+    face = 2 * (2 * 4 + 12 * e + 6 * e) + 24 * e
+    upd = 4 * 4 + 12 * e + e + 6 * e + 6 * e
+    return grad + face + upd
+
+
+def tet_leg(torch):
+    """The tetrahedral workload: 64^3 jittered cubes of six tetrahedra around a PEC sphere
+    (radius 0.15), non-reflecting box sides, Ez pulse, 300 steps, FP32 and FP64."""
+    from paper_2412_16845_amd import inputs as I
+    from paper_2412_16845_amd.gks import Solver
+    wl = I.tet_sphere_workload(n=C5_TET_N, seed=0, nsteps=TET_STEPS)
+    ex = wl.extra
+    mesh4 = (ex["verts"], ex["tets"], ex["face_cells"], ex["face_verts"])
+    ncell = mesh4[1].shape[0]
+    out = {"workload": f"tet_sphere: EM3D on {ncell} tetrahedra ({C5_TET_N}^3 jittered cubes of six, PEC sphere of "
+                       f"radius 0.15, non-reflecting sides), Ez pulse, CFL 0.5 on the smallest inradius, tau = 0.01 dt, "
+                       f"{TET_STEPS} steps", "cells": ncell, "faces": int(mesh4[2].shape[0])}
+    for prec in ("fp32", "fp64"):
+        dtype = torch.float64 if prec == "fp64" else torch.float32
+        s = Solver("tet3d", tet=mesh4, precision=prec, cfl=wl.cfl, tau_over_dt=wl.tau_over_dt)
+        U = torch.tensor(wl.U0, dtype=dtype, device="cuda")
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s.stream)
+        s.run(U, TET_STEPS)
+        b.record(s.stream)
+        torch.cuda.synchronize()
+        t_run = a.elapsed_time(b) / 1e3
+        if not torch.isfinite(U).all():
+            raise RuntimeError(f"tetrahedral {prec} run produced non-finite values")
+        t_launch, _ = time_kernel(torch, s, U, launches=50)
+        alg = tet_bytes_per_cell(prec) * ncell
+        out[prec] = {"value": round(ncell * TET_STEPS / t_run, 1), "unit": "cell-updates/s",
+                     "ms_per_step": round(t_run * 1e3 / TET_STEPS, 5),
+                     "roofline": {"bound": "hbm", "achieved": round(alg / t_launch / 1e9, 1), "peak": PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(alg / t_launch / 1e9 / PEAK_GBS, 4),
+                                  "algorithmic_bytes_per_launch": alg, "step_seconds_per_launch": t_launch}}
+        del s, U
+        torch.cuda.empty_cache()
+    return out
 
 
 def tri_phm_leg(torch):
@@ -535,6 +587,7 @@ def main():
     ap.add_argument("--no-oversized", action="store_true")
     ap.add_argument("--no-limited", action="store_true")
     ap.add_argument("--no-phm", action="store_true")
+    ap.add_argument("--no-tet", action="store_true")
     ap.add_argument("--profile-phm", choices=["fp32", "fp64"])
     ap.add_argument("--profile-kernel", choices=["fp32", "fp64"])
     ap.add_argument("--profile-tri", choices=["fp32", "fp64"])
@@ -681,6 +734,9 @@ def main():
     if not args.no_tri:
         log("[bench] triangles: ~4M cells, 2000 steps, fp32 and fp64")
         out["tri2d"] = tri_leg(torch)
+    if not args.no_tet:
+        log(f"[bench] tetrahedra: {C5_TET_N}^3 x 6 cells around a PEC sphere, {TET_STEPS} steps, fp32 and fp64")
+        out["tet3d"] = tet_leg(torch)
     if not args.no_adjoint:
         log("[bench] adjoint: 1024x1024 x 8, 800 steps forward + reverse with checkpoints every 50")
         out["adjoint"] = adjoint_leg(torch)

@@ -46,7 +46,7 @@ typedef enum {
     GKS_ESTATE = -6       /* call not valid in the context's state */
 } gks_status;
 
-typedef enum { GKS_CART2D = 0, GKS_CART3D = 1, GKS_TRI2D = 2 } gks_mesh_kind;
+typedef enum { GKS_CART2D = 0, GKS_CART3D = 1, GKS_TRI2D = 2, GKS_TET3D = 3 } gks_mesh_kind;
 /* The perfectly hyperbolic Maxwell (PHM) system (Sec. 2.1) adds the divergence-cleaning
  * potentials phi phi and psi, coupled through chi and gamma (gks_params), to the fields:
  *   GKS_TM2D_PHM: the TM fields with psi (dpsi/dt + gamma c^2 div H = 0, dH/dt += -gamma
@@ -74,6 +74,12 @@ typedef enum { GKS_LIMITER_NONE = 0, GKS_LIMITER_MINMOD = 1 } gks_limiter;
  *   along a space-filling curve keep the neighbour reads of the kernels in cache.
  *   batch: number of independent problems sharing the mesh (fields and materials carry a
  *   leading batch axis).
+ *   Tetrahedra (GKS_TET3D with GKS_EM3D; the unstructured 3D meshes of Sec. 5.5): vert_xy holds
+ *   3 coordinates per vertex, cell_verts 4 vertices per cell, face_verts 3 vertices per face,
+ *   face_cells as for triangles.  Each face's flux is evaluated once, from its owner
+ *   face_cells[2s] (the D3Q4 lattice is chiral: the other side would give a different flux);
+ *   meshes from a generator that makes the owner the lower cell index match the oracle's
+ *   convention.  Green-Gauss gradients only (least squares grows on such meshes: GKS_EINVAL).
  */
 typedef struct {
     int32_t kind, model, precision;

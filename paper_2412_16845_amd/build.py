@@ -18,7 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libgks.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["gks_host.cpp", "gks_coeffs.cpp", "gks_pattern.cpp", "gks_trimesh.cpp", "k_cart2d.hip", "k_cart3d.hip", "k_adjoint2d.hip", "k_tri.hip", "k_reduce.hip"]
+SOURCES = ["gks_host.cpp", "gks_coeffs.cpp", "gks_pattern.cpp", "gks_trimesh.cpp", "gks_tetmesh.cpp", "k_cart2d.hip", "k_cart3d.hip",
+           "k_adjoint2d.hip", "k_tri.hip", "k_tet.hip", "k_reduce.hip"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{os.path.join(ROOT, 'include')}"]

@@ -277,6 +277,25 @@ static void face_flux_eval(int model, double c, Phm ph, const double C[5], const
     for (int q = 0; q < nf; ++q) phi[q] = out[model_component(model, q)];
 }
 
+// Face operator on reconstructed states in 3D (tetrahedra): inputs [Ul Ur s1l s2l s3l s1r s2r s3r]
+// x (Ex, Ey, Ez, Hx, Hy, Hz) in the face frame, physical slopes along the face axes; output
+// dt * F~ in the face frame.
+static void tet_flux_eval(double c, const double C[5], const double *w, double mE, double mH, double *phi)
+{
+    double Ul[NV] = {0}, Ur[NV] = {0}, sl[3][NV] = {{0}}, sr[3][NV] = {{0}};
+    for (int q = 0; q < 6; ++q) {
+        Ul[q] = w[q];
+        Ur[q] = w[6 + q];
+        for (int j = 0; j < 3; ++j) {
+            sl[j][q] = w[12 + 6 * j + q];
+            sr[j][q] = w[30 + 6 * j + q];
+        }
+    }
+    double out[NV];
+    closed_flux(3, c, Phm{0.0, 0.0}, C, Ul, Ur, sl, sr, mE, mH, out);
+    for (int q = 0; q < 6; ++q) phi[q] = out[q];
+}
+
 // Probe a linear evaluator into dense K0/KE/KH and compress to the pattern tables.
 template <typename Eval>
 static bool probe(int nout, int nin, Eval ev, const Pattern &pat, double *k0, double *ke, double *kh,
@@ -331,6 +350,12 @@ bool tri_face_operator(int model, double c, double chi, double gamma, const doub
         face_flux_eval(model, c, Phm{chi, gamma}, C, w, mE, mH, phi);
     };
     return probe(nf, 6 * nf, ev, pattern_tri(model), k0, ke, kh, err, errlen);
+}
+
+bool tet_face_operator(double c, const double C[5], double *k0, double *ke, double *kh, char *err, size_t errlen)
+{
+    auto ev = [&](const double *w, double mE, double mH, double *phi) { tet_flux_eval(c, C, w, mE, mH, phi); };
+    return probe(6, 48, ev, pattern_tet(), k0, ke, kh, err, errlen);
 }
 
 }  // namespace gks

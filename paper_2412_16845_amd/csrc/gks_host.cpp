@@ -68,7 +68,12 @@ struct gks_ctx {
     // triangle meshes: per cell-face neighbours and geometry, cell areas, gradient scratch
     int32_t *d_tri_nb = nullptr;
     void *d_tri_geo = nullptr;
-    double *d_area = nullptr;
+    double *d_area = nullptr;       // cell areas (triangles) or volumes (tetrahedra), for the energy
+    // tetrahedral meshes: per cell neighbours, face slots and geometry; per face cells and
+    // geometry; the face-flux scratch
+    int32_t *d_tet_nb = nullptr, *d_tet_cf = nullptr, *d_tet_fc = nullptr;
+    void *d_tet_cgeo = nullptr, *d_tet_fgeo = nullptr, *d_flux = nullptr;
+    int64_t nface = 0;
     void *d_grad = nullptr;
 
     std::string err;
@@ -126,7 +131,11 @@ void fill_op(FaceOp<T, N0, NE, NH> &o, const double *k0, const double *ke, const
 template <typename T>
 void pack_ops(const gks_ctx *x, std::vector<char> &buf)
 {
-    if (x->kind == GKS_TRI2D && x->model == GKS_TM2D_PHM) {
+    if (x->kind == GKS_TET3D) {
+        std::vector<FaceOpEM<T>> ops(1);
+        fill_op(ops[0], x->k0[0], x->ke[0], x->kh[0]);
+        buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
+    } else if (x->kind == GKS_TRI2D && x->model == GKS_TM2D_PHM) {
         std::vector<FaceOpTP<T>> ops(1);
         fill_op(ops[0], x->k0[0], x->ke[0], x->kh[0]);
         buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
@@ -327,8 +336,68 @@ gks_status upload_tri(gks_ctx *x, const TriGeometry &g)
     return GKS_OK;
 }
 
+template <typename T>
+gks_status step_tet(gks_ctx *x, const void *Uin, void *Uout, double tn)
+{
+    TetArgs<T> a;
+    std::memset(&a, 0, sizeof a);
+    a.U = (const T *)Uin;
+    a.Unew = (T *)Uout;
+    a.epsinv = (const T *)x->epsinv;
+    a.muinv = (const T *)x->muinv;
+    a.grad = (T *)x->d_grad;
+    a.flux = (T *)x->d_flux;
+    a.ncell = (int32_t)x->ncell;
+    a.nface = (int32_t)x->nface;
+    a.batch = (int32_t)x->batch;
+    a.nb = x->d_tet_nb;
+    a.cf = x->d_tet_cf;
+    a.fc = x->d_tet_fc;
+    a.cgeo = (const T *)x->d_tet_cgeo;
+    a.fgeo = (const T *)x->d_tet_fgeo;
+    a.op = x->d_ops;
+    int e = launch_tet_step<T>(a, x->stream);
+    if (e) return hip_fail(x, e, "tetrahedral step launch");
+    const int64_t ns = (int64_t)x->src_cells.size();
+    if (ns > 0) {   // J_z drives Ez (field 2)
+        const double amp = -x->dt * source_pulse(x, tn);
+        e = launch_source_scatter<T>((T *)Uout, (const T *)x->epsinv, x->ncell, (int64_t)x->nfields * x->ncell,
+                                     (int32_t)x->batch, 2, x->d_src_cells, x->d_src_w, amp, (int32_t)ns, x->stream);
+        if (e) return hip_fail(x, e, "source launch");
+    }
+    return GKS_OK;
+}
+
+template <typename T>
+gks_status upload_tet(gks_ctx *x, const TetGeometry &g)
+{
+    const size_t nc = (size_t)g.ncell, nf = (size_t)g.nface;
+    std::vector<T> cg(g.cgeo.size()), fg(g.fgeo.size());
+    for (size_t q = 0; q < cg.size(); ++q) cg[q] = (T)g.cgeo[q];
+    for (size_t q = 0; q < fg.size(); ++q) fg[q] = (T)g.fgeo[q];
+    if (hipMalloc((void **)&x->d_tet_nb, 4 * nc * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void **)&x->d_tet_cf, 4 * nc * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc((void **)&x->d_tet_fc, 2 * nf * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&x->d_tet_cgeo, cg.size() * sizeof(T)) != hipSuccess ||
+        hipMalloc(&x->d_tet_fgeo, fg.size() * sizeof(T)) != hipSuccess ||
+        hipMalloc((void **)&x->d_area, nc * sizeof(double)) != hipSuccess ||
+        hipMalloc(&x->d_grad, (size_t)x->batch * 18 * nc * sizeof(T)) != hipSuccess ||
+        hipMalloc(&x->d_flux, (size_t)x->batch * 6 * nf * sizeof(T)) != hipSuccess)
+        return fail(x, GKS_ENOMEM, "cannot allocate the tetrahedral mesh arrays");
+    int e = hipMemcpy(x->d_tet_nb, g.nb.data(), 4 * nc * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (!e) e = hipMemcpy(x->d_tet_cf, g.cf.data(), 4 * nc * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (!e) e = hipMemcpy(x->d_tet_fc, g.fc.data(), 2 * nf * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (!e) e = hipMemcpy(x->d_tet_cgeo, cg.data(), cg.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (!e) e = hipMemcpy(x->d_tet_fgeo, fg.data(), fg.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (!e) e = hipMemcpy(x->d_area, g.vol.data(), nc * sizeof(double), hipMemcpyHostToDevice);
+    if (e) return hip_fail(x, e, "tetrahedral mesh upload");
+    return GKS_OK;
+}
+
 gks_status do_step(gks_ctx *x, const void *Uin, void *Uout, double tn)
 {
+    if (x->kind == GKS_TET3D)
+        return x->prec == GKS_FP64 ? step_tet<double>(x, Uin, Uout, tn) : step_tet<float>(x, Uin, Uout, tn);
     if (x->kind == GKS_TRI2D)
         return x->prec == GKS_FP64 ? step_tri<double>(x, Uin, Uout, tn) : step_tri<float>(x, Uin, Uout, tn);
     if (x->kind == GKS_CART2D)
@@ -406,7 +475,7 @@ gks_status ensure_out(gks_ctx *x, size_t count)
 gks_status launch_energy_into(gks_ctx *x, const void *U, double *dst)
 {
     const double vol = x->h[0] * x->h[1] * (x->kind == GKS_CART3D ? x->h[2] : 1.0);
-    const double *cell_vol = (x->kind == GKS_TRI2D) ? x->d_area : nullptr;
+    const double *cell_vol = (x->kind == GKS_TRI2D || x->kind == GKS_TET3D) ? x->d_area : nullptr;
     // E components first, then H, then the potentials (weight 1)
     const bool em = x->model == GKS_EM3D || x->model == GKS_EM3D_PHM;
     const int nE = em ? 3 : 1, nH = em ? 3 : 2;
@@ -426,7 +495,7 @@ gks_status launch_energy_into(gks_ctx *x, const void *U, double *dst)
 gks_status validate_box(gks_ctx *x, const int64_t *box)
 {
     if (!box) return fail(x, GKS_EINVAL, "box is NULL");
-    if (x->kind == GKS_TRI2D) return fail(x, GKS_ESTATE, "probe boxes need a Cartesian mesh");
+    if (x->kind == GKS_TRI2D || x->kind == GKS_TET3D) return fail(x, GKS_ESTATE, "probe boxes need a Cartesian mesh");
     for (int d = 0; d < 3; ++d) {
         const int64_t a = box[2 * d], b = box[2 * d + 1];
         if (a < 0 || b > x->n[d] || a >= b) return fail(x, GKS_EINVAL, "box axis %d [%lld, %lld) outside [0, %lld)", d,
@@ -459,14 +528,17 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
         return fail(nullptr, GKS_EINVAL, "gradient %d is neither Green-Gauss (0) nor least squares (1)", p->gradient);
     if (p->limiter != GKS_LIMITER_NONE && p->limiter != GKS_LIMITER_MINMOD)
         return fail(nullptr, GKS_EINVAL, "limiter %d is neither none (0) nor minmod (1)", p->limiter);
-    if (p->limiter != GKS_LIMITER_NONE && m->kind == GKS_TRI2D)
+    if (p->limiter != GKS_LIMITER_NONE && (m->kind == GKS_TRI2D || m->kind == GKS_TET3D))
         return fail(nullptr, GKS_EINVAL, "the slope limiter is defined on Cartesian grids only");
+    if (m->kind == GKS_TET3D && p->gradient != GKS_GRAD_GREEN_GAUSS)
+        return fail(nullptr, GKS_EINVAL, "tetrahedral meshes take Green-Gauss gradients (least squares grows there)");
     const bool phm = m->model == GKS_TM2D_PHM || m->model == GKS_EM3D_PHM;
     if (phm) {
         if (!(p->chi >= 0.0 && p->chi <= 1.0) || !(p->gamma >= 0.0 && p->gamma <= 1.0))
             return fail(nullptr, GKS_EINVAL, "chi and gamma must lie in [0, 1] (divergence waves at most as fast as c)");
         if (m->kind == GKS_TRI2D && m->model != GKS_TM2D_PHM)
             return fail(nullptr, GKS_EINVAL, "triangle meshes carry TM2D or TM2D_PHM fields");
+        if (m->kind == GKS_TET3D) return fail(nullptr, GKS_EINVAL, "tetrahedral meshes carry EM3D fields");
         if (p->limiter != GKS_LIMITER_NONE)
             return fail(nullptr, GKS_EINVAL, "the slope limiter is not available with the PHM fields");
     } else if (p->chi != 0.0 || p->gamma != 0.0) {
@@ -474,6 +546,7 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
     }
 
     TriGeometry tri;
+    TetGeometry tet;
     gks_ctx *x = new (std::nothrow) gks_ctx();
     if (!x) return fail(nullptr, GKS_ENOMEM, "cannot allocate the context");
     x->kind = m->kind;
@@ -550,6 +623,22 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
         const double nu = p->c * x->dt / tri.rmin;
         if (nu > 0.5 * (1 + 1e-12))
             return bail(fail(x, GKS_EINVAL, "c dt / (smallest inradius) = %g exceeds 0.5", nu));
+    } else if (m->kind == GKS_TET3D) {
+        if (m->model != GKS_EM3D) return bail(fail(x, GKS_EINVAL, "tetrahedral meshes carry EM3D fields"));
+        char err[256];
+        if (!build_tet_geometry(m, tet, err, sizeof err)) return bail(fail(x, GKS_EINVAL, "%s", err));
+        x->ncell = m->ncells;
+        x->nface = m->nfaces;
+        x->n[0] = m->ncells;
+        x->nfields = 6;
+        if ((int64_t)6 * std::max(x->ncell, x->nface) * ((m->precision == GKS_FP64) ? 8 : 4) > (int64_t)0xFFFFFFFF)
+            return bail(fail(x, GKS_EINVAL, "mesh too large: one batch item's fields or face fluxes exceed 4 GiB"));
+        // as on triangles: c dt <= 0.5 x (smallest inradius 3|Omega|/surface)
+        x->dt = (p->dt > 0) ? p->dt : p->cfl * tet.rmin / p->c;
+        if (!(x->dt > 0) || !std::isfinite(x->dt)) return bail(fail(x, GKS_EINVAL, "dt must be positive (set dt or cfl)"));
+        const double nu = p->c * x->dt / tet.rmin;
+        if (nu > 0.5 * (1 + 1e-12))
+            return bail(fail(x, GKS_EINVAL, "c dt / (smallest inradius) = %g exceeds 0.5", nu));
     } else {
         return bail(fail(x, GKS_EINVAL, "bad mesh kind %d", m->kind));
     }
@@ -561,6 +650,8 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
     char err[256];
     if (x->kind == GKS_TRI2D &&
         !tri_face_operator(x->model, x->c, x->chi, x->gamma, x->C, x->k0[0], x->ke[0], x->kh[0], err, sizeof err))
+        return bail(fail(x, GKS_EINVAL, "%s", err));
+    if (x->kind == GKS_TET3D && !tet_face_operator(x->c, x->C, x->k0[0], x->ke[0], x->kh[0], err, sizeof err))
         return bail(fail(x, GKS_EINVAL, "%s", err));
     if (x->kind == GKS_CART2D || x->kind == GKS_CART3D) {
         // the kernels feed full central differences U(i+1) - U(i-1) = 2 h dU/dx
@@ -584,6 +675,10 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
                                        x->nfields);
     if (x->kind == GKS_TRI2D) {
         gks_status st = (x->prec == GKS_FP64) ? upload_tri<double>(x, tri) : upload_tri<float>(x, tri);
+        if (st) return bail(st);
+    }
+    if (x->kind == GKS_TET3D) {
+        gks_status st = (x->prec == GKS_FP64) ? upload_tet<double>(x, tet) : upload_tet<float>(x, tet);
         if (st) return bail(st);
     }
     {
@@ -611,6 +706,12 @@ extern "C" gks_status gks_destroy(gks_ctx *ctx)
     if (ctx->d_tri_nb) hipFree(ctx->d_tri_nb);
     if (ctx->d_tri_geo) hipFree(ctx->d_tri_geo);
     if (ctx->d_area) hipFree(ctx->d_area);
+    if (ctx->d_tet_nb) hipFree(ctx->d_tet_nb);
+    if (ctx->d_tet_cf) hipFree(ctx->d_tet_cf);
+    if (ctx->d_tet_fc) hipFree(ctx->d_tet_fc);
+    if (ctx->d_tet_cgeo) hipFree(ctx->d_tet_cgeo);
+    if (ctx->d_tet_fgeo) hipFree(ctx->d_tet_fgeo);
+    if (ctx->d_flux) hipFree(ctx->d_flux);
     if (ctx->d_grad) hipFree(ctx->d_grad);
     delete ctx;
     return GKS_OK;

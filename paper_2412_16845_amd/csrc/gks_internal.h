@@ -32,6 +32,10 @@ bool cart_face_operator(int model, int axis, double c, double chi, double gamma,
                         size_t errlen);
 bool tri_face_operator(int model, double c, double chi, double gamma, const double C[5], double *k0, double *ke,
                        double *kh, char *err, size_t errlen);
+// Face operator of a tetrahedral face: face-frame inputs [Ul Ur s1l s2l s3l s1r s2r s3r] x (Ex .. Hz),
+// physical slopes along the face axes (PatTet); output dt * F~.
+bool tet_face_operator(double c, const double C[5], double *k0, double *ke, double *kh, char *err, size_t errlen);
+const Pattern &pattern_tet();
 
 // Coefficients of one face orientation, in the storage precision T.
 template <typename T, int N0, int NE, int NH>
@@ -106,6 +110,48 @@ struct TriGeometry {
     double rmin = 0;             // smallest inradius 2|Omega| / perimeter
 };
 bool build_tri_geometry(const gks_mesh_desc *m, int gradient, TriGeometry &g, char *err, size_t errlen);
+
+// Tetrahedral meshes (kind GKS_TET3D, six fields).  Per cell, [row][ncell]:
+//   TC_W + 3k + d   Green-Gauss weight of face slot k, component d: n_k |l_k| / (2 |Omega|)
+//   TC_N + 3k + d   outward unit normal of slot k
+//   TC_IVOL         1 / |Omega|
+// and int32 [4][ncell]: nb (neighbour or -(1 + bc)), cf (face id + 1, negative on the
+// neighbour's side).  Per face, [row][nface]:
+//   TF_N + d        unit normal owner -> neighbour
+//   TF_A, TF_B      n3^2 / (1 + n1), n2 n3 / (1 + n1) (0, 0 when n1 = -1): T' follows from n, a, b
+//   TF_AREA         |l|
+//   TF_DL + d       x_s - x_L;  TF_DR + d  x_s - x_R (0 on boundary faces)
+// and int32 [2][nface]: owner, neighbour or -(1 + bc).
+constexpr int TC_W = 0, TC_N = 12, TC_IVOL = 24, TET_CGEO_ROWS = 25;
+constexpr int TF_N = 0, TF_A = 3, TF_B = 4, TF_AREA = 5, TF_DL = 6, TF_DR = 9, TET_FGEO_ROWS = 12;
+struct TetGeometry {
+    int64_t ncell = 0, nface = 0;
+    std::vector<int32_t> nb, cf;   // [4][ncell]
+    std::vector<int32_t> fc;       // [2][nface] interleaved: owner, neighbour per face
+    std::vector<double> cgeo;      // [TET_CGEO_ROWS][ncell]
+    std::vector<double> fgeo;      // [TET_FGEO_ROWS][nface]
+    std::vector<double> vol;       // [ncell]
+    double rmin = 0;               // smallest inradius 3|Omega| / surface
+};
+bool build_tet_geometry(const gks_mesh_desc *m, TetGeometry &g, char *err, size_t errlen);
+
+template <typename T>
+struct TetArgs {
+    const T *U;
+    T *Unew;
+    const T *epsinv;      // nullable: vacuum
+    const T *muinv;       // nullable: vacuum
+    T *grad;              // scratch [batch][ncell][18]: d/dx, d/dy, d/dz of the six fields per cell
+    T *flux;              // scratch [batch][nface][6]: |l| F of each face (global frame, owner -> neighbour)
+    int32_t ncell, nface, batch;
+    const int32_t *nb;    // device [4][ncell]
+    const int32_t *cf;    // device [4][ncell]
+    const int32_t *fc;    // device [nface][2]
+    const T *cgeo;        // device [TET_CGEO_ROWS][ncell]
+    const T *fgeo;        // device [TET_FGEO_ROWS][nface]
+    const void *op;       // device: FaceOpEM<T> (face-frame inputs, PatTet)
+};
+template <typename T> int launch_tet_step(const TetArgs<T> &a, void *stream);
 
 template <typename T>
 struct TriArgs {

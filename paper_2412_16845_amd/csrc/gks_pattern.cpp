@@ -18,6 +18,8 @@ const Pattern &pattern_cart(int model, int axis)
     return axis == 0 ? make<PatEMx>() : (axis == 1 ? make<PatEMy>() : make<PatEMz>());
 }
 
+const Pattern &pattern_tet() { return make<PatTet>(); }
+
 const Pattern &pattern_tri(int model) { return model == GKS_TM2D_PHM ? make<PatTriP>() : make<PatTri>(); }
 
 }  // namespace gks

@@ -170,6 +170,10 @@ struct PatTri {
     static constexpr uint32_t HROWS = 0x1u;
 };
 
+// Tetrahedral faces: face-frame inputs [Ul Ur s1l s2l s3l s1r s2r s3r] x (Ex .. Hz) have the
+// sparsity of the Cartesian x-face table.
+using PatTet = PatEMx;
+
 // Triangle faces with the PHM potential psi: face-frame inputs [Ul Ur s1l s2l s1r s2r] x (Ez, Hn,
 // Ht, psi) have the sparsity of the Cartesian x-face table (as PatTri has that of PatTMx).
 using PatTriP = PatTPx;

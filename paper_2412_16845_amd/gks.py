@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "libgks.so")
 
-GKS_CART2D, GKS_CART3D, GKS_TRI2D = 0, 1, 2
+GKS_CART2D, GKS_CART3D, GKS_TRI2D, GKS_TET3D = 0, 1, 2, 3
 GKS_TM2D, GKS_EM3D, GKS_TM2D_PHM, GKS_EM3D_PHM = 0, 1, 2, 3
 BC = {"periodic": 0, "nonreflecting": 1, "pec": 2}
 PRECISION = {"fp64": 0, "fp32": 1}
@@ -109,7 +109,9 @@ class Solver:
 
     kind 'cart2d' (TM fields Ez, Hx, Hy on an nx x ny grid) or 'cart3d' (six fields on
     nx x ny x nz) or 'tri2d' (TM fields on a triangle mesh: pass ``tri=(verts, tris,
-    face_cells, face_verts)``).  Field tensors have shape (batch, nfields, *grid) with
+    face_cells, face_verts)``) or 'tet3d' (six fields on a tetrahedral mesh: pass
+    ``tet=(verts (nv, 3), tets (nc, 4), face_cells (nf, 2), face_verts (nf, 3))``; each face is
+    evaluated from its owner face_cells[s, 0]).  Field tensors have shape (batch, nfields, *grid) with
     grid = (ny, nx) / (nz, ny, nx) / (ncells,), contiguous, on the solver's device, dtype
     float64 ('fp64') or float32 ('fp32').  gradient: 'green_gauss' (the paper's) or 'lsq'
     (least squares; differs only on triangle meshes).  limiter: 'none' or 'minmod' (limited
@@ -122,7 +124,7 @@ class Solver:
     def __init__(self, kind: str = "cart2d", n: Sequence[int] = (64, 64), lo=None, hi=None,
                  bc: Sequence[str] = ("periodic",) * 4, precision: str = "fp64", batch: int = 1,
                  c: float = 1.0, cfl: float = 0.5, dt: float = 0.0, tau_over_dt: float = 0.01,
-                 energy_every: int = 0, unstable_growth: float = 0.0, device=None, tri=None,
+                 energy_every: int = 0, unstable_growth: float = 0.0, device=None, tri=None, tet=None,
                  gradient: str = "green_gauss", limiter: str = "none", phm=None):
         import torch
         L = lib()
@@ -173,6 +175,23 @@ class Solver:
             if phm is not None:
                 d.model = GKS_TM2D_PHM
                 self.nfields = 4
+        elif kind == "tet3d":
+            verts, tets, face_cells, face_verts = tet
+            verts = np.ascontiguousarray(verts, dtype=np.float64)
+            tets = np.ascontiguousarray(tets, dtype=np.int32)
+            face_cells = np.ascontiguousarray(face_cells, dtype=np.int32)
+            face_verts = np.ascontiguousarray(face_verts, dtype=np.int32)
+            if verts.ndim != 2 or verts.shape[1] != 3 or tets.shape[1:] != (4,) or face_verts.shape[1:] != (3,):
+                raise ValueError("tet3d needs verts (nv, 3), tets (nc, 4) and face_verts (nf, 3)")
+            self._keep += [verts, tets, face_cells, face_verts]
+            d.kind, d.model = GKS_TET3D, GKS_EM3D
+            d.nverts, d.ncells, d.nfaces = verts.shape[0], tets.shape[0], face_cells.shape[0]
+            d.vert_xy = verts.ctypes.data
+            d.cell_verts = tets.ctypes.data
+            d.face_cells = face_cells.ctypes.data
+            d.face_verts = face_verts.ctypes.data
+            self.nfields = 6
+            self.grid = (int(tets.shape[0]),)
         else:
             raise ValueError(f"unknown mesh kind {kind!r}")
         grad = GRADIENT[gradient] if isinstance(gradient, str) else int(gradient)

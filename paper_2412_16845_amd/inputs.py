@@ -430,6 +430,49 @@ def tet_box_mesh(n, seed=0, jitter=0.15, sphere=None, bc=(NONREFLECT,) * 6):
     return verts, tets.astype(np.int32), face_cells[fo].astype(np.int32), fv[fo].astype(np.int32)
 
 
+def tet_sphere_mesh(n, seed=0, radius=0.15, cache=True):
+    """tet_box_mesh with a PEC sphere of the given radius at the centre and non-reflecting box
+    sides, cached like tri_ellipse_mesh (large meshes take tens of seconds)."""
+    import hashlib
+    import os
+    import tempfile
+    args = (n, seed, radius)
+    make = lambda: tet_box_mesh(n, seed=seed, sphere=((0.5, 0.5, 0.5), radius))
+    if not cache:
+        return make()
+    with open(__file__, "rb") as f:
+        tag = hashlib.sha256(f.read() + repr(args).encode()).hexdigest()[:20]
+    d = os.environ.get("GKS_MESH_CACHE") or tempfile.gettempdir()
+    path = os.path.join(d, f"gks_tet_{tag}.npz")
+    if os.path.exists(path):
+        with np.load(path, allow_pickle=False) as z:
+            return z["verts"], z["tets"], z["face_cells"], z["face_verts"]
+    out = make()
+    try:
+        tmp = path + f".{os.getpid()}.npz"
+        np.savez(tmp, verts=out[0], tets=out[1], face_cells=out[2], face_verts=out[3])
+        os.replace(tmp, path)
+    except OSError:
+        pass
+    return out
+
+
+def tet_sphere_workload(n=64, seed=0, nsteps=200, cfl=0.5, tau_over_dt=0.01, w=0.05, radius=0.15) -> Workload:
+    """Tetrahedral workload (the unstructured 3D meshes of Sec. 5.5, with a sphere standing in
+    for the paper's aircraft, whose geometry is not available): the unit cube as n^3 jittered
+    cubes of six tetrahedra, a PEC sphere of the given radius at the centre, non-reflecting box
+    sides; Ez = Gaussian (w) in (x, y) centred at (0.3, 0.5), uniform in z (a pulse that runs
+    into the sphere), H = 0.  The time step is cfl x the smallest inradius (set by the caller's
+    solver)."""
+    verts, tets, face_cells, face_verts = tet_sphere_mesh(n, seed, radius)
+    cen = verts[tets].mean(axis=1)
+    U = np.zeros((1, 6, tets.shape[0]))
+    U[0, 2] = np.exp(-((cen[:, 0] - 0.3) ** 2 + (cen[:, 1] - 0.5) ** 2) / (2 * w * w))
+    return Workload("tet_sphere", "tet3d", (tets.shape[0],), (0.0,) * 3, (1.0,) * 3, (NONREFLECT,) * 6, U, None, None,
+                    cfl, tau_over_dt, nsteps,
+                    extra={"verts": verts, "tets": tets, "face_cells": face_cells, "face_verts": face_verts})
+
+
 def tri_ellipse_workload(h=6.8e-4, seed=0, nsteps=2000, cfl=0.5, tau_over_dt=0.01, w=0.05, eps_discs=0,
                          batch=1) -> Workload:
     """2D TM on the square with an elliptical PEC hole (non-reflecting outer square): Ez

@@ -144,3 +144,40 @@ def test_triangle_topology_is_checked(gks):
     # a valid mesh passes the host checks (and then needs a device)
     st, msg = _tri_init(gks, verts, tris, fc, fv)
     assert st in (0, -3), (st, msg)
+
+
+def _tet_init(gks, verts, tets, fc, fv, cfl=0.5, gradient=0, limiter=0, model=1):
+    d = gks.MeshDesc()
+    d.kind, d.model, d.precision, d.batch = 3, model, 0, 1
+    arrs = [np.ascontiguousarray(verts, dtype=np.float64), np.ascontiguousarray(tets, dtype=np.int32),
+            np.ascontiguousarray(fc, dtype=np.int32), np.ascontiguousarray(fv, dtype=np.int32)]
+    d.nverts, d.ncells, d.nfaces = arrs[0].shape[0], arrs[1].shape[0], arrs[2].shape[0]
+    d.vert_xy, d.cell_verts, d.face_cells, d.face_verts = (a.ctypes.data for a in arrs)
+    p = gks.Params(1.0, cfl, 0.0, 0.01, 0, 0.0, gradient, limiter)
+    h = ctypes.c_void_p()
+    st = gks.lib().gks_init_mesh(ctypes.byref(d), ctypes.byref(p), None, ctypes.byref(h))
+    msg = gks.lib().gks_last_error(None).decode()
+    if h.value:
+        gks.lib().gks_destroy(h)
+    return st, msg
+
+
+def test_tetrahedral_topology_is_checked(gks):
+    from paper_2412_16845_amd import inputs as I
+    verts, tets, fc, fv = I.tet_box_mesh(2, seed=1)
+    cases = []
+    bad = fc.copy(); bad[0, 1] = -1; cases.append((verts, tets, bad, fv, "neighbour"))
+    bad = fc.copy(); bad[3, 0] = tets.shape[0]; cases.append((verts, tets, bad, fv, "owner"))
+    cases.append((verts, tets, fc[1:], fv[1:], "faces (a tetrahedron has 4)"))
+    badv = fv.copy(); badv[5] = badv[6]; cases.append((verts, tets, fc, badv, "not a face"))
+    flat = verts.copy(); flat[:, 2] = 0.0; cases.append((flat, tets, fc, fv, "degenerate"))
+    for v, t, f, w, needle in cases:
+        st, msg = _tet_init(gks, v, t, f, w)
+        assert st == -1 and needle in msg, (st, msg, needle)
+    for kw, needle in (({"cfl": 0.6}, "exceeds 0.5"), ({"gradient": 1}, "Green-Gauss"),
+                       ({"limiter": 1}, "Cartesian grids only"), ({"model": 3}, "EM3D fields"),
+                       ({"model": 0}, "EM3D fields")):
+        st, msg = _tet_init(gks, verts, tets, fc, fv, **kw)
+        assert st == -1 and needle in msg, (kw, st, msg)
+    st, msg = _tet_init(gks, verts, tets, fc, fv)      # valid: passes the host checks
+    assert st in (0, -3), (st, msg)
