@@ -30,8 +30,9 @@ One JSON line on stdout:
 Helper modes for the profiles: --profile-kernel PREC runs only step kernels (for rocprofv3);
 --profile-tri PREC runs 20 steps of the triangle workload, --profile-3d PREC 10 steps of the 384^3
 workload, --profile-adjoint 10 adjoint steps of the 1024^2 x 8 workload, --profile-phm PREC 20 steps of
-the 4096^2 PHM workload; --copy-calibration runs a plain device copy of known size (counter scale
-factor).
+the 4096^2 PHM workload, --profile-phm3d PREC 5 steps of the 384^3 PHM workload, --profile-tet PREC 20
+steps of the tetrahedral workload; --copy-calibration runs a plain device copy of known size (counter
+scale factor).
 """
 from __future__ import annotations
 
@@ -589,6 +590,8 @@ def main():
     ap.add_argument("--no-phm", action="store_true")
     ap.add_argument("--no-tet", action="store_true")
     ap.add_argument("--profile-phm", choices=["fp32", "fp64"])
+    ap.add_argument("--profile-phm3d", choices=["fp32", "fp64"])
+    ap.add_argument("--profile-tet", choices=["fp32", "fp64"])
     ap.add_argument("--profile-kernel", choices=["fp32", "fp64"])
     ap.add_argument("--profile-tri", choices=["fp32", "fp64"])
     ap.add_argument("--profile-3d", choices=["fp32", "fp64"])
@@ -657,6 +660,31 @@ def main():
         print(json.dumps({"profiled": "adjoint fp32", "steps": 10}))
         return
 
+    if args.profile_tet:
+        from paper_2412_16845_amd import inputs as I
+        from paper_2412_16845_amd.gks import Solver
+        wt = I.tet_sphere_workload(n=C5_TET_N, seed=0, nsteps=20)
+        ex = wt.extra
+        s = Solver("tet3d", tet=(ex["verts"], ex["tets"], ex["face_cells"], ex["face_verts"]), precision=args.profile_tet,
+                   cfl=wt.cfl, tau_over_dt=wt.tau_over_dt)
+        U = torch.tensor(wt.U0, dtype=torch.float64 if args.profile_tet == "fp64" else torch.float32, device="cuda")
+        s.run(U, 20)
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled": "tet3d " + args.profile_tet, "steps": 20}))
+        return
+    if args.profile_phm3d:
+        from paper_2412_16845_amd import inputs as I
+        from paper_2412_16845_amd.gks import Solver
+        dtype = torch.float64 if args.profile_phm3d == "fp64" else torch.float32
+        w3 = I.em_phm_blocks_pec(n=C3_N, seed=0, nsteps=5)
+        s = Solver("cart3d", n=w3.n, bc=w3.bc, precision=args.profile_phm3d, cfl=w3.cfl, tau_over_dt=w3.tau_over_dt,
+                   phm=w3.extra["phm"])
+        s.set_material(torch.tensor(w3.epsinv, dtype=dtype, device="cuda"))
+        U = torch.tensor(w3.U0, dtype=dtype, device="cuda")
+        s.run(U, 5)
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled": "cart3d phm " + args.profile_phm3d, "steps": 5}))
+        return
     if args.profile_phm:
         s, U, _ = make(torch, phm_workload(20), args.profile_phm)
         B = torch.empty_like(U)
