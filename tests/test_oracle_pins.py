@@ -2,7 +2,8 @@
 
 Each test checks the oracle against something other than itself: Maxwell's curl equations,
 the exact BGK characteristic solution (ODE integration), the eigen-decomposition of the flux
-Jacobian (Sec. 3.3 / Sec. 4.1 equivalence), the textbook Fromm scheme, exact solutions, mirror
+Jacobian (Sec. 3.3 / Sec. 4.1 equivalence), the textbook Fromm scheme, the von Neumann symbol of
+the whole step written independently from the closed-form lattice moments, exact solutions, mirror
 and rotation symmetries, and the error tables printed in the paper (Sec. 5.1, Sec. 5.2).
 """
 import os
@@ -408,6 +409,76 @@ def test_energy_does_not_grow_where_the_step_is_contractive(oracle):
         W1 = oracle.energy(mesh, U)
         assert W1 <= W0 * (1 + 1e-13)
         W0 = W1
+
+
+def _tm_symbol(theta_x, theta_y, nu, C, dt, c=1.0):
+    """Amplification matrix G of one 2D TM step (U = (Ez, Hx, Hy)) for the Fourier mode
+    U_j = U_hat exp(i (theta_x j_x + theta_y j_y)) on a periodic grid of width h = c dt / nu,
+    written independently of the oracle from the closed-form moments of the D2Q4 lattice:
+    half moments V/2 +- F1(V)/(2c), interface state U0 = (Ul + Ur)/2 + (F1(Ul) - F1(Ur))/(2c),
+    second moments Q = c^2 d1 V and Q+- = c^2 d1 V / 2 +- c (F1(d1 V) + F2(d2 V)) / 2,
+    dt F = C1 F1(U0) + C2 Q(grad U0) + C3 F1(Ut) + C4 [c (Ul - Ur)/2 + (F1(Ul) + F1(Ur))/2]
+           - C5 [Q+(grad Ul) + Q-(grad Ur)],  Ut = -F1(d1 U0) - F2(d2 U0);
+    the y face in the local frame (y, -x) (H~ = (Hy, -Hx)), rotated back."""
+    h = c * dt / nu
+    c2 = c * c
+    F1 = lambda V: np.array([-c2 * V[2], 0.0 * V[0], -V[0]])     # local x flux of (Ez, H1, H2)
+    F2 = lambda V: np.array([c2 * V[1], V[0], 0.0 * V[0]])       # local y flux
+    G = np.zeros((3, 3), dtype=complex)
+    for q in range(3):
+        e = np.zeros(3, dtype=complex)
+        e[q] = 1.0
+        total = np.zeros(3, dtype=complex)
+        for axis in (0, 1):
+            th_n, th_t = (theta_x, theta_y) if axis == 0 else (theta_y, theta_x)
+            # local frame: Ez, H along the normal, H along the second local axis
+            if axis == 0:
+                to = lambda V: np.array([V[0], V[1], V[2]])
+                back = lambda V: np.array([V[0], V[1], V[2]])
+                s_t = 1.0
+            else:
+                to = lambda V: np.array([V[0], V[2], -V[1]])
+                back = lambda V: np.array([V[0], -V[2], V[1]])
+                s_t = -1.0                                       # local axis 2 is -x
+            UL = to(e)
+            UR = to(e) * np.exp(1j * th_n)
+            dnL = to(e) * 1j * np.sin(th_n) / h                  # central differences
+            dtL = s_t * to(e) * 1j * np.sin(th_t) / h
+            dnR, dtR = dnL * np.exp(1j * th_n), dtL * np.exp(1j * th_n)
+            Ul, Ur = UL + 0.5 * h * dnL, UR - 0.5 * h * dnR
+            U0 = 0.5 * (Ul + Ur) + (F1(Ul) - F1(Ur)) / (2 * c)
+            d1 = 0.5 * (dnL + dnR) + (F1(dnL) - F1(dnR)) / (2 * c)
+            d2 = 0.5 * (dtL + dtR) + (F1(dtL) - F1(dtR)) / (2 * c)
+            Ut = -F1(d1) - F2(d2)
+            Qp = 0.5 * c2 * dnL + 0.5 * c * (F1(dnL) + F2(dtL))
+            Qm = 0.5 * c2 * dnR - 0.5 * c * (F1(dnR) + F2(dtR))
+            dtF = (C[0] * F1(U0) + C[1] * c2 * d1 + C[2] * F1(Ut)
+                   + C[3] * (0.5 * c * (Ul - Ur) + 0.5 * (F1(Ul) + F1(Ur))) - C[4] * (Qp + Qm))
+            Fp = back(dtF)                                       # face on the + side of the cell
+            total += (Fp - Fp * np.exp(-1j * th_n)) / h
+        G[:, q] = e - total
+    return G
+
+
+@pytest.mark.parametrize("tau_hat", [0.0, 0.05, np.inf])
+def test_von_neumann_symbol_matches_one_step(oracle, tau_hat):
+    """One oracle step on a single Fourier mode equals G(theta) times the mode (2D TM, periodic)."""
+    N, nu = 16, 0.5
+    mesh = oracle.cart2d(N, N)
+    dt = nu / N
+    C = oracle.coefficients(dt, tau_hat * dt)
+    ix, iy = np.arange(N * N) % N, np.arange(N * N) // N
+    for mx, my in ((1, 0), (0, 3), (2, 5), (7, 7), (5, 2)):
+        tx, ty = 2 * np.pi * mx / N, 2 * np.pi * my / N
+        G = _tm_symbol(tx, ty, nu, C, dt)
+        for q in range(3):
+            for part in (np.real, np.imag):     # the step is real: apply it to both parts
+                U = np.zeros((N * N, 6))
+                U[:, 2 + q] = part(np.exp(1j * (tx * ix + ty * iy)))
+                V = oracle.step(mesh, U, dt, tau_hat * dt)
+                for r in range(3):
+                    ref = part(G[r, q] * np.exp(1j * (tx * ix + ty * iy)))
+                    assert np.max(np.abs(V[:, 2 + r] - ref)) < 1e-13, (mx, my, q, r)
 
 
 # ------------------------------------------------------------------ accuracy against exact solutions
