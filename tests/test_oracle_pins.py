@@ -165,6 +165,38 @@ def test_flux_without_slopes_is_upwind_splitting(oracle, dim, tau):
             assert np.allclose(F, ref, atol=1e-14)
 
 
+@pytest.mark.parametrize("tau_hat", [0.0, 0.3, np.inf])
+def test_face_flux_equals_d3q4_closed_forms(oracle, tau_hat):
+    """The oracle's literal sums over the four D3Q4 velocities equal the closed-form moments of
+    the lattice (third moment 4 c^3 |eps_1jm|): with F_j = A_j from Maxwell's curl equations,
+    U0 = (Ul + Ur)/2 + (F1 Ul - F1 Ur)/(2c), Q(s) = c^2 s1 + c [F3 s2 + F2 s3],
+    Q+(s) = c^2 s1/2 + c F1 s1/2 + c [F2 s2 + F3 s2 + F3 s3 + F2 s3]/2,
+    Q-(s) = c^2 s1/2 - c F1 s1/2 - c [F2 s2 - F3 s2 + F3 s3 - F2 s3]/2,
+    U_t = -M^-1 sum_j F_j s0_j, and dt F = C1 F1 U0 + C2 Q(s0) + C3 F1 U_t
+    + C4 [c (Ul - Ur)/2 + (F1 Ul + F1 Ur)/2] - C5 [Q+(sl) + Q-(sr)]."""
+    c, dt = 1.4, 0.03
+    A = [curl_operator(np.eye(3)[j], c) for j in range(3)]
+    C = oracle.coefficients(dt, tau_hat * dt)
+    for _ in range(4):
+        Ul, Ur = RNG.normal(size=6), RNG.normal(size=6)
+        sl, sr = RNG.normal(size=(3, 6)), RNG.normal(size=(3, 6))
+        mE, mH = RNG.uniform(0.3, 1.0, 2)
+        U0 = 0.5 * (Ul + Ur) + (A[0] @ Ul - A[0] @ Ur) / (2 * c)
+        s0 = [0.5 * (sl[j] + sr[j]) + (A[0] @ sl[j] - A[0] @ sr[j]) / (2 * c) for j in range(3)]
+        Q = c * c * s0[0] + c * (A[2] @ s0[1] + A[1] @ s0[2])
+        Qp = 0.5 * c * c * sl[0] + 0.5 * c * (A[0] @ sl[0]) + 0.5 * c * (A[1] @ sl[1] + A[2] @ sl[1] + A[2] @ sl[2]
+                                                                          + A[1] @ sl[2])
+        Qm = 0.5 * c * c * sr[0] - 0.5 * c * (A[0] @ sr[0]) - 0.5 * c * (A[1] @ sr[1] - A[2] @ sr[1] + A[2] @ sr[2]
+                                                                          - A[1] @ sr[2])
+        Ut = -sum(A[j] @ s0[j] for j in range(3))
+        Ut[:3] *= mE
+        Ut[3:] *= mH
+        dtF = (C[0] * (A[0] @ U0) + C[1] * Q + C[2] * (A[0] @ Ut)
+               + C[3] * (0.5 * c * (Ul - Ur) + 0.5 * (A[0] @ Ul + A[0] @ Ur)) - C[4] * (Qp + Qm))
+        F = oracle.face_flux(3, dt, tau_hat * dt, Ul, Ur, sl, sr, mE, mH, c=c)
+        assert np.allclose(F, dtF / dt, rtol=0, atol=1e-13 * max(1.0, np.abs(dtF / dt).max())), (F, dtF / dt)
+
+
 def fromm_step(w, nu):
     """Fromm's method for w_t + a w_x = 0, a > 0, Courant number nu (average of Lax-Wendroff
     and Beam-Warming; periodic)."""
