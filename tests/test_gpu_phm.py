@@ -324,3 +324,26 @@ def test_phm_tri_full_size(torch, precision):
     print(f"PHM {nc} triangles {precision}: last {K} steps rel L2 = {err:.3e}, max |psi| {np.abs(end[0, 3]).max():.3e}")
     assert np.abs(end[0, 3]).max() > 1e-3
     assert err <= TOL[precision]
+
+
+def test_phm_energy_3d_and_triangles(torch):
+    """The FP64 energy with the potentials (1/2 sum |Omega| (eps |E|^2 + mu |H|^2 + phi^2 + psi^2))
+    on the eight 3D fields and on the four triangle fields, against the oracle's definition."""
+    from paper_2412_16845_amd.gks import Solver
+    rng = np.random.default_rng(21)
+    wl = random3((9, 7, 5), (P3,) * 6, seed=22, mu=True)
+    s, U = setup3(torch, wl, "fp64")
+    W = s.energy(U)[0]
+    mesh = O.cart3d(9, 7, 5)
+    ref = O.energy(mesh, wl.U0[0].reshape(8, -1).T, eps=1.0 / wl.epsinv[0].reshape(-1),
+                   mu=1.0 / wl.muinv[0].reshape(-1))
+    assert abs(W - ref) <= 1e-12 * ref
+    mesh4 = I.tri_ellipse_mesh(0.05, seed=3, cache=False)
+    nc = mesh4[1].shape[0]
+    U0 = rng.standard_normal((1, 4, nc))
+    ei = rng.uniform(0.3, 1.0, (1, nc))
+    t = Solver("tri2d", tri=mesh4, precision="fp64", phm=(0.0, 1.0))
+    t.set_material(to_dev(torch, ei, "fp64"))
+    W = t.energy(to_dev(torch, U0, "fp64"))[0]
+    ref = O.energy(O.tri_mesh(*mesh4), O.from_soa(U0[0], "tm2d_phm"), eps=1.0 / ei[0])
+    assert abs(W - ref) <= 1e-12 * ref
