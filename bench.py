@@ -10,7 +10,7 @@ over the whole grid, with the FP64 energy diagnostic every 100 steps, as in a pr
 Inputs are resident in HBM before timing starts.
 
 One JSON line on stdout:
-  value          FP32-mode cell-updates/s (FP32 storage/flux, FP64 accumulation)
+  value          FP32-mode cell-updates/s (FP32 storage, flux and update)
   fp64           the same run in FP64
   roofline       achieved algorithmic HBM bandwidth of the step kernel (HIP events around each
                  launch) against the 8 TB/s peak; traffic = HBM bytes per launch from the
@@ -732,7 +732,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (f64 accumulation)",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "tm_dielectric_nr: 2D TM 4096x4096, non-reflecting sides, 64 dielectric discs "
                                "(eps in [1,4]), Gaussian point source, CFL 0.5, tau = 0.01 dt, energy every 100 steps",

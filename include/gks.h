@@ -18,8 +18,9 @@
  *     psi); EM3D (Ex, Ey, Ez, Hx, Hy, Hz); EM3D_PHM (Ex, Ey, Ez, Hx, Hy, Hz, phi, psi).  Units
  *     have c = eps0 = mu0 = 1 (Sec. 5), so H and B coincide in vacuum.
  *   - The element type is double for GKS_FP64 contexts and float for GKS_FP32 contexts
- *     (in FP32 the flux arithmetic is single precision and the per-cell sum of face fluxes
- *     and its addition to the old value are double precision, rounded once on store).
+ *     (in FP32 the flux arithmetic is single precision and the flux divergence is added to
+ *     the old value with one fused multiply-add, a single rounding; the host computes the
+ *     flux coefficients, and the diagnostics sum, in double precision).
  *   - All GPU work is enqueued on the stream given to gks_init_mesh and runs asynchronously,
  *     except the calls that return host values (gks_energy, gks_probe_energy, gks_run with an
  *     energy buffer), which synchronise that stream.

@@ -12,7 +12,7 @@
 //      rotated back and stored times |l|.  Each face is evaluated once, from its owner: the
 //      D3Q4 lattice is chiral, so the other side's flux would differ;
 //   3. one thread per cell: the four face fluxes with the sign of the cell's side, divided by
-//      |Omega|, added to the old value in double precision.
+//      |Omega|, added to the old value with one fused multiply-add (a single rounding).
 // Boundary faces: non-reflecting (the ghost side carries no distribution) or PEC (face-frame
 // mirror of the state, the normal slope mirrored with the opposite sign).
 #include "gks_device.h"
@@ -214,8 +214,8 @@ __global__ __launch_bounds__(TET_BLOCK) void tet_update_kernel(TetArgs<T> a)
     T *O = a.Unew + (int64_t)b * 6 * nc;
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-        const double m = (f < 3) ? (double)mE : (double)mH;
-        O[f * nc + i] = (T)((double)U[f * nc + i] - m * (double)(div[f] * iv));
+        const T m = (f < 3) ? mE : mH;
+        O[f * nc + i] = fma(-m, div[f] * iv, U[f * nc + i]);   // U - m x rounded once, x = div / |Omega|
     }
 }
 

@@ -14,7 +14,7 @@
 //      both sides, rotated into its frame (printed rotation of Sec. 3.1: local axes n and
 //      (-n_y, n_x)), evaluated as a sparse linear form of the face-frame states and slopes (the
 //      closed-form flux folded into coefficients on the host), rotated back, and the cell's
-//      divergence is added to its old value in double precision.
+//      divergence is added to its old value with one fused multiply-add (a single rounding).
 // A face is evaluated by both of its cells, each from its own side: no face fluxes are stored
 // and no atomics are needed.  Boundary faces: non-reflecting (the ghost side carries no
 // distribution) or PEC (face-frame mirror of the state, the normal slope mirrored with the
@@ -229,8 +229,8 @@ __global__ __launch_bounds__(TRI_BLOCK) void tri_step_kernel(TriArgs<T> a)
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         // 1/eps scales Ez, 1/mu scales H; psi carries no material factor
-        const double m = (f == 0) ? (double)mE : (f < 3) ? (double)mH : 1.0;
-        O[f * nc + i] = (T)((double)u[f] - m * (double)div[f]);
+        const T m = (f == 0) ? mE : (f < 3) ? mH : T(1);
+        O[f * nc + i] = fma(-m, div[f], u[f]);   // the exact u - m div, rounded once
     }
 }
 
