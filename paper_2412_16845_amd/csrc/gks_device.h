@@ -166,15 +166,16 @@ __device__ __forceinline__ void limit_pair(T fp, T fq, T bp, T bq, T &dp, T &dq)
 // (callers pass mE, mH as the SUM of the two cells' 1/eps, 1/mu: the host halves KE, KH)
 // (gks_pattern.h); the loops unroll into straight-line FMAs on the structural non-zeros.
 // K points to the coefficients (a ConstPtr from scalar_ptr).
-template <typename P, typename T, int NF, int NIN, typename Op>
+// K0 is applied in chunks of CH entries: the coefficients of a chunk are loaded only once the
+// previous chunk has started, so at most two chunks' scalar registers are live.  12 suits most
+// kernels; a kernel whose scalar registers spill with 12 passes a smaller chunk (FP64 takes two
+// scalar registers per coefficient).
+template <typename P, int CH = 12, typename T, int NF, int NIN, typename Op>
 __device__ __forceinline__ void apply_op(const T (&w)[NIN], T mE, T mH, Op K, T (&phi)[NF])
 {
     T a[NF], e[NF], h[NF];
 #pragma unroll
     for (int r = 0; r < NF; ++r) a[r] = e[r] = h[r] = T(0);
-    // K0 in chunks of CH entries; the coefficients of a chunk are loaded only once the previous
-    // chunk has started (at most two chunks' scalar registers are live)
-    constexpr int CH = 12;
 #pragma unroll
     for (int q = 0; q < P::N0; ++q) {
         if (q % CH == 1 && q + CH - 1 < P::N0) asm volatile("" : "+s"(K) : "v"(a[P::R0[q - 1]]));

@@ -39,6 +39,11 @@ template <typename T, int NF> constexpr int rows3d()
 }
 constexpr int OUT_X3 = WAVE - 4;
 
+// Coefficient chunk of the face operators (apply_op): 6 for the fp64 six-field kernel, whose
+// scalar registers spill less with it (384^3: 4131 -> 3774 us; 8 and 12 are slower there, and
+// the other instances are fastest with 12).
+template <typename T, int NF> constexpr int CH3() { return (sizeof(T) == 8 && NF == 6) ? 6 : 12; }
+
 // Fields that change sign under a PEC mirror across an x-, y- or z-wall (tangential E, normal H,
 // and phi, which follows div E; psi is even).
 constexpr uint32_t ODD_X = (1u << 1) | (1u << 2) | (1u << 3) | (1u << 6);
@@ -210,7 +215,7 @@ struct March3D {
                     w[6 * NF + f] = G[f];
                     w[7 * NF + f] = G[NF + f];
                 }
-                apply_op<typename Fields3D<NF>::PZ>(w, A.mE + B.mE, A.mH + B.mH, opz, Z);
+                apply_op<typename Fields3D<NF>::PZ, CH3<T, NF>()>(w, A.mE + B.mE, A.mH + B.mH, opz, Z);
             } else {
                 const bool zl = zlu || (BXY && nr_c), zr = zru || (BXY && nr_c);
                 T w[8 * NF];
@@ -225,7 +230,7 @@ struct March3D {
                     w[6 * NF + f] = zr ? T(0) : G[f];
                     w[7 * NF + f] = zr ? T(0) : G[NF + f];
                 }
-                apply_op<typename Fields3D<NF>::PZ>(w, A.mE + B.mE, A.mH + B.mH, opz, Z);
+                apply_op<typename Fields3D<NF>::PZ, CH3<T, NF>()>(w, A.mE + B.mE, A.mH + B.mH, opz, Z);
             }
             if (q - 1 >= z0) {
                 const uint32_t so = (uint32_t)(q - 1) * pbytes;
@@ -274,7 +279,7 @@ struct March3D {
                 w[6 * NF + f] = s.g[f][rowp][lane];
                 w[7 * NF + f] = s.g[2 * NF + f][rowp][lane];
             }
-            apply_op<typename Fields3D<NF>::PY>(w, B.mE + s.g[3 * NF][rowp][lane], B.mH + s.g[3 * NF + 1][rowp][lane],
+            apply_op<typename Fields3D<NF>::PY, CH3<T, NF>()>(w, B.mE + s.g[3 * NF][rowp][lane], B.mH + s.g[3 * NF + 1][rowp][lane],
                                                 opy, py);
 #pragma unroll
             for (int f = 0; f < NF; ++f) s.p[f][row][lane] = py[f];
@@ -294,7 +299,7 @@ struct March3D {
                 w[6 * NF + f] = from_right(G[NF + f]);
                 w[7 * NF + f] = from_right(G[2 * NF + f]);
             }
-            apply_op<typename Fields3D<NF>::PX>(w, B.mE + from_right(B.mE), B.mH + from_right(B.mH), opx, px);
+            apply_op<typename Fields3D<NF>::PX, CH3<T, NF>()>(w, B.mE + from_right(B.mE), B.mH + from_right(B.mH), opx, px);
         }
         if constexpr (NU == 2) {
             // share the fields of plane q+1 in the other buffer (its last readers, in the
