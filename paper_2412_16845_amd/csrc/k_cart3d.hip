@@ -39,10 +39,10 @@ template <typename T, int NF> constexpr int rows3d()
 }
 constexpr int OUT_X3 = WAVE - 4;
 
-// Coefficient chunk of the face operators (apply_op): 6 for the fp64 six-field kernel, whose
-// scalar registers spill less with it (384^3: 4131 -> 3774 us; 8 and 12 are slower there, and
-// the other instances are fastest with 12).
-template <typename T, int NF> constexpr int CH3() { return (sizeof(T) == 8 && NF == 6) ? 6 : 12; }
+// Coefficient chunk of the face operators (apply_op): 5 for the fp64 six-field kernel (384^3:
+// 4131 us with 12; 3, 4, 5, 6 and 8 give 4045, 3714, 3618, 3789 and 4328 us), 12 for the others,
+// which are fastest with it.
+template <typename T, int NF> constexpr int CH3() { return (sizeof(T) == 8 && NF == 6) ? 5 : 12; }
 
 // Fields that change sign under a PEC mirror across an x-, y- or z-wall (tangential E, normal H,
 // and phi, which follows div E; psi is even).
