@@ -198,14 +198,13 @@ __device__ __forceinline__ void apply_op(const T (&w)[NIN], T mE, T mH, Op K, T 
 
 // As apply_op, and also returns the material parts e = KE w and h = KH w (per output row; the
 // rows outside EROWS / HROWS are zero): phi = K0 w + mE e + mH h.
-template <typename P, typename T, int NF, int NIN, typename Op>
+template <typename P, int CH = 12, typename T, int NF, int NIN, typename Op>
 __device__ __forceinline__ void apply_op_parts(const T (&w)[NIN], T mE, T mH, Op K, T (&phi)[NF], T (&e)[NF],
                                                T (&h)[NF])
 {
     T a[NF];
 #pragma unroll
     for (int r = 0; r < NF; ++r) a[r] = e[r] = h[r] = T(0);
-    constexpr int CH = 12;   // coefficient chunks, as in apply_op
 #pragma unroll
     for (int q = 0; q < P::N0; ++q) {
         if (q % CH == 1 && q + CH - 1 < P::N0) asm volatile("" : "+s"(K) : "v"(a[P::R0[q - 1]]));
@@ -226,7 +225,7 @@ __device__ __forceinline__ void apply_op_parts(const T (&w)[NIN], T mE, T mH, Op
 }
 
 // Transpose: wbar += K(mE, mH)^T abar.
-template <typename P, typename T, int NF, int NIN, typename Op>
+template <typename P, int CH = 12, typename T, int NF, int NIN, typename Op>
 __device__ __forceinline__ void apply_op_transpose(const T (&abar)[NF], T mE, T mH, Op K, T (&wbar)[NIN])
 {
     T ae[NF], ah[NF];
@@ -235,7 +234,6 @@ __device__ __forceinline__ void apply_op_transpose(const T (&abar)[NF], T mE, T 
         ae[r] = mE * abar[r];
         ah[r] = mH * abar[r];
     }
-    constexpr int CH = 12;   // coefficient chunks, as in apply_op
 #pragma unroll
     for (int q = 0; q < P::N0; ++q) {
         if (q % CH == 1 && q + CH - 1 < P::N0) asm volatile("" : "+s"(K) : "v"(wbar[P::C0[q - 1]]));

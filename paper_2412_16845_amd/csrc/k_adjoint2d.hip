@@ -28,6 +28,11 @@
 namespace gks {
 
 constexpr int ADJ_BLOCK = 256;
+// Coefficient chunk of the forward and transposed face operators: small chunks keep fewer
+// scalar registers live and halve the scalar spills of the march (1024^2 x 8 adjoint step:
+// 221.5 -> 208.9 us in fp32 and 482.7 -> 433.1 us in fp64 with 4 instead of 12; 3, 5, 6 and 8
+// are slower).
+constexpr int ADJ_CH = 4;
 // One wave per workgroup for the march: its waves finish at different times, and a single-wave
 // workgroup lets a freed slot take the next tile at once (4-wave workgroups wait for four free
 // slots on one compute unit).  Measured on 1024^2 x 8: 231 vs 241 us (fp32), 503 vs 552 us (fp64).
@@ -129,12 +134,12 @@ struct AdjStrip {
                                          T (&wbar)[18], T &sE, T &sH) const
     {
         T e[3], h[3];
-        apply_op_parts<P>(w, mEs, mHs, K, phi, e, h);
+        apply_op_parts<P, ADJ_CH>(w, mEs, mHs, K, phi, e, h);
 #pragma unroll
         for (int q = 0; q < 18; ++q) wbar[q] = T(0);
         // reload the coefficients for the transposed pass rather than keeping them live
         asm volatile("" : "+s"(K) : "v"(phi[2]));
-        apply_op_transpose<P>(ad, mEs, mHs, K, wbar);
+        apply_op_transpose<P, ADJ_CH>(ad, mEs, mHs, K, wbar);
         sE = ad[0] * e[0] + ad[1] * e[1] + ad[2] * e[2];
         sH = ad[0] * h[0] + ad[1] * h[1] + ad[2] * h[2];
     }
