@@ -183,10 +183,11 @@ int gks::cart2d_pick_tile_y(int nx, int ny, int batch, int ncu, int precision)
 #endif
     // Short tiles give many waves per SIMD to hide memory latency; adjacent tiles march in
     // opposite directions and share their halo rows through the L2, so the extra halo reads of
-    // short tiles mostly hit the cache.  16 rows measured best (12..24 within 2%) on 4096^2 in
-    // both precisions.
-    (void)nx; (void)batch; (void)ncu; (void)precision;
-    return std::max(1, std::min(16, ny));
+    // short tiles mostly hit the cache.  Measured on 4096^2 (12..24 rows within 3%): 14 rows in
+    // fp32 (114.0 us, against 115.7 at 16; also the best or within 1% for the PHM and limited
+    // kernels), 16 in fp64 (203.4 us, against 205.5 at 14).
+    (void)nx; (void)batch; (void)ncu;
+    return std::max(1, std::min(precision == GKS_FP32 ? 14 : 16, ny));
 }
 
 int gks::cart3d_pick_tile_z(int nx, int ny, int nz, int batch, int ncu, int precision, int nfields)
