@@ -243,9 +243,10 @@ struct Strip2D {
             apply_op<typename FS::PX, CH2>(v, Rs.mE[k] + mEr, Rs.mH[k] + mHr, opx, fx[k]);
         }
 
-        // update: per-cell flux divergence (FP32 in FP32 mode), then the old value and the
-        // source added in FP64 with a single rounding (a single point-source cell is handled
-        // here; longer source lists by a separate scatter kernel)
+        // update: per-cell flux divergence (FP32 in FP32 mode), then its addition to the old
+        // value with a single rounding; the row of a single point-source cell adds the source
+        // in the same rounding, in FP64 (longer source lists are added by a separate scatter
+        // kernel)
         const int row = q - 2 * sd;
         const uint32_t rowc = (uint32_t)row * (uint32_t)a.nx;
         T nv[NC][NF], div[NC][NF];
