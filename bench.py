@@ -148,11 +148,31 @@ def roofline(precision, t_launch):
             "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch}
 
 
-def cpu_baseline(wl, dt):
-    """The FP64 oracle (OpenMP over all host cores) on a 1024 x 1024 window of the workload
-    (its centre, with the source and inclusions; cut sides non-reflecting) for a few steps."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_threads() -> int:
+    """Threads the oracle's OpenMP runtime uses in this process."""
+    import ctypes
     from oracle import gks_oracle as O
-    O.build()
+    O.lib()
+    try:
+        return int(ctypes.CDLL("libgomp.so.1").omp_get_max_threads())
+    except OSError:
+        return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def oracle_window_rate(wl, dt, max_steps, max_seconds):
+    """Cell-updates/s of the FP64 oracle on a 1024 x 1024 window of the workload (its centre,
+    with the source and inclusions; cut sides non-reflecting): (rate, steps, seconds)."""
+    from oracle import gks_oracle as O
     x0 = y0 = (N - 1024) // 2
     mesh = O.cart_window((N, N, 1), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), [1, 1, 1, 1], (x0, y0, 0),
                          (x0 + 1024, y0 + 1024, 1), 2)
@@ -166,12 +186,55 @@ def cpu_baseline(wl, dt):
         U = O.run(mesh, U, 1, dt, wl.tau_over_dt * dt, epsinv=ei, source=src, t0=steps * dt)
         steps += 1
         el = time.perf_counter() - t0
-        if el > 12.0 or steps >= 40:
+        if el > max_seconds or steps >= max_steps:
             break
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(1024 * 1024 * steps / el, 1), "unit": "cell-updates/s", "cores": cores,
-            "kind": "oracle", "sample": f"1024x1024 centre window of the 4096x4096 workload, {steps} steps, "
-                                        f"{el:.1f} s, FP64 literal per-face lattice sums"}
+    return 1024 * 1024 * steps / el, steps, el
+
+
+def cpu_baseline(wl):
+    """The FP64 oracle (literal per-face lattice sums) on the host: all cores on a window of the
+    benchmark workload, one core on the same window (a child process with one OpenMP thread),
+    and the 64 x 64 periodic Gaussian configuration in full (200 steps) on all cores."""
+    import subprocess
+    from oracle import gks_oracle as O
+    from paper_2412_16845_amd import inputs as I
+    O.build()
+    dt = wl.cfl / N   # c dt = cfl h on the unit square
+    rate, steps, el = oracle_window_rate(wl, dt, 40, 12.0)
+    threads = oracle_threads()
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; "
+            "from paper_2412_16845_amd import inputs as I; "
+            "r = bench.oracle_window_rate(I.tm_dielectric_nr(nx=bench.N, seed=0, nsteps=1000), %r, 4, 8.0); "
+            "print(json.dumps({'rate': r[0], 'steps': r[1], 'seconds': r[2], 'threads': bench.oracle_threads()}))"
+            % (ROOT, dt))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    one = None
+    try:
+        p = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+        if p.returncode == 0:
+            one = json.loads(p.stdout.strip().splitlines()[-1])
+    except (subprocess.TimeoutExpired, ValueError, IndexError):
+        one = None
+    c1 = I.tm_gaussian_periodic(64, seed=0, nsteps=200)
+    mesh = O.cart2d(64, 64, bc=(0, 0, 0, 0))
+    U = O.from_soa(c1.U0[0].reshape(3, -1), "tm2d")
+    dt1 = c1.cfl / 64
+    t0 = time.perf_counter()
+    O.run(mesh, U, c1.nsteps, dt1, c1.tau_over_dt * dt1)
+    t_c1 = time.perf_counter() - t0
+    out = {"value": round(rate, 1), "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"1024x1024 centre window of the 4096x4096 workload, {steps} steps, {el:.1f} s, "
+                     f"FP64 literal per-face lattice sums, {threads} OpenMP threads",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+           "c1_full": {"value": round(64 * 64 * c1.nsteps / t_c1, 1), "unit": "cell-updates/s",
+                       "seconds": round(t_c1, 3), "cores": threads,
+                       "sample": "64x64 periodic Gaussian pulse, 200 steps (the whole configuration), literal oracle"}}
+    if one is not None:
+        out["one_core"] = {"value": round(one["rate"], 1), "unit": "cell-updates/s", "cores": one["threads"],
+                           "sample": f"the same window, {one['steps']} steps, {one['seconds']:.1f} s, "
+                                     f"OMP_NUM_THREADS=1"}
+    return out
 
 
 ADJ_N, ADJ_BATCH, ADJ_STEPS, ADJ_K = 1024, 8, 800, 50
@@ -770,7 +833,7 @@ def main():
         out["adjoint"] = adjoint_leg(torch)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline: oracle on a 1024x1024 window")
-        out["cpu_baseline"] = cpu_baseline(wl, f64["dt"])
+        out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
 
 

@@ -18,9 +18,10 @@
  *     psi); EM3D (Ex, Ey, Ez, Hx, Hy, Hz); EM3D_PHM (Ex, Ey, Ez, Hx, Hy, Hz, phi, psi).  Units
  *     have c = eps0 = mu0 = 1 (Sec. 5), so H and B coincide in vacuum.
  *   - The element type is double for GKS_FP64 contexts and float for GKS_FP32 contexts
- *     (in FP32 the flux arithmetic is single precision and the flux divergence is added to
- *     the old value with one fused multiply-add, a single rounding; the host computes the
- *     flux coefficients, and the diagnostics sum, in double precision).
+ *     (in FP32 the fields are stored and the face fluxes computed in single precision; each
+ *     cell sums its face fluxes and adds them to its old value in double precision, rounding
+ *     once to single precision on store; the host computes the flux coefficients, and the
+ *     diagnostics sum, in double precision).
  *   - All GPU work is enqueued on the stream given to gks_init_mesh and runs asynchronously,
  *     except the calls that return host values (gks_energy, gks_probe_energy, gks_run with an
  *     energy buffer), which synchronise that stream.
@@ -100,9 +101,10 @@ typedef struct {
  *   c:            lattice speed = speed of light (> 0).
  *   cfl, dt:      dt > 0 is used as given; otherwise dt = cfl * h / c with h the smallest
  *                 cell width (Cartesian) or the smallest inradius 2|Omega|/perimeter
- *                 (triangles).  c dt / h above 0.5 is rejected (GKS_EINVAL): 0.5 is the
- *                 scheme's stability limit in 2D.  3D grids are stable only up to 1/3 (the
- *                 D3Q4 scheme grows at 1/2); that is left to the caller.
+ *                 (triangles).  c dt / h above the stability limit is rejected (GKS_EINVAL):
+ *                 0.5 on 2D grids and triangle meshes, 1/3 on 3D Cartesian grids (the D3Q4
+ *                 step grows above it: at 1/2 a Fourier mode gains about 10% per step).
+ *                 Tetrahedral meshes take c dt / (smallest inradius 3|Omega|/surface) <= 0.5.
  *   tau_over_dt:  collision time tau = tau_over_dt * dt (>= 0; +INFINITY = collisionless).
  *   energy_every: gks_run records the energy every this many steps (0 = never).
  *   unstable_growth: gks_run fails with GKS_EUNSTABLE when a recorded energy exceeds this
@@ -187,9 +189,12 @@ gks_status gks_step(gks_ctx *ctx, const void *U_in, void *U_out, double t_n);
  * nsteps steps in place on U (device) starting at t0 (t^n = t0 + n dt), ping-ponging with a
  * library-owned buffer.  energy_host: NULL, or host memory for (nsteps / energy_every) x batch
  * doubles receiving W = 1/2 sum |Omega| (eps |E|^2 + mu |H|^2) after every energy_every-th
- * step; when given, the recorded energies are checked once all steps are done: a NaN/Inf
- * energy returns GKS_ENONFINITE and growth beyond unstable_growth returns GKS_EUNSTABLE (U
- * holds the state after the last step either way).
+ * step.  When given, each record is checked while the next energy_every steps run: a NaN/Inf
+ * energy returns GKS_ENONFINITE and growth beyond unstable_growth times the first record returns
+ * GKS_EUNSTABLE.  The run then stops early: U holds the state after the record that followed
+ * the failing one (at most energy_every steps past it), the records up to that one are written
+ * and the later entries of energy_host are left untouched; the error text names the batch item
+ * and the step of the failing record.
  */
 gks_status gks_run(gks_ctx *ctx, void *U, int64_t nsteps, double t0, double *energy_host);
 
@@ -200,7 +205,10 @@ gks_status gks_run(gks_ctx *ctx, void *U, int64_t nsteps, double t0, double *ene
  *   g_muinv  += (dPhi/d muinv)^T lam_np1            (device, double, [batch][ncells]; nullable)
  * U_n is the state the forward step started from (device, field type).  lam_n must not
  * overlap lam_np1 or U_n.  Cartesian 2D TM contexts without the slope limiter only (GKS_ESTATE
- * otherwise: the limited step is nonlinear, and the PHM model has no adjoint kernel).
+ * otherwise: the limited step is nonlinear, and the PHM model has no adjoint kernel).  The
+ * co-states and material gradients of the ghost positions around the grid go through a scratch
+ * buffer of batch x (4 (nx + ny) + 16) x (16 + 3 x element size) bytes, which the context
+ * allocates on its first adjoint call (GKS_ENOMEM if that fails) and keeps.
  */
 gks_status gks_adjoint_step(gks_ctx *ctx, const void *U_n, const void *lam_np1, void *lam_n,
                             double *g_epsinv, double *g_muinv, double t_n);

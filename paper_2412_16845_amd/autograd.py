@@ -14,8 +14,8 @@ state after ``nsteps`` steps and is differentiable with respect to U0, 1/eps and
 design workload.
 
 Memory: checkpoints hold ceil(nsteps / K) states and the backward pass K more (K =
-checkpoint_every), plus two co-states and the library's adjoint scratch (about 14 values per
-cell and batch item).
+checkpoint_every), plus two co-states and the library's adjoint scratch (the ghost positions
+around the grid only: about 4 (nx + ny) positions per batch item).
 """
 from __future__ import annotations
 

@@ -62,7 +62,8 @@ struct gks_ctx {
     size_t d_out_count = 0;
     double *h_out = nullptr;        // pinned host mirror
     size_t h_out_count = 0;
-    void *adj_scratch = nullptr;    // adjoint: padded face adjoints, ghost co-states, ghost material gradients
+    hipEvent_t rec_ev[2] = {nullptr, nullptr};   // gks_run: energy record r read back (r mod 2)
+    void *adj_scratch = nullptr;    // adjoint: co-states and material gradients of the ghost positions
     size_t adj_scratch_bytes = 0;
 
     // triangle meshes: per cell-face neighbours and geometry, cell areas, gradient scratch
@@ -408,24 +409,21 @@ gks_status do_step(gks_ctx *x, const void *Uin, void *Uout, double tn)
     return fail(x, GKS_ESTATE, "this mesh kind has no step kernel");
 }
 
+// Bytes of adjoint scratch one call needs: padg [batch][2][npos] doubles, then padpsi
+// [batch][3][npos] of the field type, over the npos ghost positions around the grid.
+size_t adjoint_scratch_bytes(const gks_ctx *x)
+{
+    const size_t npos = (size_t)adjoint_ring_positions((int)x->n[0], (int)x->n[1]);
+    return (size_t)x->batch * npos * (2 * sizeof(double) + 3 * elem_size(x));
+}
+
 template <typename T>
 gks_status adjoint_cart2d(gks_ctx *x, const void *Un, const void *lam_np1, void *lam_n, double *g_epsinv,
-                          double *g_muinv, double tn)
+                          double *g_muinv, double tn, void *scratch)
 {
-    const int64_t npos = (x->n[0] + 4) * (x->n[1] + 4);
-    const size_t n9 = (size_t)x->batch * 9 * npos, n3 = (size_t)x->batch * 3 * npos, n2 = (size_t)x->batch * 2 * npos;
-    const size_t bytes = n2 * sizeof(double) + (n9 + n3) * sizeof(T);
-    if (x->adj_scratch_bytes < bytes) {
-        if (x->adj_scratch) hipFree(x->adj_scratch);
-        x->adj_scratch = nullptr;
-        x->adj_scratch_bytes = 0;
-        if (hipMalloc(&x->adj_scratch, bytes) != hipSuccess)
-            return fail(x, GKS_ENOMEM, "cannot allocate the %zu-byte adjoint scratch", bytes);
-        x->adj_scratch_bytes = bytes;
-    }
-    double *padg = (double *)x->adj_scratch;
-    T *pad9 = (T *)(padg + n2);
-    T *padpsi = pad9 + n9;
+    const size_t npos = (size_t)adjoint_ring_positions((int)x->n[0], (int)x->n[1]);
+    double *padg = (double *)scratch;
+    T *padpsi = (T *)(padg + (size_t)x->batch * 2 * npos);
     Cart2DAdjArgs<T> a;
     std::memset(&a, 0, sizeof a);
     a.U = (const T *)Un;
@@ -440,7 +438,7 @@ gks_status adjoint_cart2d(gks_ctx *x, const void *Un, const void *lam_np1, void 
     a.batch = (int32_t)x->batch;
     for (int i = 0; i < 4; ++i) a.bc[i] = x->bc[i];
     a.ops = (const FaceOpTM<T> *)x->d_ops;
-    int e = launch_cart2d_adjoint<T>(a, pad9, padpsi, padg, x->stream);
+    int e = launch_cart2d_adjoint<T>(a, padpsi, padg, x->stream);
     if (e) return hip_fail(x, e, "adjoint launch");
     const int64_t ns = (int64_t)x->src_cells.size();
     if (ns > 0 && g_epsinv) {
@@ -450,6 +448,24 @@ gks_status adjoint_cart2d(gks_ctx *x, const void *Un, const void *lam_np1, void 
         if (e) return hip_fail(x, e, "adjoint source launch");
     }
     return GKS_OK;
+}
+
+// Checks shared by the adjoint entry points (no launch, no allocation).
+gks_status check_adjoint(gks_ctx *ctx, const void *U_n, const void *lam_np1, void *lam_n, double *g_epsinv,
+                         double *g_muinv, double t_n)
+{
+    if (ctx->kind != GKS_CART2D) return fail(ctx, GKS_ESTATE, "the adjoint step exists for Cartesian 2D TM contexts only");
+    if (ctx->limiter)
+        return fail(ctx, GKS_ESTATE, "the adjoint step is that of the linear (unlimited) step; this context limits slopes");
+    if (ctx->model != GKS_TM2D) return fail(ctx, GKS_ESTATE, "the adjoint step is built for the TM fields without PHM");
+    if (!U_n || !lam_np1 || !lam_n) return fail(ctx, GKS_EINVAL, "U_n, lam_np1 or lam_n is NULL");
+    const size_t sb = state_bytes(ctx), gb = (size_t)ctx->batch * ctx->ncell * sizeof(double);
+    if (ranges_overlap(lam_n, lam_np1, sb) || ranges_overlap(lam_n, U_n, sb))
+        return fail(ctx, GKS_EINVAL, "lam_n overlaps lam_np1 or U_n");
+    if (g_epsinv && g_muinv && ranges_overlap(g_epsinv, g_muinv, gb))
+        return fail(ctx, GKS_EINVAL, "g_epsinv and g_muinv overlap");
+    if (!std::isfinite(t_n)) return fail(ctx, GKS_EINVAL, "t_n is not finite");
+    return check_device(ctx);
 }
 
 gks_status ensure_out(gks_ctx *x, size_t count)
@@ -606,8 +622,12 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
         x->dt = (p->dt > 0) ? p->dt : p->cfl * hmin / p->c;
         if (!(x->dt > 0) || !std::isfinite(x->dt)) return bail(fail(x, GKS_EINVAL, "dt must be positive (set dt or cfl)"));
         const double nu = p->c * x->dt / hmin;
-        if (nu > 0.5 * (1 + 1e-12))
-            return bail(fail(x, GKS_EINVAL, "Courant number c dt / h = %g exceeds the stability limit 0.5", nu));
+        // 2D: 0.5 is the stability limit of the D2Q4 step.  3D: the D3Q4 step grows above 1/3
+        // (the amplification factor of a Fourier mode exceeds 1 at 0.4 and 0.5 for small tau)
+        const double numax = (nd == 2) ? 0.5 : 1.0 / 3.0;
+        if (nu > numax * (1 + 1e-12))
+            return bail(fail(x, GKS_EINVAL, "Courant number c dt / h = %g exceeds the stability limit %s of the %dD step",
+                             nu, nd == 2 ? "0.5" : "1/3", nd));
     } else if (m->kind == GKS_TRI2D) {
         if (m->model != GKS_TM2D && m->model != GKS_TM2D_PHM)
             return bail(fail(x, GKS_EINVAL, "triangle meshes carry TM2D or TM2D_PHM fields"));
@@ -701,6 +721,8 @@ extern "C" gks_status gks_destroy(gks_ctx *ctx)
     if (ctx->d_partial) hipFree(ctx->d_partial);
     if (ctx->d_out) hipFree(ctx->d_out);
     if (ctx->h_out) hipHostFree(ctx->h_out);
+    for (hipEvent_t &ev : ctx->rec_ev)
+        if (ev) hipEventDestroy(ev);
     if (ctx->d_src_cells) hipFree(ctx->d_src_cells);
     if (ctx->d_src_w) hipFree(ctx->d_src_w);
     if (ctx->adj_scratch) hipFree(ctx->adj_scratch);
@@ -784,6 +806,26 @@ extern "C" gks_status gks_step(gks_ctx *ctx, const void *U_in, void *U_out, doub
     return do_step(ctx, U_in, U_out, t_n);
 }
 
+namespace {
+
+// Checks energy record r (host copy in ctx->h_out) of gks_run: not finite -> GKS_ENONFINITE,
+// above unstable_growth times the first record -> GKS_EUNSTABLE.
+gks_status check_record(gks_ctx *x, int64_t r, int64_t every)
+{
+    for (int64_t b = 0; b < x->batch; ++b) {
+        const double w = x->h_out[r * x->batch + b], w0 = x->h_out[b];
+        if (!std::isfinite(w))
+            return fail(x, GKS_ENONFINITE, "energy of batch item %lld is not finite after step %lld", (long long)b,
+                        (long long)((r + 1) * every));
+        if (x->unstable_growth > 0 && w > x->unstable_growth * w0)
+            return fail(x, GKS_EUNSTABLE, "energy of batch item %lld grew by %g after step %lld", (long long)b, w / w0,
+                        (long long)((r + 1) * every));
+    }
+    return GKS_OK;
+}
+
+}  // namespace
+
 extern "C" gks_status gks_run(gks_ctx *ctx, void *U, int64_t nsteps, double t0, double *energy_host)
 {
     if (!ctx) return GKS_EINVAL;
@@ -806,39 +848,50 @@ extern "C" gks_status gks_run(gks_ctx *ctx, void *U, int64_t nsteps, double t0, 
     if (nrec) {
         st = ensure_out(ctx, (size_t)nrec * ctx->batch);
         if (st) return st;
+        for (hipEvent_t &ev : ctx->rec_ev)
+            if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+                return fail(ctx, GKS_EDEVICE, "cannot create the energy record events");
     }
+    // Each energy record is copied to pinned host memory as soon as it is computed; record r - 1
+    // is checked once record r has been enqueued (the host then waits for the GPU to finish the
+    // steps of record r - 1 only, so that the steps of record r keep it busy meanwhile).  The run
+    // stops at the first failing record, at most energy_every steps after it.
     void *cur = U, *nxt = ctx->pingpong;
-    for (int64_t k = 0; k < nsteps; ++k) {
+    int64_t nenq = 0, nchecked = 0;   // records enqueued / checked
+    gks_status bad = GKS_OK;
+    int e = 0;
+    for (int64_t k = 0; k < nsteps && bad == GKS_OK; ++k) {
         st = do_step(ctx, cur, nxt, t0 + (double)k * ctx->dt);
         if (st) return st;
         std::swap(cur, nxt);
         if (every && (k + 1) % every == 0) {
-            st = launch_energy_into(ctx, cur, ctx->d_out + ((k + 1) / every - 1) * ctx->batch);
+            const int64_t r = nenq++;
+            double *dst = ctx->d_out + r * ctx->batch;
+            st = launch_energy_into(ctx, cur, dst);
             if (st) return st;
+            e = hipMemcpyAsync(ctx->h_out + r * ctx->batch, dst, ctx->batch * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream);
+            if (!e) e = hipEventRecord(ctx->rec_ev[r & 1], ctx->stream);
+            if (e) return hip_fail(ctx, e, "energy readback");
+            if (r >= 1) {
+                e = hipEventSynchronize(ctx->rec_ev[(r - 1) & 1]);
+                if (e) return hip_fail(ctx, e, "energy readback");
+                bad = check_record(ctx, r - 1, every);
+                nchecked = r;
+            }
         }
     }
     if (cur != U) {
-        int e = hipMemcpyAsync(U, cur, bytes, hipMemcpyDeviceToDevice, ctx->stream);
+        e = hipMemcpyAsync(U, cur, bytes, hipMemcpyDeviceToDevice, ctx->stream);
         if (e) return hip_fail(ctx, e, "state copy");
     }
-    if (nrec) {
-        const size_t cnt = (size_t)nrec * ctx->batch;
-        int e = hipMemcpyAsync(ctx->h_out, ctx->d_out, cnt * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
-        if (!e) e = hipStreamSynchronize(ctx->stream);
+    if (nenq) {
+        e = hipStreamSynchronize(ctx->stream);
         if (e) return hip_fail(ctx, e, "energy readback");
-        std::memcpy(energy_host, ctx->h_out, cnt * sizeof(double));
-        for (int64_t r = 0; r < nrec; ++r)
-            for (int64_t b = 0; b < ctx->batch; ++b) {
-                const double w = energy_host[r * ctx->batch + b];
-                if (!std::isfinite(w))
-                    return fail(ctx, GKS_ENONFINITE, "energy of batch item %lld is not finite after step %lld",
-                                (long long)b, (long long)((r + 1) * every));
-                if (ctx->unstable_growth > 0 && w > ctx->unstable_growth * energy_host[b])
-                    return fail(ctx, GKS_EUNSTABLE, "energy of batch item %lld grew by %g after step %lld", (long long)b,
-                                w / energy_host[b], (long long)((r + 1) * every));
-            }
+        for (int64_t r = nchecked; r < nenq && bad == GKS_OK; ++r) bad = check_record(ctx, r, every);
+        std::memcpy(energy_host, ctx->h_out, (size_t)nenq * ctx->batch * sizeof(double));
     }
-    return GKS_OK;
+    return bad;
 }
 
 extern "C" gks_status gks_energy(gks_ctx *ctx, const void *U, double *out_host)
@@ -908,19 +961,18 @@ extern "C" gks_status gks_adjoint_step(gks_ctx *ctx, const void *U_n, const void
                                        double *g_epsinv, double *g_muinv, double t_n)
 {
     if (!ctx) return GKS_EINVAL;
-    if (ctx->kind != GKS_CART2D) return fail(ctx, GKS_ESTATE, "the adjoint step exists for Cartesian 2D TM contexts only");
-    if (ctx->limiter)
-        return fail(ctx, GKS_ESTATE, "the adjoint step is that of the linear (unlimited) step; this context limits slopes");
-    if (ctx->model != GKS_TM2D) return fail(ctx, GKS_ESTATE, "the adjoint step is built for the TM fields without PHM");
-    if (!U_n || !lam_np1 || !lam_n) return fail(ctx, GKS_EINVAL, "U_n, lam_np1 or lam_n is NULL");
-    const size_t sb = state_bytes(ctx), gb = (size_t)ctx->batch * ctx->ncell * sizeof(double);
-    if (ranges_overlap(lam_n, lam_np1, sb) || ranges_overlap(lam_n, U_n, sb))
-        return fail(ctx, GKS_EINVAL, "lam_n overlaps lam_np1 or U_n");
-    if (g_epsinv && g_muinv && ranges_overlap(g_epsinv, g_muinv, gb))
-        return fail(ctx, GKS_EINVAL, "g_epsinv and g_muinv overlap");
-    if (!std::isfinite(t_n)) return fail(ctx, GKS_EINVAL, "t_n is not finite");
-    gks_status st = check_device(ctx);
+    gks_status st = check_adjoint(ctx, U_n, lam_np1, lam_n, g_epsinv, g_muinv, t_n);
     if (st) return st;
-    return ctx->prec == GKS_FP64 ? adjoint_cart2d<double>(ctx, U_n, lam_np1, lam_n, g_epsinv, g_muinv, t_n)
-                                 : adjoint_cart2d<float>(ctx, U_n, lam_np1, lam_n, g_epsinv, g_muinv, t_n);
+    const size_t bytes = adjoint_scratch_bytes(ctx);
+    if (ctx->adj_scratch_bytes < bytes) {
+        if (ctx->adj_scratch) hipFree(ctx->adj_scratch);
+        ctx->adj_scratch = nullptr;
+        ctx->adj_scratch_bytes = 0;
+        if (hipMalloc(&ctx->adj_scratch, bytes) != hipSuccess)
+            return fail(ctx, GKS_ENOMEM, "cannot allocate the %zu-byte adjoint scratch", bytes);
+        ctx->adj_scratch_bytes = bytes;
+    }
+    return ctx->prec == GKS_FP64
+               ? adjoint_cart2d<double>(ctx, U_n, lam_np1, lam_n, g_epsinv, g_muinv, t_n, ctx->adj_scratch)
+               : adjoint_cart2d<float>(ctx, U_n, lam_np1, lam_n, g_epsinv, g_muinv, t_n, ctx->adj_scratch);
 }

@@ -185,10 +185,12 @@ struct Cart2DAdjArgs {
 
 // Launchers (defined in the .hip files).  Return a hipError_t as int.
 template <typename T> int launch_cart2d_step(const Cart2DArgs<T> &a, void *stream);
-// Adjoint of one 2D step.  Scratch (device): pad9 [batch][9][(nx+4)(ny+4)] and padpsi
-// [batch][3][(nx+4)(ny+4)] of T, padg [batch][2][(nx+4)(ny+4)] doubles; all fully overwritten.
-template <typename T> int launch_cart2d_adjoint(const Cart2DAdjArgs<T> &a, T *pad9, T *padpsi, double *padg,
-                                                void *stream);
+// Adjoint of one 2D step.  Scratch (device), over the npos = adjoint_ring_positions(nx, ny)
+// ghost positions around the grid: padpsi [batch][3][npos] of T and padg [batch][2][npos]
+// doubles; every entry is written by the step's first kernel before its second reads it, so
+// the scratch needs no clearing between calls.
+template <typename T> int launch_cart2d_adjoint(const Cart2DAdjArgs<T> &a, T *padpsi, double *padg, void *stream);
+int64_t adjoint_ring_positions(int nx, int ny);
 // g_epsinv[b][cells[s]] += lam[b][Ez][cells[s]] * amp * weight[s]  (1/eps gradient of the source)
 template <typename T> int launch_adjoint_source(const T *lam, double *g_epsinv, int64_t ncell, int64_t fstride,
                                                 int32_t batch, const int64_t *cells, const double *weight,

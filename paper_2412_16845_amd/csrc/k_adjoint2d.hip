@@ -20,8 +20,8 @@
 // material sensitivities), accumulates their shares per position (the right cell's share of an
 // x face by DPP), and finishes row q-3, whose faces and whose neighbours' faces are then all
 // known.  Cells receive lambda and their gradients; ghost positions (two layers around the
-// grid) write psi and their material gradients to a padded scratch that a small kernel then
-// adds, with the mirror signs, onto the cells they image.  Everything runs in a fixed order
+// grid) write psi and their material gradients to a scratch array of the ghost positions that
+// a small kernel then adds, with the mirror signs, onto the cells they image.  Everything runs in a fixed order
 // (no atomics), so the adjoint is deterministic.
 #include "gks_device.h"
 
@@ -39,10 +39,21 @@ constexpr int ADJ_CH = 4;
 constexpr int ADJ_MARCH_BLOCK = 64;
 constexpr int ADJ_TILE_Y = 24;   // rows per wave tile (1024^2 x 8: 221 us, against 231 at 16, 236 at 32)
 
-struct Pad2D {
-    int nx, ny, px;   // px = nx + 4
-    __device__ __forceinline__ int64_t idx(int i, int j) const { return (int64_t)(j + 2) * px + (i + 2); }
-    __device__ __forceinline__ int64_t size() const { return (int64_t)(ny + 4) * px; }
+// The ghost positions of an nx x ny grid: the two layers of positions (i, j) around it,
+// -2 <= i <= nx+1 and -2 <= j <= ny+1 outside [0, nx) x [0, ny).  Numbered row by row for the
+// two ghost rows below and the two above, then four per grid row (columns -2, -1, nx, nx+1):
+// 4 (nx + 4) + 4 ny positions, the only ones whose co-states and material gradients go through
+// scratch memory.
+struct Ring2D {
+    int nx, ny;
+    __host__ __device__ int64_t size() const { return 4 * (int64_t)(nx + 4) + 4 * (int64_t)ny; }
+    __device__ __forceinline__ int64_t idx(int i, int j) const
+    {
+        const int64_t w = nx + 4;
+        if (j < 0) return (j + 2) * w + (i + 2);
+        if (j >= ny) return (2 + j - ny) * w + (i + 2);
+        return 4 * w + 4 * (int64_t)j + (i < 0 ? i + 2 : i - nx + 2);
+    }
 };
 
 template <typename T>
@@ -264,7 +275,7 @@ struct AdjStrip {
                     if (a.g_epsinv) a.g_epsinv[(int64_t)b * ncell + c] += gE;
                     if (a.g_muinv) a.g_muinv[(int64_t)b * ncell + c] += gH;
                 } else {
-                    const Pad2D pd{a.nx, a.ny, a.nx + 4};
+                    const Ring2D pd{a.nx, a.ny};
                     const int64_t npos = pd.size(), pp = pd.idx(x, r);
 #pragma unroll
                     for (int f = 0; f < 3; ++f) padpsi[((int64_t)b * 3 + f) * npos + pp] = psi[f];
@@ -378,7 +389,7 @@ struct Band2D {
 template <typename T>
 __global__ __launch_bounds__(ADJ_BLOCK) void adj2d_fold_kernel(Cart2DAdjArgs<T> a, const T *padpsi, const double *padg)
 {
-    const Pad2D pd{a.nx, a.ny, a.nx + 4};
+    const Ring2D pd{a.nx, a.ny};
     const int64_t npos = pd.size();
     const int64_t ncell = (int64_t)a.nx * a.ny;
     const int b = blockIdx.y;
@@ -433,10 +444,11 @@ __global__ void adj_source_kernel(const T *lam, double *g_epsinv, int64_t ncell,
     g_epsinv[(int64_t)b * ncell + c] += (double)lam[(int64_t)b * fstride + c] * (amp * weight[s]);
 }
 
+int64_t adjoint_ring_positions(int nx, int ny) { return Ring2D{nx, ny}.size(); }
+
 template <typename T>
-int launch_cart2d_adjoint(const Cart2DAdjArgs<T> &a, T *pad9, T *padpsi, double *padg, void *stream)
+int launch_cart2d_adjoint(const Cart2DAdjArgs<T> &a, T *padpsi, double *padg, void *stream)
 {
-    (void)pad9;
     hipStream_t s = (hipStream_t)stream;
     const int ntx = (a.nx + (WAVE - 4) - 1) / (WAVE - 4), nty = (a.ny + ADJ_TILE_Y - 1) / ADJ_TILE_Y;
     const int64_t waves = (int64_t)ntx * nty * a.batch;
@@ -464,8 +476,8 @@ int launch_adjoint_source(const T *lam, double *g_epsinv, int64_t ncell, int64_t
     return (int)hipGetLastError();
 }
 
-template int launch_cart2d_adjoint<float>(const Cart2DAdjArgs<float> &, float *, float *, double *, void *);
-template int launch_cart2d_adjoint<double>(const Cart2DAdjArgs<double> &, double *, double *, double *, void *);
+template int launch_cart2d_adjoint<float>(const Cart2DAdjArgs<float> &, float *, double *, void *);
+template int launch_cart2d_adjoint<double>(const Cart2DAdjArgs<double> &, double *, double *, void *);
 template int launch_adjoint_source<float>(const float *, double *, int64_t, int64_t, int32_t, const int64_t *,
                                           const double *, double, int32_t, void *);
 template int launch_adjoint_source<double>(const double *, double *, int64_t, int64_t, int32_t, const int64_t *,

@@ -15,9 +15,9 @@
 //   3. evaluates the GKS flux of the horizontal face below the middle row and of the vertical
 //      face right of each column, as sparse linear forms of the stencil values (the
 //      closed-form moments of Sec. 3.1 folded into coefficients on the host);
-//   4. forms the flux divergence of each cell of the row it finishes, adds it to the old value
-//      with a single rounding (FP32: one fused multiply-add; FP64, and the row of a single
-//      source cell: in double precision, with the explicit source) and stores once
+//   4. sums the face fluxes of each cell of the row it finishes in double precision (in FP32
+//      mode the fluxes are widened first), adds the divergence and a single point source to the
+//      old value in double precision and stores the result rounded once to the storage type
 //      (longer source lists are added afterwards by a small scatter kernel, which keeps the
 //      per-cell source tests out of the marching loop).
 // The row loop is unrolled six times so that the rotating window (six row slots, two gradient
@@ -243,46 +243,30 @@ struct Strip2D {
             apply_op<typename FS::PX, CH2>(v, Rs.mE[k] + mEr, Rs.mH[k] + mHr, opx, fx[k]);
         }
 
-        // update: per-cell flux divergence (FP32 in FP32 mode), then its addition to the old
-        // value with a single rounding; the row of a single point-source cell adds the source
-        // in the same rounding, in FP64 (longer source lists are added by a separate scatter
-        // kernel)
+        // update: the face fluxes (FP32 in FP32 mode) are widened to FP64, their divergence is
+        // summed and added to the old value in FP64 with the explicit point source, and the
+        // result is rounded once to the storage type (longer source lists are added by a
+        // separate scatter kernel)
         const int row = q - 2 * sd;
         const uint32_t rowc = (uint32_t)row * (uint32_t)a.nx;
-        T nv[NC][NF], div[NC][NF];
+        T nv[NC][NF];
+        double src[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) src[k] = (row == a.src_row && gx0 + k == a.src_col) ? a.src_amp : 0.0;
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                const T fl = (k > 0) ? fx[k > 0 ? k - 1 : 0][f] : from_left(fx[NC - 1][f]);
-                const T dyf = DN ? fyP[k][f] - fyN[k][f] : fyN[k][f] - fyP[k][f];   // upper - lower face
-                div[k][f] = (fx[k][f] - fl) + dyf;
+                const double fr = (double)fx[k][f];
+                const double fl = (double)((k > 0) ? fx[k > 0 ? k - 1 : 0][f] : from_left(fx[NC - 1][f]));
+                const double fu = (double)(DN ? fyP[k][f] : fyN[k][f]);   // upper face
+                const double fd = (double)(DN ? fyN[k][f] : fyP[k][f]);   // lower face
+                const double div = (fr - fl) + (fu - fd);
+                // 1/eps scales Ez, 1/mu scales H; psi carries no material factor
+                const double m = (f == 0) ? (double)Rs.mE[k] : (f < 3) ? (double)Rs.mH[k] : 1.0;
+                const double add = (f == 0) ? src[k] : 0.0;
+                nv[k][f] = (T)fma(m, add - div, (double)Rs.u[k][f]);
             }
-        }
-        // 1/eps scales Ez, 1/mu scales H; psi carries no material factor
-        if (sizeof(T) == 4 && row != a.src_row) {   // uniform: FP32, a row without the point source
-            // one fused multiply-add: the exact U - m div rounded once to FP32, never less
-            // accurate than the FP64 form below (4096^2: 113.7 -> 113.0 us; FP64 keeps its form,
-            // where the second copy of the update added scalar spills, 203.7 -> 205.9 us)
-#pragma unroll
-            for (int k = 0; k < NC; ++k)
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    const T m = (f == 0) ? Rs.mE[k] : (f < 3) ? Rs.mH[k] : T(1);
-                    nv[k][f] = fma(-m, div[k][f], Rs.u[k][f]);
-                }
-        } else {
-            double src[NC];
-#pragma unroll
-            for (int k = 0; k < NC; ++k) src[k] = (row == a.src_row && gx0 + k == a.src_col) ? a.src_amp : 0.0;
-#pragma unroll
-            for (int k = 0; k < NC; ++k)
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    const double m = (f == 0) ? (double)Rs.mE[k] : (f < 3) ? (double)Rs.mH[k] : 1.0;
-                    const double add = (f == 0) ? src[k] : 0.0;
-                    nv[k][f] = (T)((double)Rs.u[k][f] + m * (add - (double)div[k][f]));
-                }
         }
         if constexpr (!BND) {
             // interior strips: every lane but the two halo lanes writes all its columns

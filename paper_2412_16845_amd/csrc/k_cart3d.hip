@@ -15,8 +15,9 @@
 //      closed-form moments of Sec. 3.1 folded into coefficients on the host), the flux of the
 //      face above each cell (y, with the upper row's data from LDS), right of it (x, with the
 //      next lane's data by DPP) and below it in z (from the previous plane kept in registers);
-//   4. shares the y fluxes and finishes the flux divergence of each cell of plane q-1, adding
-//      it to the old value with a single rounding (one fused multiply-add) on store.
+//   4. shares the y fluxes and finishes the flux divergence of each cell of plane q-1, summed in
+//      double precision (the FP32 face fluxes are widened first), adds it to the old value in
+//      double precision and stores the result rounded once to the storage type.
 // Each face is evaluated once; each field value is loaded once per workgroup.  In fp32 the
 // fields are double-buffered by plane parity (the next plane's fields are written before the
 // last barrier of the current one), which leaves two barriers per plane; in fp64 they are
@@ -144,11 +145,20 @@ struct March3D {
 
     __device__ __forceinline__ bool plane_nr(int gz) const { return side_nr(gz, a.nz, a.bc[4], a.bc[5]); }
 
+    // The differences of plane q-1 for the z face below plane q: in fp32 they are read back
+    // from the LDS slot this wave wrote them to in the previous step, which keeps them out of
+    // the 128 registers of the 16-wave workgroup (with them in registers the double-precision
+    // accumulator spilled: 384^3, 1528 -> 1378 us); fp64 keeps them in registers (3604 us
+    // against 3770 us with the LDS reads).
+    static constexpr bool GP_LDS = sizeof(T) == 4;
+    __device__ __forceinline__ T gprev(const T (&Gp)[3 * NF], int k) const { return GP_LDS ? s.g[k][row][lane] : Gp[k]; }
+
     // One march step with central plane q: A = q-1, B = q, C = q+1 (loaded), D receives q+2.
     // Gp / G: differences of planes q-1 / q.  acc: on entry the x and y divergence of plane
-    // q-1 minus the flux of the z face below it; on exit the same for plane q.
+    // q-1 minus the flux of the z face below it, in double precision; on exit the same for
+    // plane q.
     __device__ __forceinline__ void step(int q, Plane &A, Plane &B, Plane &C, Plane &D, T (&Gp)[3 * NF],
-                                         T (&G)[3 * NF], T (&acc)[NF]) const
+                                         T (&G)[3 * NF], double (&acc)[NF]) const
     {
         const OpT *ops = (const OpT *)a.ops;
         // plane q+2 (beyond the range: re-read the last halo plane, already cached, so that the
@@ -208,9 +218,9 @@ struct March3D {
                 for (int f = 0; f < NF; ++f) {
                     w[f] = A.u[f];
                     w[NF + f] = B.u[f];
-                    w[2 * NF + f] = Gp[2 * NF + f];
-                    w[3 * NF + f] = Gp[f];
-                    w[4 * NF + f] = Gp[NF + f];
+                    w[2 * NF + f] = gprev(Gp, 2 * NF + f);
+                    w[3 * NF + f] = gprev(Gp, f);
+                    w[4 * NF + f] = gprev(Gp, NF + f);
                     w[5 * NF + f] = G[2 * NF + f];
                     w[6 * NF + f] = G[f];
                     w[7 * NF + f] = G[NF + f];
@@ -223,9 +233,9 @@ struct March3D {
                 for (int f = 0; f < NF; ++f) {
                     w[f] = zl ? T(0) : A.u[f];
                     w[NF + f] = zr ? T(0) : B.u[f];
-                    w[2 * NF + f] = zl ? T(0) : Gp[2 * NF + f];
-                    w[3 * NF + f] = zl ? T(0) : Gp[f];
-                    w[4 * NF + f] = zl ? T(0) : Gp[NF + f];
+                    w[2 * NF + f] = zl ? T(0) : gprev(Gp, 2 * NF + f);
+                    w[3 * NF + f] = zl ? T(0) : gprev(Gp, f);
+                    w[4 * NF + f] = zl ? T(0) : gprev(Gp, NF + f);
                     w[5 * NF + f] = zr ? T(0) : G[2 * NF + f];
                     w[6 * NF + f] = zr ? T(0) : G[f];
                     w[7 * NF + f] = zr ? T(0) : G[NF + f];
@@ -236,17 +246,17 @@ struct March3D {
                 const uint32_t so = (uint32_t)(q - 1) * pbytes;
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
-                    const T div = acc[f] + Z[f];
+                    // the divergence and its addition to the old value in double precision,
+                    // rounded once to the storage type on store
+                    const double div = acc[f] + (double)Z[f];
                     // 1/eps scales E, 1/mu scales H; the potentials carry no material factor
-                    // FP32: one fused multiply-add, the exact U - m div rounded once (384^3: 1321 ->
-                    // 1309 us against the FP64 form, which rounds twice); FP64 unchanged
-                    const T m = (f < 3) ? A.mE : (f < 6) ? A.mH : T(1);
-                    const T nv = fma(-m, div, A.u[f]);
+                    const double m = (f < 3) ? (double)A.mE : (f < 6) ? (double)A.mH : 1.0;
+                    const T nv = (T)fma(-m, div, (double)A.u[f]);
                     if (writer) buf_store(nv, rO, vcol, so + f * fbytes);
                 }
             }
 #pragma unroll
-            for (int f = 0; f < NF; ++f) acc[f] = -Z[f];
+            for (int f = 0; f < NF; ++f) acc[f] = -(double)Z[f];
         }
         if (need_g) {
 #pragma unroll
@@ -311,18 +321,20 @@ struct March3D {
         __syncthreads();
         if (outp && need_all) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) acc[f] += (px[f] - from_left(px[f])) + (py[f] - s.p[f][rowm][lane]);
+            for (int f = 0; f < NF; ++f)
+                acc[f] += ((double)px[f] - (double)from_left(px[f])) + ((double)py[f] - (double)s.p[f][rowm][lane]);
         }
     }
 
     __device__ __forceinline__ void run() const
     {
         Plane P0, P1, P2, P3;
-        T G0[3 * NF], G1[3 * NF], acc[NF];
+        T G0[3 * NF], G1[3 * NF];
+        double acc[NF];   // flux divergence of the plane being finished, in double precision
 #pragma unroll
         for (int k = 0; k < 3 * NF; ++k) G0[k] = G1[k] = T(0);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) acc[f] = T(0);
+        for (int f = 0; f < NF; ++f) acc[f] = 0.0;
         const int qs = z0 - 1;
         load(qs - 1, P0);
         load(qs, P1);
@@ -333,14 +345,27 @@ struct March3D {
             __syncthreads();
         }
         const int n = z1 - z0 + 2;   // central planes z0-1 .. z1
-        for (int i = 0; i < n; i += 4) {
-            step(qs + i, P0, P1, P2, P3, G1, G0, acc);
-            if (i + 1 >= n) break;
-            step(qs + i + 1, P1, P2, P3, P0, G0, G1, acc);
-            if (i + 2 >= n) break;
-            step(qs + i + 2, P2, P3, P0, P1, G1, G0, acc);
-            if (i + 3 >= n) break;
-            step(qs + i + 3, P3, P0, P1, P2, G0, G1, acc);
+        if constexpr (GP_LDS) {
+            // one register set of differences: the previous plane's come from LDS
+            for (int i = 0; i < n; i += 4) {
+                step(qs + i, P0, P1, P2, P3, G0, G0, acc);
+                if (i + 1 >= n) break;
+                step(qs + i + 1, P1, P2, P3, P0, G0, G0, acc);
+                if (i + 2 >= n) break;
+                step(qs + i + 2, P2, P3, P0, P1, G0, G0, acc);
+                if (i + 3 >= n) break;
+                step(qs + i + 3, P3, P0, P1, P2, G0, G0, acc);
+            }
+        } else {
+            for (int i = 0; i < n; i += 4) {
+                step(qs + i, P0, P1, P2, P3, G1, G0, acc);
+                if (i + 1 >= n) break;
+                step(qs + i + 1, P1, P2, P3, P0, G0, G1, acc);
+                if (i + 2 >= n) break;
+                step(qs + i + 2, P2, P3, P0, P1, G1, G0, acc);
+                if (i + 3 >= n) break;
+                step(qs + i + 3, P3, P0, P1, P2, G0, G1, acc);
+            }
         }
     }
 };

@@ -12,7 +12,7 @@
 //      rotated back and stored times |l|.  Each face is evaluated once, from its owner: the
 //      D3Q4 lattice is chiral, so the other side's flux would differ;
 //   3. one thread per cell: the four face fluxes with the sign of the cell's side, divided by
-//      |Omega|, added to the old value with one fused multiply-add (a single rounding).
+//      |Omega|, added to the old value in double precision and rounded once on store.
 // Boundary faces: non-reflecting (the ghost side carries no distribution) or PEC (face-frame
 // mirror of the state, the normal slope mirrored with the opposite sign).
 #include "gks_device.h"
@@ -197,25 +197,28 @@ __global__ __launch_bounds__(TET_BLOCK) void tet_update_kernel(TetArgs<T> a)
     const int b = blockIdx.y;
     if (i >= nc) return;
     const T *Fl = a.flux + (int64_t)b * nf * 6;
-    T div[6];
+    double div[6];   // sum of the four face fluxes, in double precision
 #pragma unroll
-    for (int f = 0; f < 6; ++f) div[f] = T(0);
+    for (int f = 0; f < 6; ++f) div[f] = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int32_t cf = a.cf[k * nc + i];
         const int64_t s = (cf > 0 ? cf : -cf) - 1;
-        const T sg = cf > 0 ? T(1) : T(-1);
 #pragma unroll
-        for (int f = 0; f < 6; ++f) div[f] = fma(sg, Fl[s * 6 + f], div[f]);
+        for (int f = 0; f < 6; ++f) {
+            const double v = (double)Fl[s * 6 + f];
+            div[f] = cf > 0 ? div[f] + v : div[f] - v;
+        }
     }
-    const T iv = a.cgeo[TC_IVOL * nc + i];
+    const double iv = (double)a.cgeo[TC_IVOL * nc + i];
     const T mE = HAS_EPS ? a.epsinv[(int64_t)b * nc + i] : T(1), mH = HAS_MU ? a.muinv[(int64_t)b * nc + i] : T(1);
     const T *U = a.U + (int64_t)b * 6 * nc;
     T *O = a.Unew + (int64_t)b * 6 * nc;
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-        const T m = (f < 3) ? mE : mH;
-        O[f * nc + i] = fma(-m, div[f] * iv, U[f * nc + i]);   // U - m x rounded once, x = div / |Omega|
+        // U - m div / |Omega| in double precision, rounded once to the storage type
+        const double m = (f < 3) ? (double)mE : (double)mH;
+        O[f * nc + i] = (T)fma(-m, div[f] * iv, (double)U[f * nc + i]);
     }
 }
 

@@ -13,8 +13,10 @@
 //   2. the cell's three faces and its update: each face is reconstructed at its midpoint from
 //      both sides, rotated into its frame (printed rotation of Sec. 3.1: local axes n and
 //      (-n_y, n_x)), evaluated as a sparse linear form of the face-frame states and slopes (the
-//      closed-form flux folded into coefficients on the host), rotated back, and the cell's
-//      divergence is added to its old value with one fused multiply-add (a single rounding).
+//      closed-form flux folded into coefficients on the host; both states taken relative to the
+//      cell's own, which leaves the sum of the three fluxes unchanged), rotated back, and the
+//      cell's divergence is summed and added to its old value in double precision, rounded once
+//      on store.
 // A face is evaluated by both of its cells, each from its own side: no face fluxes are stored
 // and no atomics are needed.  Boundary faces: non-reflecting (the ghost side carries no
 // distribution) or PEC (face-frame mirror of the state, the normal slope mirrored with the
@@ -142,9 +144,9 @@ __global__ __launch_bounds__((tri_block<T, NF>())) void tri_step_kernel(TriArgs<
     for (int f = 0; f < NF; ++f) u[f] = U[f * nc + i];
     load_grad<T, NF>(Gr, i, gx, gy);
     const T mE = HAS_EPS ? E[i] : T(1), mH = HAS_MU ? M[i] : T(1);
-    T div[NF];
+    double div[NF];   // sum of the face fluxes, in double precision
 #pragma unroll
-    for (int f = 0; f < NF; ++f) div[f] = T(0);
+    for (int f = 0; f < NF; ++f) div[f] = 0.0;
     // midpoint offsets of slots 0 and 1; slot 2's is minus their sum
     const T ax01[2] = {a.geo[(TG_AX + 0) * nc + i], a.geo[(TG_AX + 1) * nc + i]};
     const T ay01[2] = {a.geo[(TG_AY + 0) * nc + i], a.geo[(TG_AY + 1) * nc + i]};
@@ -155,19 +157,25 @@ __global__ __launch_bounds__((tri_block<T, NF>())) void tri_step_kernel(TriArgs<
         const T lw = a.geo[(TG_LW + k) * nc + i];
         const T ax = k < 2 ? ax01[k < 2 ? k : 0] : -(ax01[0] + ax01[1]);
         const T ay = k < 2 ? ay01[k < 2 ? k : 0] : -(ay01[0] + ay01[1]);
-        // own side: reconstruction at the midpoint, slopes along n and t, all in the face frame;
-        // w = [Ul Ur s1l s2l s1r s2r] x fields
+        // The face operator is linear and, for a constant state on both sides, gives that
+        // state's physical flux through the face, which the cell's three faces sum to zero
+        // (sum_k |l_k| n_k = 0).  Both sides therefore enter relative to the cell's own state
+        // (U_l - U_i, U_r - U_i): the result is the same, and the FP32 rounding of the stored
+        // geometry then scales these differences instead of the state itself, so it does not
+        // accumulate into a spurious source.  w = [Ul Ur s1l s2l s1r s2r] x fields, face frame.
         T w[6 * NF];
+        T tu[NF];   // the cell's own state in the face frame
+        to_face<T, NF>(u, nx, ny, tu);
         {
-            T ul[NF], dn[NF], dt[NF];
+            T dl[NF], dn[NF], dt[NF];
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                ul[f] = u[f] + gx[f] * ax + gy[f] * ay;
+                dl[f] = gx[f] * ax + gy[f] * ay;   // U_l - U_i: the reconstruction offset
                 dn[f] = gx[f] * nx + gy[f] * ny;
                 dt[f] = gy[f] * nx - gx[f] * ny;
             }
             T o[NF];
-            to_face<T, NF>(ul, nx, ny, o);
+            to_face<T, NF>(dl, nx, ny, o);
 #pragma unroll
             for (int f = 0; f < NF; ++f) w[f] = o[f];
             to_face<T, NF>(dn, nx, ny, o);
@@ -180,17 +188,17 @@ __global__ __launch_bounds__((tri_block<T, NF>())) void tri_step_kernel(TriArgs<
         T mEs, mHs;
         if (nb >= 0) {
             const T bx = a.geo[(TG_BX + k) * nc + i], by = a.geo[(TG_BY + k) * nc + i];
-            T ur[NF], dn[NF], dt[NF], hxs[NF], hys[NF];
+            T dr[NF], dn[NF], dt[NF], hxs[NF], hys[NF];
             load_grad<T, NF>(Gr, nb, hxs, hys);
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 const T v = U[f * nc + nb], hx = hxs[f], hy = hys[f];
-                ur[f] = v + hx * bx + hy * by;
+                dr[f] = (v - u[f]) + (hx * bx + hy * by);   // U_r - U_i
                 dn[f] = hx * nx + hy * ny;
                 dt[f] = hy * nx - hx * ny;
             }
             T o[NF];
-            to_face<T, NF>(ur, nx, ny, o);
+            to_face<T, NF>(dr, nx, ny, o);
 #pragma unroll
             for (int f = 0; f < NF; ++f) w[NF + f] = o[f];
             to_face<T, NF>(dn, nx, ny, o);
@@ -202,20 +210,24 @@ __global__ __launch_bounds__((tri_block<T, NF>())) void tri_step_kernel(TriArgs<
             mEs = mE + (HAS_EPS ? E[nb] : T(1));
             mHs = mH + (HAS_MU ? M[nb] : T(1));
         } else if (nb == -(1 + GKS_BC_PEC)) {
-            // face-frame mirror P = diag(-1, -1, +1[, +1]) on (Ez, Hn, Ht[, psi]); normal slope
-            // -P, tangential slope P
+            // face-frame mirror P = diag(-1, -1, +1[, +1]) on (Ez, Hn, Ht[, psi]) of the left
+            // state U_i + w_l: U_r - U_i = P w_l + (P - 1) U_i; normal slope -P, tangential slope P
             constexpr T PS[4] = {T(-1), T(-1), T(1), T(1)};
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                w[NF + f] = PS[f] * w[f];
+                w[NF + f] = PS[f] * w[f] + (PS[f] - T(1)) * tu[f];
                 w[4 * NF + f] = -PS[f] * w[2 * NF + f];
                 w[5 * NF + f] = PS[f] * w[3 * NF + f];
             }
             mEs = mE + mE;
             mHs = mH + mH;
         } else {
+            // non-reflecting: no distribution on the ghost side, U_r = 0, U_r - U_i = -U_i
 #pragma unroll
-            for (int f = 0; f < NF; ++f) w[NF + f] = w[4 * NF + f] = w[5 * NF + f] = T(0);
+            for (int f = 0; f < NF; ++f) {
+                w[NF + f] = -tu[f];
+                w[4 * NF + f] = w[5 * NF + f] = T(0);
+            }
             mEs = mE + mE;
             mHs = mH + mH;
         }
@@ -223,18 +235,20 @@ __global__ __launch_bounds__((tri_block<T, NF>())) void tri_step_kernel(TriArgs<
         // coefficient chunk: 6 for the fp64 TM kernel (4.06M cells: 395.4 -> 390.7 us, no scalar
         // spills), 12 elsewhere
         apply_op<P, (sizeof(T) == 8 && NF == 3) ? 6 : 12>(w, mEs, mHs, scalar_ptr((const OpT *)a.op), phi);
-        // back to the global frame, times |l| / |Omega|
-        div[0] = fma(lw, phi[0], div[0]);
-        div[1] = fma(lw, phi[1] * nx - phi[2] * ny, div[1]);
-        div[2] = fma(lw, phi[1] * ny + phi[2] * nx, div[2]);
-        if constexpr (NF == 4) div[3] = fma(lw, phi[3], div[3]);
+        // back to the global frame, times |l| / |Omega| (the face's flux, in the storage type),
+        // added to the divergence in double precision
+        div[0] += (double)(lw * phi[0]);
+        div[1] += (double)(lw * (phi[1] * nx - phi[2] * ny));
+        div[2] += (double)(lw * (phi[1] * ny + phi[2] * nx));
+        if constexpr (NF == 4) div[3] += (double)(lw * phi[3]);
     }
     T *O = a.Unew + (int64_t)b * NF * nc;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        // 1/eps scales Ez, 1/mu scales H; psi carries no material factor
-        const T m = (f == 0) ? mE : (f < 3) ? mH : T(1);
-        O[f * nc + i] = fma(-m, div[f], u[f]);   // the exact u - m div, rounded once
+        // 1/eps scales Ez, 1/mu scales H; psi carries no material factor.  u - m div in double
+        // precision, rounded once to the storage type
+        const double m = (f == 0) ? (double)mE : (f < 3) ? (double)mH : 1.0;
+        O[f * nc + i] = (T)fma(-m, div[f], (double)u[f]);
     }
 }
 

@@ -85,11 +85,25 @@ def _init(gks, **over):
     ({"model": 2, "chi": -0.1}, "[0, 1]"),
     ({"model": 2, "limiter": 1}, "not available with the PHM"),
     ({"model": 2, "kind": 1, "n": (8, 8, 8)}, "Cartesian 2D"),
+    # 3D grids: the D3Q4 step grows above a Courant number of 1/3 (0.5 is 2D's limit)
+    ({"model": 1, "kind": 1, "n": (8, 8, 8), "cfl": 0.5}, "1/3"),
+    ({"model": 1, "kind": 1, "n": (8, 8, 8), "cfl": 0.34}, "1/3"),
+    ({"model": 3, "kind": 1, "n": (8, 8, 8), "cfl": 0.4}, "1/3"),
+    ({"model": 1, "kind": 1, "n": (8, 8, 8), "dt": 0.05}, "1/3"),   # c dt / h = 0.4
 ])
 def test_init_rejects_bad_arguments(gks, over, needle):
     st, msg = _init(gks, **over)
     assert st == -1, (st, msg)
     assert needle in msg
+
+
+def test_init_accepts_3d_courant_one_third(gks):
+    """The 3D limit itself is accepted (CFL 1/3 runs every 3D workload); the rejections above
+    are therefore the limit, not a blanket refusal of 3D grids.  The check precedes any GPU call,
+    so only the argument path is exercised here: without a GPU the call fails later, at the
+    device query."""
+    st, msg = _init(gks, model=1, kind=1, n=(8, 8, 8), cfl=1.0 / 3.0)
+    assert "1/3" not in msg and "Courant" not in msg, msg
 
 
 def test_null_arguments(gks):
