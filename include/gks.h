@@ -213,6 +213,19 @@ gks_status gks_run(gks_ctx *ctx, void *U, int64_t nsteps, double t0, double *ene
 gks_status gks_adjoint_step(gks_ctx *ctx, const void *U_n, const void *lam_np1, void *lam_n,
                             double *g_epsinv, double *g_muinv, double t_n);
 
+/*
+ * gks_adjoint_step for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same operation, arguments,
+ * results and errors, but its scratch is a static device array of 16 MiB per GPU that the
+ * library holds until the process ends, so the call itself allocates nothing.  A grid and batch
+ * needing more scratch than that (see gks_adjoint_step) are refused with GKS_EINVAL before any
+ * launch.  The array is shared by every call on one GPU, across contexts: calls that overlap on
+ * one GPU (concurrent streams, threads) race and must be serialised by the caller.  Each call
+ * writes every scratch entry it reads, so nothing carries over from earlier calls.
+ */
+gks_status gks_adjoint_step_noalloc(gks_ctx *ctx, const void *U_n, const void *lam_np1, void *lam_n,
+                                    double *g_epsinv, double *g_muinv, double t_n);
+
 /* Energy W = 1/2 sum_i |Omega_i| (eps_i |E_i|^2 + mu_i |H_i|^2) of each batch item (plus
  * 1/2 sum_i |Omega_i| (phi_i^2 + psi_i^2) with the PHM models), summed in double precision in
  * a fixed order; out_host: host, [batch].  Synchronises the stream. */

@@ -65,6 +65,8 @@ struct gks_ctx {
     hipEvent_t rec_ev[2] = {nullptr, nullptr};   // gks_run: energy record r read back (r mod 2)
     void *adj_scratch = nullptr;    // adjoint: co-states and material gradients of the ghost positions
     size_t adj_scratch_bytes = 0;
+    void *static_scratch = nullptr; // gks_adjoint_step_noalloc: this device's static scratch array
+    int static_scratch_err = 0;     // its lookup's error (hipError_t) when static_scratch is NULL
 
     // triangle meshes: per cell-face neighbours and geometry, cell areas, gradient scratch
     int32_t *d_tri_nb = nullptr;
@@ -691,6 +693,11 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
     }
     if (x->kind == GKS_CART2D)
         x->tile_y = cart2d_pick_tile_y((int)x->n[0], (int)x->n[1], (int)x->batch, x->ncu, x->prec);
+    if (x->kind == GKS_CART2D && x->model == GKS_TM2D) {
+        // the device address of the allocation-free adjoint's static scratch (once per device)
+        x->static_scratch_err = adjoint_static_scratch(&x->static_scratch);
+        if (x->static_scratch_err) x->static_scratch = nullptr;
+    }
     if (x->kind == GKS_CART3D)
         x->tile_z = cart3d_pick_tile_z((int)x->n[0], (int)x->n[1], (int)x->n[2], (int)x->batch, x->ncu, x->prec,
                                        x->nfields);
@@ -975,4 +982,27 @@ extern "C" gks_status gks_adjoint_step(gks_ctx *ctx, const void *U_n, const void
     return ctx->prec == GKS_FP64
                ? adjoint_cart2d<double>(ctx, U_n, lam_np1, lam_n, g_epsinv, g_muinv, t_n, ctx->adj_scratch)
                : adjoint_cart2d<float>(ctx, U_n, lam_np1, lam_n, g_epsinv, g_muinv, t_n, ctx->adj_scratch);
+}
+
+// ---------------------------------------------------------------- allocation-free adjoint step
+extern "C" gks_status gks_adjoint_step_noalloc(gks_ctx *ctx, const void *U_n, const void *lam_np1, void *lam_n,
+                                               double *g_epsinv, double *g_muinv, double t_n)
+{
+    if (!ctx) return GKS_EINVAL;
+    if (ctx->kind == GKS_CART2D && ctx->model == GKS_TM2D) {
+        const size_t bytes = adjoint_scratch_bytes(ctx);
+        if (bytes > ADJ_STATIC_SCRATCH_BYTES)
+            return fail(ctx, GKS_EINVAL,
+                        "this grid and batch need %zu bytes of adjoint scratch; the static scratch holds %zu "
+                        "(use gks_adjoint_step)",
+                        bytes, (size_t)ADJ_STATIC_SCRATCH_BYTES);
+    }
+    gks_status st = check_adjoint(ctx, U_n, lam_np1, lam_n, g_epsinv, g_muinv, t_n);
+    if (st) return st;
+    if (!ctx->static_scratch)
+        return fail(ctx, GKS_EDEVICE, "the static adjoint scratch of this device is not available (lookup failed: %s)",
+                    hipGetErrorString((hipError_t)ctx->static_scratch_err));
+    return ctx->prec == GKS_FP64
+               ? adjoint_cart2d<double>(ctx, U_n, lam_np1, lam_n, g_epsinv, g_muinv, t_n, ctx->static_scratch)
+               : adjoint_cart2d<float>(ctx, U_n, lam_np1, lam_n, g_epsinv, g_muinv, t_n, ctx->static_scratch);
 }

@@ -191,6 +191,11 @@ template <typename T> int launch_cart2d_step(const Cart2DArgs<T> &a, void *strea
 // the scratch needs no clearing between calls.
 template <typename T> int launch_cart2d_adjoint(const Cart2DAdjArgs<T> &a, T *padpsi, double *padg, void *stream);
 int64_t adjoint_ring_positions(int nx, int ny);
+// The allocation-free adjoint's scratch: a static device array of ADJ_STATIC_SCRATCH_BYTES per
+// GPU.  adjoint_static_scratch returns its address on the current device (looked up once per
+// device, then cached); a hipError_t as int.
+constexpr size_t ADJ_STATIC_SCRATCH_BYTES = size_t(16) << 20;
+int adjoint_static_scratch(void **ptr);
 // g_epsinv[b][cells[s]] += lam[b][Ez][cells[s]] * amp * weight[s]  (1/eps gradient of the source)
 template <typename T> int launch_adjoint_source(const T *lam, double *g_epsinv, int64_t ncell, int64_t fstride,
                                                 int32_t batch, const int64_t *cells, const double *weight,

@@ -23,6 +23,8 @@
 // grid) write psi and their material gradients to a scratch array of the ghost positions that
 // a small kernel then adds, with the mirror signs, onto the cells they image.  Everything runs in a fixed order
 // (no atomics), so the adjoint is deterministic.
+#include <mutex>
+
 #include "gks_device.h"
 
 namespace gks {
@@ -445,6 +447,33 @@ __global__ void adj_source_kernel(const T *lam, double *g_epsinv, int64_t ncell,
 }
 
 int64_t adjoint_ring_positions(int nx, int ny) { return Ring2D{nx, ny}.size(); }
+
+// Scratch of the allocation-free adjoint step (gks_adjoint_step_noalloc): one array per GPU in
+// the library's device data, shared by every call on that GPU.  Its address on each device is
+// looked up once (with that device current) and kept; host code passes that address, never the
+// array's name, to the kernels.
+static __device__ __align__(256) unsigned char scratch[ADJ_STATIC_SCRATCH_BYTES];
+
+int adjoint_static_scratch(void **ptr)
+{
+    constexpr int MAXDEV = 64;
+    static std::mutex mu;
+    static void *addr[MAXDEV] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev < 0 || dev >= MAXDEV) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        if (!p) return (int)hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return 0;
+}
 
 template <typename T>
 int launch_cart2d_adjoint(const Cart2DAdjArgs<T> &a, T *padpsi, double *padg, void *stream)

@@ -26,7 +26,7 @@ STATUS = {0: "GKS_OK", -1: "GKS_EINVAL", -2: "GKS_ENOMEM", -3: "GKS_EDEVICE", -4
 # entry points declared in include/gks.h
 EXPORTS = ("gks_init_mesh", "gks_destroy", "gks_last_error", "gks_get_dt", "gks_flux_coefficients",
            "gks_set_material", "gks_set_point_source", "gks_step", "gks_run", "gks_adjoint_step",
-           "gks_energy", "gks_probe_energy", "gks_probe_energy_grad")
+           "gks_energy", "gks_probe_energy", "gks_probe_energy_grad", "gks_adjoint_step_noalloc")
 
 
 class GKSError(RuntimeError):
@@ -77,6 +77,7 @@ def lib():
         "gks_step": [vp, vp, vp, dbl],
         "gks_run": [vp, vp, i64, dbl, vp],
         "gks_adjoint_step": [vp, vp, vp, vp, vp, vp, dbl],
+        "gks_adjoint_step_noalloc": [vp, vp, vp, vp, vp, vp, dbl],
         "gks_energy": [vp, vp, vp],
         "gks_probe_energy": [vp, vp, vp, vp],
         "gks_probe_energy_grad": [vp, vp, vp, vp],
@@ -300,6 +301,19 @@ class Solver:
         self._check(lib().gks_adjoint_step(self._h, _ptr(U_n), _ptr(lam_np1), _ptr(lam_n),
                                            _ptr(ge) if ge is not None else None,
                                            _ptr(gm) if gm is not None else None, float(t)))
+        return lam_n
+
+    def adjoint_step_noalloc(self, U_n, lam_np1, lam_n, g_epsinv=None, g_muinv=None, t: float = 0.0):
+        """adjoint_step through gks_adjoint_step_noalloc (the library's static scratch, no device
+        allocation in the call): every output buffer is passed in."""
+        self._state(U_n, "U_n")
+        self._state(lam_np1, "lam_np1")
+        self._state(lam_n, "lam_n")
+        ge = self._cellmap(g_epsinv, "g_epsinv", self.torch.float64)
+        gm = self._cellmap(g_muinv, "g_muinv", self.torch.float64)
+        self._check(lib().gks_adjoint_step_noalloc(self._h, _ptr(U_n), _ptr(lam_np1), _ptr(lam_n),
+                                                   _ptr(ge) if ge is not None else None,
+                                                   _ptr(gm) if gm is not None else None, float(t)))
         return lam_n
 
     def energy(self, U) -> np.ndarray:
