@@ -170,7 +170,9 @@ __device__ __forceinline__ void limit_pair(T fp, T fq, T bp, T bq, T &dp, T &dq)
 // previous chunk has started, so at most two chunks' scalar registers are live.  12 suits most
 // kernels; a kernel whose scalar registers spill with 12 passes a smaller chunk (FP64 takes two
 // scalar registers per coefficient).
-template <typename P, int CH = 12, typename T, int NF, int NIN, typename Op>
+// HM = false: the operator's KH part is folded into K0 on the host (every face has 1/mu = 1), so
+// the KH products and their scaling are skipped and mH is unused.
+template <typename P, int CH = 12, bool HM = true, typename T, int NF, int NIN, typename Op>
 __device__ __forceinline__ void apply_op(const T (&w)[NIN], T mE, T mH, Op K, T (&phi)[NF])
 {
     T a[NF], e[NF], h[NF];
@@ -185,20 +187,22 @@ __device__ __forceinline__ void apply_op(const T (&w)[NIN], T mE, T mH, Op K, T 
     asm volatile("" : "+s"(K) : "v"(a[P::R0[P::N0 - 1]]));
 #pragma unroll
     for (int q = 0; q < P::NE; ++q) e[P::RE[q]] = fma(K->ke[q], w[P::CE[q]], e[P::RE[q]]);
+    if constexpr (HM) {
 #pragma unroll
-    for (int q = 0; q < P::NH; ++q) h[P::RH[q]] = fma(K->kh[q], w[P::CH[q]], h[P::RH[q]]);
+        for (int q = 0; q < P::NH; ++q) h[P::RH[q]] = fma(K->kh[q], w[P::CH[q]], h[P::RH[q]]);
+    }
 #pragma unroll
     for (int r = 0; r < NF; ++r) {
         T v = a[r];
         if ((P::EROWS >> r) & 1u) v = fma(mE, e[r], v);
-        if ((P::HROWS >> r) & 1u) v = fma(mH, h[r], v);
+        if (HM && ((P::HROWS >> r) & 1u)) v = fma(mH, h[r], v);
         phi[r] = v;
     }
 }
 
 // As apply_op, and also returns the material parts e = KE w and h = KH w (per output row; the
 // rows outside EROWS / HROWS are zero): phi = K0 w + mE e + mH h.
-template <typename P, int CH = 12, typename T, int NF, int NIN, typename Op>
+template <typename P, int CH = 12, bool HM = true, typename T, int NF, int NIN, typename Op>
 __device__ __forceinline__ void apply_op_parts(const T (&w)[NIN], T mE, T mH, Op K, T (&phi)[NF], T (&e)[NF],
                                                T (&h)[NF])
 {
@@ -213,19 +217,21 @@ __device__ __forceinline__ void apply_op_parts(const T (&w)[NIN], T mE, T mH, Op
     asm volatile("" : "+s"(K) : "v"(a[P::R0[P::N0 - 1]]));
 #pragma unroll
     for (int q = 0; q < P::NE; ++q) e[P::RE[q]] = fma(K->ke[q], w[P::CE[q]], e[P::RE[q]]);
+    if constexpr (HM) {
 #pragma unroll
-    for (int q = 0; q < P::NH; ++q) h[P::RH[q]] = fma(K->kh[q], w[P::CH[q]], h[P::RH[q]]);
+        for (int q = 0; q < P::NH; ++q) h[P::RH[q]] = fma(K->kh[q], w[P::CH[q]], h[P::RH[q]]);
+    }
 #pragma unroll
     for (int r = 0; r < NF; ++r) {
         T v = a[r];
         if ((P::EROWS >> r) & 1u) v = fma(mE, e[r], v);
-        if ((P::HROWS >> r) & 1u) v = fma(mH, h[r], v);
+        if (HM && ((P::HROWS >> r) & 1u)) v = fma(mH, h[r], v);
         phi[r] = v;
     }
 }
 
-// Transpose: wbar += K(mE, mH)^T abar.
-template <typename P, int CH = 12, typename T, int NF, int NIN, typename Op>
+// Transpose: wbar += K(mE, mH)^T abar (HM = false: KH folded into K0, as in apply_op).
+template <typename P, int CH = 12, bool HM = true, typename T, int NF, int NIN, typename Op>
 __device__ __forceinline__ void apply_op_transpose(const T (&abar)[NF], T mE, T mH, Op K, T (&wbar)[NIN])
 {
     T ae[NF], ah[NF];
@@ -242,8 +248,10 @@ __device__ __forceinline__ void apply_op_transpose(const T (&abar)[NF], T mE, T 
     asm volatile("" : "+s"(K) : "v"(wbar[P::C0[P::N0 - 1]]));
 #pragma unroll
     for (int q = 0; q < P::NE; ++q) wbar[P::CE[q]] = fma(K->ke[q], ae[P::RE[q]], wbar[P::CE[q]]);
+    if constexpr (HM) {
 #pragma unroll
-    for (int q = 0; q < P::NH; ++q) wbar[P::CH[q]] = fma(K->kh[q], ah[P::RH[q]], wbar[P::CH[q]]);
+        for (int q = 0; q < P::NH; ++q) wbar[P::CH[q]] = fma(K->kh[q], ah[P::RH[q]], wbar[P::CH[q]]);
+    }
 }
 
 // abar . (KE w) and abar . (KH w): derivatives of abar . phi with respect to mE and mH.

@@ -35,7 +35,9 @@ struct gks_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
     int ncu = 256;                  // compute units of the device
-    int32_t tile_y = 64;            // rows per wave tile (Cartesian 2D)
+    int32_t ntile_rows = 0;         // Cartesian 2D: tile rows of the step (entries of d_tiles)
+    int32_t tiles_per_band = 0;     // Cartesian 2D: entries per band (one band per XCD)
+    int32_t *d_tiles = nullptr;     // Cartesian 2D: [ntile_rows][4] tile rows in dispatch order
     int32_t tile_z = 64;            // planes per workgroup tile (Cartesian 3D)
     const void *epsinv = nullptr, *muinv = nullptr;
 
@@ -131,8 +133,31 @@ void fill_op(FaceOp<T, N0, NE, NH> &o, const double *k0, const double *ke, const
     for (int q = 0; q < NH; ++q) o.kh[q] = (T)(0.5 * kh[q]);
 }
 
+// K0 + KH on the pattern pf (K0 of the folded operator), from K0 and KH on the pattern p; every
+// entry of K0 and KH must have its place in pf.
+bool fold_kh(const Pattern &p, const Pattern &pf, const double *k0, const double *kh, double *out)
+{
+    auto place = [&](int r, int c) {
+        for (int q = 0; q < pf.n0; ++q)
+            if (pf.r0[q] == r && pf.c0[q] == c) return q;
+        return -1;
+    };
+    for (int q = 0; q < pf.n0; ++q) out[q] = 0.0;
+    for (int q = 0; q < p.n0; ++q) {
+        const int at = place(p.r0[q], p.c0[q]);
+        if (at < 0) return false;
+        out[at] += k0[q];
+    }
+    for (int q = 0; q < p.nH; ++q) {
+        const int at = place(p.rH[q], p.cH[q]);
+        if (at < 0) return false;
+        out[at] += kh[q];
+    }
+    return true;
+}
+
 template <typename T>
-void pack_ops(const gks_ctx *x, std::vector<char> &buf)
+bool pack_ops(const gks_ctx *x, std::vector<char> &buf)
 {
     if (x->kind == GKS_TET3D) {
         std::vector<FaceOpEM<T>> ops(1);
@@ -147,8 +172,16 @@ void pack_ops(const gks_ctx *x, std::vector<char> &buf)
         fill_op(ops[0], x->k0[0], x->ke[0], x->kh[0]);
         buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
     } else if (x->model == GKS_TM2D) {
-        std::vector<FaceOpTM<T>> ops(2);
-        for (int ax = 0; ax < 2; ++ax) fill_op(ops[ax], x->k0[ax], x->ke[ax], x->kh[ax]);
+        // x and y faces, then the same with the 1/mu part folded into K0 for vacuum 1/mu (the
+        // kernels pass the sum of the two cells' 1/mu, 2 in vacuum, against KH stored halved)
+        std::vector<FaceOpTM<T>> ops(4);
+        for (int ax = 0; ax < 2; ++ax) {
+            fill_op(ops[ax], x->k0[ax], x->ke[ax], x->kh[ax]);
+            double k0f[TM_N0];
+            const Pattern &p = pattern_cart(x->model, ax);
+            if (!fold_kh(p, p, x->k0[ax], x->kh[ax], k0f)) return false;
+            fill_op(ops[2 + ax], k0f, x->ke[ax], x->kh[ax]);
+        }
         buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
     } else if (x->model == GKS_TM2D_PHM) {
         std::vector<FaceOpTP<T>> ops(2);
@@ -159,18 +192,28 @@ void pack_ops(const gks_ctx *x, std::vector<char> &buf)
         for (int ax = 0; ax < 3; ++ax) fill_op(ops[ax], x->k0[ax], x->ke[ax], x->kh[ax]);
         buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
     } else {
+        // x-, y- and z-faces, then the same with the 1/mu part folded into K0 (vacuum 1/mu)
         std::vector<FaceOpEM<T>> ops(3);
-        for (int ax = 0; ax < 3; ++ax) fill_op(ops[ax], x->k0[ax], x->ke[ax], x->kh[ax]);
+        std::vector<FaceOpEMF<T>> folded(3);
+        for (int ax = 0; ax < 3; ++ax) {
+            fill_op(ops[ax], x->k0[ax], x->ke[ax], x->kh[ax]);
+            double k0f[EMF_N0];
+            if (!fold_kh(pattern_cart(x->model, ax), pattern_cart_em_folded(ax), x->k0[ax], x->kh[ax], k0f))
+                return false;
+            fill_op(folded[ax], k0f, x->ke[ax], x->kh[ax]);
+        }
         buf.assign((const char *)ops.data(), (const char *)(ops.data() + ops.size()));
+        buf.insert(buf.end(), (const char *)folded.data(), (const char *)(folded.data() + folded.size()));
     }
+    return true;
 }
 
 // Copies the face operators, rounded once to the storage precision, to device memory.
 gks_status upload_ops(gks_ctx *x)
 {
     std::vector<char> buf;
-    if (x->prec == GKS_FP64) pack_ops<double>(x, buf);
-    else pack_ops<float>(x, buf);
+    const bool ok = (x->prec == GKS_FP64) ? pack_ops<double>(x, buf) : pack_ops<float>(x, buf);
+    if (!ok) return fail(x, GKS_EINVAL, "internal: a 1/mu operator entry lies outside K0's pattern");
     if (hipMalloc(&x->d_ops, buf.size()) != hipSuccess) return fail(x, GKS_ENOMEM, "cannot allocate face operators");
     int e = hipMemcpy(x->d_ops, buf.data(), buf.size(), hipMemcpyHostToDevice);
     if (e) return hip_fail(x, e, "face operator upload");
@@ -179,18 +222,62 @@ gks_status upload_ops(gks_ctx *x)
 
 }  // namespace
 
-int gks::cart2d_pick_tile_y(int nx, int ny, int batch, int ncu, int precision)
+std::vector<int32_t> gks::cart2d_tile_table(int ny, int batch, int precision, int ntx, int32_t &tiles_per_band)
 {
+    // Workgroups reach the 8 XCDs round-robin (XCD = workgroup id mod 8) and each XCD starts its
+    // workgroups in id order.  The tile rows are therefore cut in 8 bands of the (batch item,
+    // row) sequence, one per XCD, each padded to the same length, and workgroup g works on band
+    // g mod 8, taking that band's tiles in the table's order.  Each band lists tall tiles first
+    // and short ones last: tall tiles re-read fewer halo rows (4 per tile), and the short ones
+    // end the band, so the last waves of an XCD are short and the drain of the launch is short.
+    // Measured on 4096^2 (fp32, per launch): uniform 14-row tiles 113.4 us; tall 32 / short 8
+    // rows with the short rows 0.3 of each band 110.8 us (fp64 203.3 us, as with 16-row tiles).
+    // A band whose last workgroup also ran the next band's first (tall) tiles cost up to 30%:
+    // the padding keeps every band on its own XCD.  Vertically adjacent tiles of a band march in
+    // opposite directions, so the halo rows they share are read at about the same time (the
+    // second read hits the L2); tiles never straddle two batch items.
+    int tall = 32, shrt = 8;
+    double frac = 0.3;
+    (void)precision;
 #ifdef GKS_FORCE_TILE_Y
-    return GKS_FORCE_TILE_Y;   // build-time override for tuning sweeps
+    tall = shrt = GKS_FORCE_TILE_Y;   // build-time override for tuning sweeps: uniform tiles
+    frac = 0.0;
 #endif
-    // Short tiles give many waves per SIMD to hide memory latency; adjacent tiles march in
-    // opposite directions and share their halo rows through the L2, so the extra halo reads of
-    // short tiles mostly hit the cache.  Measured on 4096^2 (12..24 rows within 3%): 14 rows in
-    // fp32 (114.0 us, against 115.7 at 16; also the best or within 1% for the PHM and limited
-    // kernels), 16 in fp64 (203.4 us, against 205.5 at 14).
-    (void)nx; (void)batch; (void)ncu;
-    return std::max(1, std::min(precision == GKS_FP32 ? 14 : 16, ny));
+    const int64_t total = (int64_t)ny * batch;
+    std::vector<std::vector<int32_t>> bands(NBANDS);
+    size_t most = 0;
+    for (int64_t band = 0; band < NBANDS; ++band) {
+        const int64_t r0 = total * band / NBANDS, r1 = total * (band + 1) / NBANDS;
+        const int64_t split = r1 - (int64_t)(frac * (double)(r1 - r0) + 0.5);
+        std::vector<int32_t> &tab = bands[band];
+        int64_t r = r0;
+        int k = 0;
+        while (r < r1) {
+            const int64_t b = r / ny, y = r % ny;
+            const int64_t h = r < split ? tall : shrt;
+            const int64_t lim = std::min(r < split ? split : r1, (b + 1) * ny);   // stay in the batch item
+            const int64_t e = std::min(r + h, lim);
+            tab.push_back((int32_t)b);
+            tab.push_back((int32_t)y);
+            tab.push_back((int32_t)(y + (e - r)));
+            tab.push_back(k++ & 1);
+            r = e;
+        }
+        most = std::max(most, tab.size() / 4);
+    }
+    // pad every band to the same number of tile rows, and that to whole workgroups of strips
+    size_t per = most;
+    while ((per * (size_t)ntx) % CART2D_WAVES_PER_BLOCK) ++per;
+    std::vector<int32_t> out;
+    for (auto &tab : bands) {
+        out.insert(out.end(), tab.begin(), tab.end());
+        for (size_t q = tab.size() / 4; q < per; ++q) {
+            const int32_t pad[4] = {-1, 0, 0, 0};   // no tile: its waves exit at once
+            out.insert(out.end(), pad, pad + 4);
+        }
+    }
+    tiles_per_band = (int32_t)per;
+    return out;
 }
 
 int gks::cart3d_pick_tile_z(int nx, int ny, int nz, int batch, int ncu, int precision, int nfields)
@@ -236,8 +323,8 @@ gks_status step_cart2d(gks_ctx *x, const void *Uin, void *Uout, double tn)
     a.batch = (int32_t)x->batch;
     for (int i = 0; i < 4; ++i) a.bc[i] = x->bc[i];
     a.ntx = (a.nx + cart2d_tile_x(x->prec) - 1) / cart2d_tile_x(x->prec);
-    a.tile_y = x->tile_y;
-    a.nty = (a.ny + a.tile_y - 1) / a.tile_y;
+    a.nty = x->tiles_per_band;
+    a.tiles = x->d_tiles;
     a.nfields = x->nfields;
     a.ops = x->d_ops;
     a.limiter = x->limiter;
@@ -691,8 +778,15 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, x->device) == hipSuccess && ncu > 0)
             x->ncu = ncu;
     }
-    if (x->kind == GKS_CART2D)
-        x->tile_y = cart2d_pick_tile_y((int)x->n[0], (int)x->n[1], (int)x->batch, x->ncu, x->prec);
+    if (x->kind == GKS_CART2D) {
+        const int ntx = (int)((x->n[0] + cart2d_tile_x(x->prec) - 1) / cart2d_tile_x(x->prec));
+        const std::vector<int32_t> tab = cart2d_tile_table((int)x->n[1], (int)x->batch, x->prec, ntx, x->tiles_per_band);
+        x->ntile_rows = (int32_t)(tab.size() / 4);
+        if (hipMalloc((void **)&x->d_tiles, tab.size() * sizeof(int32_t)) != hipSuccess)
+            return bail(fail(x, GKS_ENOMEM, "cannot allocate the tile table"));
+        const int e = hipMemcpy(x->d_tiles, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e) return bail(hip_fail(x, e, "tile table upload"));
+    }
     if (x->kind == GKS_CART2D && x->model == GKS_TM2D) {
         // the device address of the allocation-free adjoint's static scratch (once per device)
         x->static_scratch_err = adjoint_static_scratch(&x->static_scratch);
@@ -724,6 +818,7 @@ extern "C" gks_status gks_destroy(gks_ctx *ctx)
 {
     if (!ctx) return GKS_OK;
     if (ctx->d_ops) hipFree(ctx->d_ops);
+    if (ctx->d_tiles) hipFree(ctx->d_tiles);
     if (ctx->pingpong) hipFree(ctx->pingpong);
     if (ctx->d_partial) hipFree(ctx->d_partial);
     if (ctx->d_out) hipFree(ctx->d_out);

@@ -17,12 +17,14 @@ struct Pattern {
     const uint8_t *r0, *c0, *rE, *cE, *rH, *cH;
 };
 const Pattern &pattern_cart(int model, int axis);
+const Pattern &pattern_cart_em_folded(int axis);
 const Pattern &pattern_tri(int model);
 
 constexpr int TM_N0 = 24, TM_NE = 6, TM_NH = 4;
 constexpr int TP_N0 = 42, TP_NE = 8, TP_NH = 16;
 constexpr int EM_N0 = 80, EM_NE = 12, EM_NH = 12;
 constexpr int EP_N0 = 168, EP_NE = 36, EP_NH = 36;
+constexpr int EMF_N0 = 84;   // EM with the 1/mu part folded into K0 (vacuum 1/mu)
 
 void flux_coefficients(double dt, double tau, double C[5]);
 // Face operator of an axis-aligned Cartesian face (normal +e_axis), global-frame inputs whose
@@ -48,6 +50,7 @@ template <typename T> using FaceOpTM = FaceOp<T, TM_N0, TM_NE, TM_NH>;
 template <typename T> using FaceOpTP = FaceOp<T, TP_N0, TP_NE, TP_NH>;
 template <typename T> using FaceOpEM = FaceOp<T, EM_N0, EM_NE, EM_NH>;
 template <typename T> using FaceOpEP = FaceOp<T, EP_N0, EP_NE, EP_NH>;
+template <typename T> using FaceOpEMF = FaceOp<T, EMF_N0, EM_NE, EM_NH>;
 
 
 
@@ -61,8 +64,9 @@ struct Cart2DArgs {
     int32_t nx, ny;
     int32_t batch;
     int32_t bc[4];        // x-, x+, y-, y+
-    int32_t ntx, nty;     // tiles per row / column
-    int32_t tile_y;       // rows per tile
+    int32_t ntx, nty;     // strips per row; tile rows per band (one band per XCD)
+    const int32_t *tiles; // device [NBANDS][nty][4]: batch item (-1: none), first row, end row,
+                          // march downwards
     int32_t nfields;      // 3: (Ez, Hx, Hy); 4: (Ez, Hx, Hy, psi)
     const void *ops;      // device: x-face and y-face operators (FaceOpTM<T> or FaceOpTP<T>)
     int32_t src_row, src_col; // one point source applied inside the step (src_row < 0: none)
@@ -212,10 +216,11 @@ int cart3d_tile_y(int precision, int nfields);
 int cart3d_pick_tile_z(int nx, int ny, int nz, int batch, int ncu, int precision, int nfields);
 // Columns written per wave strip (depends on the element size).
 int cart2d_tile_x(int precision);
-// Rows per wave tile for an nx x ny x batch grid on a device with ncu compute units: the
-// kernel is throughput bound per compute unit, so the step time follows the largest number of
-// 4-wave workgroups any unit receives times the rows each wave marches (plus its 4 halo rows).
-int cart2d_pick_tile_y(int nx, int ny, int batch, int ncu, int precision);
+// Tile rows of the 2D step, four ints each (batch item or -1, first row, end row, march
+// downwards), NBANDS bands of tiles_per_band entries, one band per XCD: see gks_host.cpp.
+constexpr int NBANDS = 8;
+constexpr int CART2D_WAVES_PER_BLOCK = 4;
+std::vector<int32_t> cart2d_tile_table(int ny, int batch, int precision, int ntx, int32_t &tiles_per_band);
 
 // Energy: partial sums per (batch, block) then a fixed-order final sum; all FP64.
 // Fields [0, nE) are E (weight eps), [nE, nE + nH) are H (weight mu), the rest potentials (1).

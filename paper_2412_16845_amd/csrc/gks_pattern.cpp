@@ -18,6 +18,11 @@ const Pattern &pattern_cart(int model, int axis)
     return axis == 0 ? make<PatEMx>() : (axis == 1 ? make<PatEMy>() : make<PatEMz>());
 }
 
+const Pattern &pattern_cart_em_folded(int axis)
+{
+    return axis == 0 ? make<PatEMxF>() : (axis == 1 ? make<PatEMyF>() : make<PatEMzF>());
+}
+
 const Pattern &pattern_tet() { return make<PatTet>(); }
 
 const Pattern &pattern_tri(int model) { return model == GKS_TM2D_PHM ? make<PatTriP>() : make<PatTri>(); }

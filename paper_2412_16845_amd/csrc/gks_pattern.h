@@ -170,6 +170,50 @@ struct PatTri {
     static constexpr uint32_t HROWS = 0x1u;
 };
 
+// The EM tables with the 1/mu part folded into K0, for vacuum 1/mu: K0's entries, then those of
+// KH that K0 does not have (the host adds KH onto K0 there); KE unchanged.
+struct PatEMxF {
+    static constexpr int N0 = 84;
+    static constexpr uint8_t R0[84] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 1, 1, 2, 2};
+    static constexpr uint8_t C0[84] = {0, 6, 12, 20, 22, 23, 25, 28, 29, 30, 38, 40, 41, 43, 46, 47, 1, 5, 7, 11, 13, 17, 21, 27, 31, 35, 39, 45, 2, 4, 8, 10, 14, 16, 21, 27, 32, 34, 39, 45, 3, 9, 15, 19, 20, 23, 25, 26, 28, 33, 37, 38, 41, 43, 44, 46, 2, 4, 8, 10, 14, 16, 18, 24, 32, 34, 36, 42, 1, 5, 7, 11, 13, 17, 18, 24, 31, 35, 36, 42, 18, 36, 24, 42};
+    static constexpr int NE = PatEMx::NE;
+    static constexpr uint8_t RE[12] = {4, 4, 4, 4, 4, 4, 5, 5, 5, 5, 5, 5};
+    static constexpr uint8_t CE[12] = {14, 16, 21, 32, 34, 39, 13, 17, 27, 31, 35, 45};
+    static constexpr uint32_t EROWS = PatEMx::EROWS;
+    static constexpr int NH = 0;
+    static constexpr uint8_t RH[1] = {0};
+    static constexpr uint8_t CH[1] = {0};
+    static constexpr uint32_t HROWS = 0;
+};
+
+struct PatEMyF {
+    static constexpr int N0 = 84;
+    static constexpr uint8_t R0[84] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 0, 0, 2, 2};
+    static constexpr uint8_t C0[84] = {0, 5, 6, 11, 12, 17, 22, 28, 30, 35, 40, 46, 1, 7, 13, 20, 21, 23, 24, 27, 29, 31, 38, 39, 41, 42, 45, 47, 2, 3, 8, 9, 14, 15, 22, 28, 32, 33, 40, 46, 2, 3, 8, 9, 14, 15, 19, 25, 32, 33, 37, 43, 4, 10, 16, 18, 20, 23, 24, 26, 27, 34, 36, 38, 41, 42, 44, 45, 0, 5, 6, 11, 12, 17, 19, 25, 30, 35, 37, 43, 19, 37, 25, 43};
+    static constexpr int NE = PatEMy::NE;
+    static constexpr uint8_t RE[12] = {3, 3, 3, 3, 3, 3, 5, 5, 5, 5, 5, 5};
+    static constexpr uint8_t CE[12] = {14, 15, 22, 32, 33, 40, 12, 17, 28, 30, 35, 46};
+    static constexpr uint32_t EROWS = PatEMy::EROWS;
+    static constexpr int NH = 0;
+    static constexpr uint8_t RH[1] = {0};
+    static constexpr uint8_t CH[1] = {0};
+    static constexpr uint32_t HROWS = 0;
+};
+
+struct PatEMzF {
+    static constexpr int N0 = 84;
+    static constexpr uint8_t R0[84] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 5, 0, 0, 1, 1};
+    static constexpr uint8_t C0[84] = {0, 4, 6, 10, 12, 16, 23, 29, 30, 34, 41, 47, 1, 3, 7, 9, 13, 15, 23, 29, 31, 33, 41, 47, 2, 8, 14, 19, 21, 22, 24, 27, 28, 32, 37, 39, 40, 42, 45, 46, 1, 3, 7, 9, 13, 15, 20, 26, 31, 33, 38, 44, 0, 4, 6, 10, 12, 16, 20, 26, 30, 34, 38, 44, 5, 11, 17, 18, 19, 22, 24, 25, 27, 35, 36, 37, 40, 42, 43, 45, 20, 38, 26, 44};
+    static constexpr int NE = PatEMz::NE;
+    static constexpr uint8_t RE[12] = {3, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 4};
+    static constexpr uint8_t CE[12] = {13, 15, 23, 31, 33, 41, 12, 16, 29, 30, 34, 47};
+    static constexpr uint32_t EROWS = PatEMz::EROWS;
+    static constexpr int NH = 0;
+    static constexpr uint8_t RH[1] = {0};
+    static constexpr uint8_t CH[1] = {0};
+    static constexpr uint32_t HROWS = 0;
+};
+
 // Tetrahedral faces: face-frame inputs [Ul Ur s1l s2l s3l s1r s2r s3r] x (Ex .. Hz) have the
 // sparsity of the Cartesian x-face table.
 using PatTet = PatEMx;
@@ -189,5 +233,6 @@ static_assert(PatEPz::N0 == EP_N0 && PatEPz::NE == EP_NE && PatEPz::NH == EP_NH,
 static_assert(PatEMx::N0 == EM_N0 && PatEMx::NE == EM_NE && PatEMx::NH == EM_NH, "EM table size");
 static_assert(PatEMy::N0 == EM_N0 && PatEMy::NE == EM_NE && PatEMy::NH == EM_NH, "EM table size");
 static_assert(PatEMz::N0 == EM_N0 && PatEMz::NE == EM_NE && PatEMz::NH == EM_NH, "EM table size");
+static_assert(PatEMxF::N0 == EMF_N0 && PatEMyF::N0 == EMF_N0 && PatEMzF::N0 == EMF_N0, "folded EM table size");
 
 }  // namespace gks

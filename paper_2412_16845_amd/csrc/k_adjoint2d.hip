@@ -85,8 +85,12 @@ __device__ __forceinline__ bool row_is_nr(int gy, int ny, int bclo, int bchi)
     return (gy < 0 && bclo == GKS_BC_NONREFLECT) || (gy >= ny && bchi == GKS_BC_NONREFLECT);
 }
 
-template <typename T, bool HAS_EPS, bool HAS_MU, bool BND>
+// HM = false (vacuum 1/mu and no 1/mu gradient asked for): the operators' 1/mu parts are
+// folded into K0 on the host (the second pair of operators), which drops their products from
+// the forward and the transposed evaluation of every face.
+template <typename T, bool HAS_EPS, bool HAS_MU, bool HM, bool BND>
 struct AdjStrip {
+    static constexpr int OPS0 = HM ? 0 : 2;
     const Cart2DAdjArgs<T> &a;
     Rsrc rU, rL, rE, rM;
     uint32_t fbytes;
@@ -147,14 +151,14 @@ struct AdjStrip {
                                          T (&wbar)[18], T &sE, T &sH) const
     {
         T e[3], h[3];
-        apply_op_parts<P, ADJ_CH>(w, mEs, mHs, K, phi, e, h);
+        apply_op_parts<P, ADJ_CH, HM>(w, mEs, mHs, K, phi, e, h);
 #pragma unroll
         for (int q = 0; q < 18; ++q) wbar[q] = T(0);
         // reload the coefficients for the transposed pass rather than keeping them live
         asm volatile("" : "+s"(K) : "v"(phi[2]));
-        apply_op_transpose<P, ADJ_CH>(ad, mEs, mHs, K, wbar);
+        apply_op_transpose<P, ADJ_CH, HM>(ad, mEs, mHs, K, wbar);
         sE = ad[0] * e[0] + ad[1] * e[1] + ad[2] * e[2];
-        sH = ad[0] * h[0] + ad[1] * h[1] + ad[2] * h[2];
+        sH = HM ? ad[0] * h[0] + ad[1] * h[1] + ad[2] * h[2] : T(0);
     }
 
     // Step i of the march (head row q = qs + i); I = i mod 4 selects the register slots:
@@ -206,7 +210,7 @@ struct AdjStrip {
             }
             const T mEs = P1.mE + from_right(P1.mE), mHs = P1.mH + from_right(P1.mH);
             T phi[3], wbar[18], sE, sH;
-            face<PatTMx>(w, mEs, mHs, ad, scalar_ptr_after(a.ops, G1[5]), phi, wbar, sE, sH);
+            face<PatTMx>(w, mEs, mHs, ad, scalar_ptr_after(a.ops + OPS0, G1[5]), phi, wbar, sE, sH);
             // the left cell (this lane) and the right cell (the next lane, by DPP); a
             // non-reflecting ghost side receives nothing: the sending lane zeroes the right
             // cell's share, so the moves need no select on the receiving side
@@ -240,7 +244,7 @@ struct AdjStrip {
             ad[1] = P2.mH * P2.l[1] - P1.mH * P1.l[1];
             ad[2] = P2.mH * P2.l[2] - P1.mH * P1.l[2];
             T phi[3], wbar[18], sE, sH;
-            face<PatTMy>(w, P2.mE + P1.mE, P2.mH + P1.mH, ad, scalar_ptr_after(a.ops + 1, G1[2]), phi, wbar, sE, sH);
+            face<PatTMy>(w, P2.mE + P1.mE, P2.mH + P1.mH, ad, scalar_ptr_after(a.ops + OPS0 + 1, G1[2]), phi, wbar, sE, sH);
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
                 A2.ub[f] += zl ? T(0) : wbar[f];
@@ -266,7 +270,7 @@ struct AdjStrip {
             for (int f = 0; f < 3; ++f)
                 psi[f] = lf[f] - A3.ub[f] - from_left(A3.dxb[f]) + from_right(A3.dxb[f]) - A4.dyb[f] + A2.dyb[f];
             const double gE = -(double)lf[0] * (double)A3.div[0] - (double)A3.sE;
-            const double gH = -((double)lf[1] * (double)A3.div[1] + (double)lf[2] * (double)A3.div[2]) - (double)A3.sH;
+            const double gH = HM ? -((double)lf[1] * (double)A3.div[1] + (double)lf[2] * (double)A3.div[2]) - (double)A3.sH : 0.0;
             const bool ry = r >= 0 && r < a.ny;
             const bool own_y = (r >= -2 && r <= a.ny + 1) && ((r >= R0 && r < R1 && ry) || (!ry && (first_y || last_y)));
             if (own_x && own_y) {
@@ -315,7 +319,7 @@ struct AdjStrip {
     }
 };
 
-template <typename T, bool HAS_EPS, bool HAS_MU>
+template <typename T, bool HAS_EPS, bool HAS_MU, bool HM>
 __global__ __launch_bounds__(ADJ_MARCH_BLOCK) void adj2d_march_kernel(Cart2DAdjArgs<T> a, T *padpsi, double *padg, int32_t ntx,
                                                                 int32_t nty)
 {
@@ -340,7 +344,7 @@ __global__ __launch_bounds__(ADJ_MARCH_BLOCK) void adj2d_march_kernel(Cart2DAdjA
     const bool interior = x0 >= 0 && x0 + WAVE - 1 <= a.nx - 1 && R0 - 4 >= 0 && R1 + 2 <= a.ny - 1;
     auto go = [&](auto bnd) {
         constexpr bool BND = decltype(bnd)::value;
-        AdjStrip<T, HAS_EPS, HAS_MU, BND> s{a, rU, rL, rE, rM, fbytes, lane, x, x0};
+        AdjStrip<T, HAS_EPS, HAS_MU, HM, BND> s{a, rU, rL, rE, rM, fbytes, lane, x, x0};
         bool mx, nrx;
         const int sx = map_axis(x, a.nx, a.bc[0], a.bc[1], mx, nrx);
         s.vx = (uint32_t)sx * (uint32_t)sizeof(T);
@@ -483,13 +487,18 @@ int launch_cart2d_adjoint(const Cart2DAdjArgs<T> &a, T *padpsi, double *padg, vo
     const int64_t waves = (int64_t)ntx * nty * a.batch;
     dim3 grid((unsigned)((waves + ADJ_MARCH_BLOCK / WAVE - 1) / (ADJ_MARCH_BLOCK / WAVE)));
     if (a.epsinv && a.muinv)
-        hipLaunchKernelGGL((adj2d_march_kernel<T, true, true>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
-    else if (a.epsinv)
-        hipLaunchKernelGGL((adj2d_march_kernel<T, true, false>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
+        hipLaunchKernelGGL((adj2d_march_kernel<T, true, true, true>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
     else if (a.muinv)
-        hipLaunchKernelGGL((adj2d_march_kernel<T, false, true>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
+        hipLaunchKernelGGL((adj2d_march_kernel<T, false, true, true>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
+    else if (a.g_muinv) {   // vacuum 1/mu, but its gradient is asked for
+        if (a.epsinv)
+            hipLaunchKernelGGL((adj2d_march_kernel<T, true, false, true>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
+        else
+            hipLaunchKernelGGL((adj2d_march_kernel<T, false, false, true>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
+    } else if (a.epsinv)
+        hipLaunchKernelGGL((adj2d_march_kernel<T, true, false, false>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
     else
-        hipLaunchKernelGGL((adj2d_march_kernel<T, false, false>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
+        hipLaunchKernelGGL((adj2d_march_kernel<T, false, false, false>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
     const int64_t nband = Band2D(a.nx, a.ny).count();
     dim3 gband((unsigned)((nband + ADJ_BLOCK - 1) / ADJ_BLOCK), a.batch);
     hipLaunchKernelGGL(adj2d_fold_kernel<T>, gband, dim3(ADJ_BLOCK), 0, s, a, (const T *)padpsi, (const double *)padg);

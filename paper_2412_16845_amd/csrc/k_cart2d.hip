@@ -5,8 +5,8 @@
 //
 // One wavefront owns a strip of 64 lanes x NC adjacent columns (NC = 2 for FP32, 1 for FP64,
 // so that every lane moves 8 bytes per field and row); the two outermost columns on each side
-// are halo, the rest are written.  The wave marches a tile of rows upwards (the tile height is
-// chosen by the host to balance the workgroups over the compute units).  Each field value is
+// are halo, the rest are written.  The wave marches a tile of rows up or down (the host's tile
+// table gives each tile row's batch item, rows and direction, in dispatch order).  Each field value is
 // loaded once per strip row; neighbours along x come from the lane itself or from the adjacent
 // lanes through DPP moves, so no LDS and no barriers are needed.  Per row the wave:
 //   1. issues the loads of the row PF rows ahead (structure-of-arrays, 512 contiguous bytes
@@ -88,6 +88,10 @@ struct Strip2D {
     // coefficient chunk of the face operators: 8 for the fp64 PHM kernel (4096^2: 274.2 ->
     // 269.8 us), 12 elsewhere (the fastest there)
     static constexpr int CH2 = (sizeof(T) == 8 && NF == 4) ? 8 : 12;
+    // vacuum 1/mu with the TM fields: the host folds the operators' 1/mu parts into K0 (the
+    // second pair of operators), which saves five multiply-adds per face
+    static constexpr bool HM = HAS_MU || NF != 3;
+    static constexpr int OPS0 = HM ? 0 : 2;
     const Cart2DArgs<T> &a;
     Rsrc rU, rE, rM, rO;   // this batch item's fields, 1/eps, 1/mu, output fields
     uint32_t fbytes;       // bytes per field array
@@ -150,7 +154,7 @@ struct Strip2D {
         const int q = qs + sd * i;
         const OpT *ops = (const OpT *)a.ops;
         // coefficients of the horizontal faces: loaded after the previous row's divergence
-        const auto opy = scalar_ptr_after(ops + 1, fyP[0][0]);
+        const auto opy = scalar_ptr_after(ops + OPS0 + 1, fyP[0][0]);
         // rows beyond the tile and its halo are not needed: re-read the last halo row instead
         // (already cached), which keeps the load unconditional so the loads in flight are
         // counted exactly
@@ -207,11 +211,11 @@ struct Strip2D {
             }
             // face material: the two cells' values (a ghost reads its interior cell); the
             // operator applies their mean
-            apply_op<typename FS::PY, CH2>(w, RL.mE[k] + RR.mE[k], RL.mH[k] + RR.mH[k], opy, fyN[k]);
+            apply_op<typename FS::PY, CH2, HM>(w, RL.mE[k] + RR.mE[k], HM ? RL.mH[k] + RR.mH[k] : T(2), opy, fyN[k]);
         }
         if (i < 2) return;
         // coefficients of the vertical faces: loaded once the horizontal faces are done
-        const auto opx = scalar_ptr_after(ops, fyN[NC - 1][2]);
+        const auto opx = scalar_ptr_after(ops + OPS0, fyN[NC - 1][2]);
 
         // vertical faces right of each column, row q-2s: inputs [UL UR dxL dyL dxR dyR] x fields
         T ul[NC][NF], dl[NC][2 * NF];
@@ -239,8 +243,8 @@ struct Strip2D {
                 v[5 * NF + f] = (k < last) ? dl[kr][NF + f] : from_right(dl[0][NF + f]);
             }
             const T mEr = (k < last) ? Rs.mE[kr] : from_right(Rs.mE[0]);
-            const T mHr = (k < last) ? Rs.mH[kr] : from_right(Rs.mH[0]);
-            apply_op<typename FS::PX, CH2>(v, Rs.mE[k] + mEr, Rs.mH[k] + mHr, opx, fx[k]);
+            const T mHr = !HM ? T(1) : (k < last) ? Rs.mH[kr] : from_right(Rs.mH[0]);
+            apply_op<typename FS::PX, CH2, HM>(v, Rs.mE[k] + mEr, Rs.mH[k] + mHr, opx, fx[k]);
         }
 
         // update: the face fluxes (FP32 in FP32 mode) are widened to FP64, their divergence is
@@ -342,13 +346,18 @@ __global__ __launch_bounds__(STEP2D_BLOCK) void cart2d_step_kernel(Cart2DArgs<T>
     const int lane = threadIdx.x & (WAVE - 1);
     // the wave's index inside the block is uniform: say so, so that everything derived from it
     // (tile, batch item, buffer resources, row offsets) lives in scalar registers
-    const int wave = xcd_logical_block() * (STEP2D_BLOCK / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    const int per_b = a.ntx * a.nty;
-    const int b = wave / per_b;
-    if (b >= a.batch) return;
-    const int rem = wave - b * per_b;
-    const int ty = rem / a.ntx;
-    const int tx = rem - ty * a.ntx;
+    // workgroup g runs on XCD g mod 8 and works on that XCD's band of tile rows, in order
+    const int band = blockIdx.x % NBANDS;
+    const int wave = (blockIdx.x / NBANDS) * (STEP2D_BLOCK / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int tl = wave / a.ntx;   // tile row within the band
+    if (tl >= a.nty) return;
+    const int tx = wave - tl * a.ntx;
+    const int t = band * a.nty + tl;
+    const int b = __builtin_amdgcn_readfirstlane(a.tiles[4 * t]);
+    if (b < 0) return;   // padding of a shorter band
+    const int y0 = __builtin_amdgcn_readfirstlane(a.tiles[4 * t + 1]);
+    const int y1 = __builtin_amdgcn_readfirstlane(a.tiles[4 * t + 2]);   // rows [y0, y1) are written
+    const bool down = __builtin_amdgcn_readfirstlane(a.tiles[4 * t + 3]) != 0;
 
     const int64_t ncell = (int64_t)a.nx * a.ny;
     const uint32_t fbytes = (uint32_t)(ncell * (int64_t)sizeof(T));
@@ -359,8 +368,6 @@ __global__ __launch_bounds__(STEP2D_BLOCK) void cart2d_step_kernel(Cart2DArgs<T>
 
     const int x0 = tx * out_cols<T>() - HALO;
     const int gx0 = x0 + NC * lane;
-    const int y0 = ty * a.tile_y;
-    const int y1 = min(y0 + a.tile_y, a.ny);   // rows [y0, y1) are written
     const uint32_t vlane = (uint32_t)(NC * lane) * (uint32_t)sizeof(T);
 
     const bool interior = x0 >= 0 && x0 + WAVE * NC - 1 <= a.nx - 1 && y0 - 2 >= 0 && y1 + 1 <= a.ny - 1;
@@ -375,7 +382,7 @@ __global__ __launch_bounds__(STEP2D_BLOCK) void cart2d_step_kernel(Cart2DArgs<T>
         }
         s.y0 = y0;
         s.y1 = y1;
-        s.run(ty & 1);
+        s.run(down);
     } else {
         Strip2D<T, NC, NF, HAS_EPS, HAS_MU, true, LIM> s{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0};
 #pragma unroll
@@ -389,16 +396,17 @@ __global__ __launch_bounds__(STEP2D_BLOCK) void cart2d_step_kernel(Cart2DArgs<T>
         }
         s.y0 = y0;
         s.y1 = y1;
-        s.run(ty & 1);
+        s.run(down);
     }
 }
 
 template <typename T>
 int launch_cart2d_step(const Cart2DArgs<T> &a, void *stream)
 {
-    const int waves = a.ntx * a.nty * a.batch;
+    static_assert(STEP2D_BLOCK / WAVE == CART2D_WAVES_PER_BLOCK, "the tile table pads bands to whole workgroups");
+    const int waves = a.ntx * a.nty;   // per band: a whole number of workgroups (padded by the host)
     const int wpb = STEP2D_BLOCK / WAVE;
-    dim3 grid((waves + wpb - 1) / wpb), block(STEP2D_BLOCK);
+    dim3 grid(NBANDS * ((waves + wpb - 1) / wpb)), block(STEP2D_BLOCK);
     hipStream_t s = (hipStream_t)stream;
     if (a.nfields == 4) {   // TM with psi (never limited: the host refuses that combination)
         if (a.limiter) return (int)hipErrorInvalidValue;

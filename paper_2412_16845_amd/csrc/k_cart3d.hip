@@ -53,17 +53,27 @@ constexpr uint32_t ODD_Z = (1u << 0) | (1u << 1) | (1u << 5) | (1u << 6);
 
 // Face operators of the two field sets.
 template <int NF> struct Fields3D;
+// PXF.. and OpF: the operators with the 1/mu part folded into K0, stored after the three plain
+// ones (six fields only; the eight-field kernel always applies KH).
 template <> struct Fields3D<6> {
     using PX = PatEMx;
     using PY = PatEMy;
     using PZ = PatEMz;
+    using PXF = PatEMxF;
+    using PYF = PatEMyF;
+    using PZF = PatEMzF;
     template <typename T> using Op = FaceOpEM<T>;
+    template <typename T> using OpF = FaceOpEMF<T>;
 };
 template <> struct Fields3D<8> {
     using PX = PatEPx;
     using PY = PatEPy;
     using PZ = PatEPz;
+    using PXF = PatEPx;
+    using PYF = PatEPy;
+    using PZF = PatEPz;
     template <typename T> using Op = FaceOpEP<T>;
+    template <typename T> using OpF = FaceOpEP<T>;
 };
 
 template <typename T, int NF>
@@ -111,6 +121,18 @@ struct March3D {
     static constexpr int R = rows3d<T, NF>();
     using OpT = typename Fields3D<NF>::template Op<T>;
     using Plane = Plane3<T, NF>;
+    // vacuum 1/mu with the six fields: the folded operators, which save the KH products (about
+    // ten multiply-adds per face)
+    static constexpr bool HM = HAS_MU || NF != 6;
+    using FS = Fields3D<NF>;
+    using PX_ = typename std::conditional<HM, typename FS::PX, typename FS::PXF>::type;
+    using PY_ = typename std::conditional<HM, typename FS::PY, typename FS::PYF>::type;
+    using PZ_ = typename std::conditional<HM, typename FS::PZ, typename FS::PZF>::type;
+    using OpU = typename std::conditional<HM, typename FS::template Op<T>, typename FS::template OpF<T>>::type;
+    __device__ __forceinline__ const OpU *opsets() const
+    {
+        return HM ? (const OpU *)a.ops : (const OpU *)((const char *)a.ops + 3 * sizeof(OpT));
+    }
     const Cart3DArgs<T> &a;
     Lds3<T, NF> &s;
     Rsrc rU, rE, rM, rO;
@@ -160,7 +182,7 @@ struct March3D {
     __device__ __forceinline__ void step(int q, Plane &A, Plane &B, Plane &C, Plane &D, T (&Gp)[3 * NF],
                                          T (&G)[3 * NF], double (&acc)[NF]) const
     {
-        const OpT *ops = (const OpT *)a.ops;
+        const OpU *ops = opsets();
         // plane q+2 (beyond the range: re-read the last halo plane, already cached, so that the
         // load stays unconditional)
         load(min(q + 2, z1 + 1), D);
@@ -225,7 +247,7 @@ struct March3D {
                     w[6 * NF + f] = G[f];
                     w[7 * NF + f] = G[NF + f];
                 }
-                apply_op<typename Fields3D<NF>::PZ, CH3<T, NF>()>(w, A.mE + B.mE, A.mH + B.mH, opz, Z);
+                apply_op<PZ_, CH3<T, NF>(), HM>(w, A.mE + B.mE, A.mH + B.mH, opz, Z);
             } else {
                 const bool zl = zlu || (BXY && nr_c), zr = zru || (BXY && nr_c);
                 T w[8 * NF];
@@ -240,7 +262,7 @@ struct March3D {
                     w[6 * NF + f] = zr ? T(0) : G[f];
                     w[7 * NF + f] = zr ? T(0) : G[NF + f];
                 }
-                apply_op<typename Fields3D<NF>::PZ, CH3<T, NF>()>(w, A.mE + B.mE, A.mH + B.mH, opz, Z);
+                apply_op<PZ_, CH3<T, NF>(), HM>(w, A.mE + B.mE, A.mH + B.mH, opz, Z);
             }
             if (q - 1 >= z0) {
                 const uint32_t so = (uint32_t)(q - 1) * pbytes;
@@ -289,8 +311,8 @@ struct March3D {
                 w[6 * NF + f] = s.g[f][rowp][lane];
                 w[7 * NF + f] = s.g[2 * NF + f][rowp][lane];
             }
-            apply_op<typename Fields3D<NF>::PY, CH3<T, NF>()>(w, B.mE + s.g[3 * NF][rowp][lane], B.mH + s.g[3 * NF + 1][rowp][lane],
-                                                opy, py);
+            apply_op<PY_, CH3<T, NF>(), HM>(w, B.mE + s.g[3 * NF][rowp][lane], B.mH + s.g[3 * NF + 1][rowp][lane],
+                                            opy, py);
 #pragma unroll
             for (int f = 0; f < NF; ++f) s.p[f][row][lane] = py[f];
         }
@@ -309,7 +331,7 @@ struct March3D {
                 w[6 * NF + f] = from_right(G[NF + f]);
                 w[7 * NF + f] = from_right(G[2 * NF + f]);
             }
-            apply_op<typename Fields3D<NF>::PX, CH3<T, NF>()>(w, B.mE + from_right(B.mE), B.mH + from_right(B.mH), opx, px);
+            apply_op<PX_, CH3<T, NF>(), HM>(w, B.mE + from_right(B.mE), HM ? B.mH + from_right(B.mH) : T(2), opx, px);
         }
         if constexpr (NU == 2) {
             // share the fields of plane q+1 in the other buffer (its last readers, in the
