@@ -526,6 +526,7 @@ gks_status adjoint_cart2d(gks_ctx *x, const void *Un, const void *lam_np1, void 
     a.ny = (int32_t)x->n[1];
     a.batch = (int32_t)x->batch;
     for (int i = 0; i < 4; ++i) a.bc[i] = x->bc[i];
+    a.ncu = x->ncu;
     a.ops = (const FaceOpTM<T> *)x->d_ops;
     int e = launch_cart2d_adjoint<T>(a, padpsi, padg, x->stream);
     if (e) return hip_fail(x, e, "adjoint launch");

@@ -184,6 +184,7 @@ struct Cart2DAdjArgs {
     const T *muinv;       // nullable: vacuum
     int32_t nx, ny, batch;
     int32_t bc[4];
+    int32_t ncu;              // compute units of the device (sizes the march's tiles)
     const FaceOpTM<T> *ops;   // device: x-face and y-face operators
 };
 

@@ -39,7 +39,28 @@ constexpr int ADJ_CH = 4;
 // workgroup lets a freed slot take the next tile at once (4-wave workgroups wait for four free
 // slots on one compute unit).  Measured on 1024^2 x 8: 231 vs 241 us (fp32), 503 vs 552 us (fp64).
 constexpr int ADJ_MARCH_BLOCK = 64;
-constexpr int ADJ_TILE_Y = 24;   // rows per wave tile (1024^2 x 8: 221 us, against 231 at 16, 236 at 32)
+// Rows per wave tile: a wave marches its tile's rows plus five (the halo and the pipeline), and
+// all tiles are alike, so the march takes about ceil(tiles / wave slots) x (rows + 5) row steps,
+// the wave slots being the device's compute units times the waves one unit holds of the kernel
+// variant.  The height is picked in [16, 40] to minimise that (a last round that is almost empty
+// costs a whole tile's time: 1024^2 x 8 in fp32, three waves per SIMD, had 6192 tiles of 24
+// rows for 3072 slots).
+int adj_tile_rows(int nx, int ny, int batch, int64_t slots)
+{
+    const int64_t ntx = (nx + (WAVE - 4) - 1) / (WAVE - 4);
+    int pick = 24;
+    double best = 1e300;
+    for (int ty = 16; ty <= 40; ++ty) {
+        const int64_t tiles = ntx * ((ny + ty - 1) / ty) * batch;
+        const int64_t rounds = (tiles + slots - 1) / std::max<int64_t>(slots, 1);
+        const double cost = (double)rounds * (ty + 5);
+        if (cost < best) {
+            best = cost;
+            pick = ty;
+        }
+    }
+    return pick;
+}
 
 // The ghost positions of an nx x ny grid: the two layers of positions (i, j) around it,
 // -2 <= i <= nx+1 and -2 <= j <= ny+1 outside [0, nx) x [0, ny).  Numbered row by row for the
@@ -321,7 +342,7 @@ struct AdjStrip {
 
 template <typename T, bool HAS_EPS, bool HAS_MU, bool HM>
 __global__ __launch_bounds__(ADJ_MARCH_BLOCK) void adj2d_march_kernel(Cart2DAdjArgs<T> a, T *padpsi, double *padg, int32_t ntx,
-                                                                int32_t nty)
+                                                                int32_t nty, int32_t tile_y)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = xcd_logical_block() * (ADJ_MARCH_BLOCK / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -338,7 +359,7 @@ __global__ __launch_bounds__(ADJ_MARCH_BLOCK) void adj2d_march_kernel(Cart2DAdjA
     const Rsrc rE = make_rsrc(a.epsinv ? a.epsinv + (int64_t)b * ncell : a.U, fbytes);
     const Rsrc rM = make_rsrc(a.muinv ? a.muinv + (int64_t)b * ncell : a.U, fbytes);
     const int x0 = tx * (WAVE - 4) - 2, x = x0 + lane;
-    const int y0 = ty * ADJ_TILE_Y, y1 = min(y0 + ADJ_TILE_Y, a.ny);
+    const int y0 = ty * tile_y, y1 = min(y0 + tile_y, a.ny);
     const bool first_y = ty == 0, last_y = ty == nty - 1;
     const int R0 = first_y ? -2 : y0, R1 = last_y ? a.ny + 2 : y1;
     const bool interior = x0 >= 0 && x0 + WAVE - 1 <= a.nx - 1 && R0 - 4 >= 0 && R1 + 2 <= a.ny - 1;
@@ -479,26 +500,39 @@ int adjoint_static_scratch(void **ptr)
     return 0;
 }
 
+// One launch of the march kernel variant: the tile height follows from the device's compute
+// units and the waves one unit holds of this variant (its occupancy, looked up once).
+template <typename T, bool HAS_EPS, bool HAS_MU, bool HM>
+static void launch_march(const Cart2DAdjArgs<T> &a, T *padpsi, double *padg, hipStream_t s)
+{
+    static const int waves_per_cu = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj2d_march_kernel<T, HAS_EPS, HAS_MU, HM>,
+                                                         ADJ_MARCH_BLOCK, 0) != hipSuccess ||
+            n <= 0)
+            n = 8;
+        return n * (ADJ_MARCH_BLOCK / WAVE);
+    }();
+    const int64_t slots = (int64_t)std::max(a.ncu, 1) * waves_per_cu;
+    const int ty = adj_tile_rows(a.nx, a.ny, a.batch, slots);
+    const int ntx = (a.nx + (WAVE - 4) - 1) / (WAVE - 4), nty = (a.ny + ty - 1) / ty;
+    const int64_t waves = (int64_t)ntx * nty * a.batch;
+    dim3 grid((unsigned)((waves + ADJ_MARCH_BLOCK / WAVE - 1) / (ADJ_MARCH_BLOCK / WAVE)));
+    hipLaunchKernelGGL((adj2d_march_kernel<T, HAS_EPS, HAS_MU, HM>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg,
+                       ntx, nty, ty);
+}
+
 template <typename T>
 int launch_cart2d_adjoint(const Cart2DAdjArgs<T> &a, T *padpsi, double *padg, void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    const int ntx = (a.nx + (WAVE - 4) - 1) / (WAVE - 4), nty = (a.ny + ADJ_TILE_Y - 1) / ADJ_TILE_Y;
-    const int64_t waves = (int64_t)ntx * nty * a.batch;
-    dim3 grid((unsigned)((waves + ADJ_MARCH_BLOCK / WAVE - 1) / (ADJ_MARCH_BLOCK / WAVE)));
-    if (a.epsinv && a.muinv)
-        hipLaunchKernelGGL((adj2d_march_kernel<T, true, true, true>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
-    else if (a.muinv)
-        hipLaunchKernelGGL((adj2d_march_kernel<T, false, true, true>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
+    if (a.epsinv && a.muinv) launch_march<T, true, true, true>(a, padpsi, padg, s);
+    else if (a.muinv) launch_march<T, false, true, true>(a, padpsi, padg, s);
     else if (a.g_muinv) {   // vacuum 1/mu, but its gradient is asked for
-        if (a.epsinv)
-            hipLaunchKernelGGL((adj2d_march_kernel<T, true, false, true>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
-        else
-            hipLaunchKernelGGL((adj2d_march_kernel<T, false, false, true>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
-    } else if (a.epsinv)
-        hipLaunchKernelGGL((adj2d_march_kernel<T, true, false, false>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
-    else
-        hipLaunchKernelGGL((adj2d_march_kernel<T, false, false, false>), grid, dim3(ADJ_MARCH_BLOCK), 0, s, a, padpsi, padg, ntx, nty);
+        if (a.epsinv) launch_march<T, true, false, true>(a, padpsi, padg, s);
+        else launch_march<T, false, false, true>(a, padpsi, padg, s);
+    } else if (a.epsinv) launch_march<T, true, false, false>(a, padpsi, padg, s);
+    else launch_march<T, false, false, false>(a, padpsi, padg, s);
     const int64_t nband = Band2D(a.nx, a.ny).count();
     dim3 gband((unsigned)((nband + ADJ_BLOCK - 1) / ADJ_BLOCK), a.batch);
     hipLaunchKernelGGL(adj2d_fold_kernel<T>, gband, dim3(ADJ_BLOCK), 0, s, a, (const T *)padpsi, (const double *)padg);

@@ -130,6 +130,11 @@ class Solver:
         import torch
         L = lib()
         self.torch = torch
+        self._init = dict(kind=kind, n=n, lo=lo, hi=hi, bc=bc, precision=precision, batch=batch, c=c, cfl=cfl, dt=dt,
+                          tau_over_dt=tau_over_dt, energy_every=energy_every, unstable_growth=unstable_growth,
+                          device=device, tri=tri, tet=tet, gradient=gradient, limiter=limiter, phm=phm)
+        self._source = None
+        self._twin = None
         self.kind = kind
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.precision = precision
@@ -271,6 +276,23 @@ class Solver:
             raise ValueError("cells and weights differ in length")
         self._check(lib().gks_set_point_source(self._h, c.shape[0], c.ctypes.data if c.size else None,
                                                w.ctypes.data if w.size else None, J0, t0, sigma_t))
+        self._source = (c, w, J0, t0, sigma_t)
+        if self._twin is not None:
+            self._twin.set_point_source(*self._source)
+
+    def twin(self):
+        """A second solver of the same mesh, parameters, materials and source, bound to a stream of
+        its own (made once and kept): its launches run concurrently with this solver's.  The
+        caller orders the two streams (events) where one reads what the other writes."""
+        if self._twin is None:
+            side = self.torch.cuda.Stream(self.device)
+            with self.torch.cuda.device(self.device), self.torch.cuda.stream(side):
+                t = Solver(**self._init)
+            if self._source is not None:
+                t.set_point_source(*self._source)
+            self._twin = t
+        self._twin.set_material(*self._material)
+        return self._twin
 
     def step(self, U, out=None, t: float = 0.0):
         self._state(U, "U")

@@ -293,6 +293,37 @@ def test_gksfunction_is_run_then_probe(torch):
     assert np.array_equal(grads[0][1], grads[1][1]) and np.array_equal(grads[0][2], grads[1][2])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_checkpoint_schedules_agree_bit_for_bit(torch, precision):
+    """The backward pass recomputes segment states on the solver's twin stream while the main
+    stream reverses the segment after; events order the two.  Every checkpoint spacing (one
+    segment; two; many, with a ragged last one; one step per segment) runs the same kernels in
+    the same order on the same data, so the loss and all gradients must agree bit for bit: a
+    missing wait would let a recompute overwrite states still being read, or the adjoint read
+    states not yet written.  Both material maps; no source (the source time of a step is formed
+    from its segment's start, which differs in its last bits between spacings)."""
+    from paper_2412_16845_amd import autograd as AG
+    nx, ny, K = 24, 20, 11
+    rng = np.random.default_rng(51)
+    U0 = rng.standard_normal((BATCH, 3, ny, nx))
+    ei = rng.uniform(0.25, 1.0, (BATCH, ny, nx))
+    mi = rng.uniform(0.5, 1.0, (BATCH, ny, nx))
+    box = (10, 16, 6, 12)
+    out = []
+    for every in (K, 6, 4, 3, 1):
+        s, E, M = solver_for(torch, nx, ny, (N, P, N, N), 0.01, precision, BATCH, ei, mi)
+        U = dev(torch, U0, precision).requires_grad_(True)
+        E.requires_grad_(True)
+        M.requires_grad_(True)
+        loss = AG.probe_energy(s, AG.run(s, U, K, E, M, t0=0.003, checkpoint_every=every), box).sum()
+        loss.backward()
+        out.append((every, loss.item(), U.grad.cpu().numpy(), E.grad.cpu().numpy(), M.grad.cpu().numpy()))
+    for every, *rest in out[1:]:
+        assert rest[0] == out[0][1], every
+        for a, b in zip(rest[1:], out[0][2:]):
+            assert np.array_equal(a, b), every
+
+
 def test_c5_gradient_against_finite_differences(torch):
     """The differentiable workload at full size: 1024 x 1024 x 8 dielectric maps, probe-box Ez
     energy after 800 steps, reverse mode with checkpoints every 50 steps.  The FP64 gradient
