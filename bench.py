@@ -535,11 +535,18 @@ def tri_leg(torch):
             raise RuntimeError(f"triangle {prec} run produced non-finite values")
         t_launch, _ = time_kernel(torch, s, U, launches=100)
         alg = tri_bytes_per_cell(prec) * ncell
+        # the same time against the byte models of the two other layouts: geometry rebuilt from
+        # vertices on the fly (3 vertex ids, shared coordinates, 3 neighbours, no gradient
+        # scratch) and precomputed per-face geometry
+        models = {"on_the_fly": 56 if prec == "fp32" else 88, "per_face_geometry": 150 if prec == "fp32" else 250}
         out[prec] = {"value": round(ncell * C4_STEPS / t_run, 1), "unit": "cell-updates/s",
                      "ms_per_step": round(t_run * 1e3 / C4_STEPS, 5), "dt": s.dt,
                      "roofline": {"bound": "hbm", "achieved": round(alg / t_launch / 1e9, 1), "peak": PEAK_GBS,
                                   "unit": "GB/s", "frac": round(alg / t_launch / 1e9 / PEAK_GBS, 4),
-                                  "algorithmic_bytes_per_launch": alg, "step_seconds_per_launch": t_launch}}
+                                  "algorithmic_bytes_per_launch": alg, "step_seconds_per_launch": t_launch},
+                     "frac_against_other_layouts": {
+                         k: {"bytes_per_cell": b, "frac": round(b * ncell / t_launch / 1e9 / PEAK_GBS, 4)}
+                         for k, b in models.items()}}
         del s, U
         torch.cuda.empty_cache()
     return out
@@ -777,8 +784,17 @@ def main():
         if not torch.isfinite(U).all():
             raise RuntimeError(f"{prec} run produced non-finite values")
         t_launch, t_med = time_kernel(torch, s, U)
-        res[prec] = {"seconds": el, "wall": wall, "t_launch": t_launch, "t_launch_median": t_med, "dt": s.dt}
-        log(f"[bench] {prec}: {el * 1e3 / args.steps:.4f} ms/step, kernel {t_launch * 1e6:.1f} us/launch")
+        # the recipe's fields are zero away from the source for most of the run; the same launches
+        # on a state of unit normal values in every cell show whether the data changes the time
+        g = torch.Generator(device="cuda")
+        g.manual_seed(7)
+        Ur = torch.randn(U.shape, generator=g, dtype=U.dtype, device=U.device)
+        t_rand, _ = time_kernel(torch, s, Ur)
+        res[prec] = {"seconds": el, "wall": wall, "t_launch": t_launch, "t_launch_median": t_med, "dt": s.dt,
+                     "t_launch_random": t_rand}
+        log(f"[bench] {prec}: {el * 1e3 / args.steps:.4f} ms/step, kernel {t_launch * 1e6:.1f} us/launch "
+            f"({t_rand * 1e6:.1f} us from a random state)")
+        del Ur
         del s, U, ei
         torch.cuda.empty_cache()
 
@@ -804,6 +820,9 @@ def main():
         "fp64": {"value": round(ncell * args.steps / f64["seconds"], 1), "unit": "cell-updates/s",
                  "ms_per_step": round(f64["seconds"] * 1e3 / args.steps, 5), "dtype": "f64",
                  "roofline": roofline("fp64", f64["t_launch"])},
+        "kernel_us_per_launch_by_state": {
+            prec: {"recipe_state": round(res[prec]["t_launch"] * 1e6, 2),
+                   "random_state": round(res[prec]["t_launch_random"] * 1e6, 2)} for prec in ("fp32", "fp64")},
     }
     if not args.no_limited:
         log("[bench] limited 2D step: 4096x4096, minmod slopes, fp32 and fp64")
