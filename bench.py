@@ -431,9 +431,18 @@ def cart3d_leg(torch):
         if not torch.isfinite(U).all():
             raise RuntimeError(f"3D {prec} run produced non-finite values")
         t_launch, _ = time_kernel(torch, s, U, launches=30)
+        # this kernel is bound by its arithmetic, and arithmetic on nonzero data draws more power:
+        # the same launches on a state of unit normal values in every cell
+        g = torch.Generator(device="cuda")
+        g.manual_seed(11)
+        Ur = torch.randn(U.shape, generator=g, dtype=dtype, device="cuda")
+        t_rand, _ = time_kernel(torch, s, Ur, launches=30)
+        del Ur
         alg = C3_BYTES_PER_CELL[prec] * ncell
         out[prec] = {"value": round(ncell * C3_STEPS / t_run, 1), "unit": "cell-updates/s",
                      "ms_per_step": round(t_run * 1e3 / C3_STEPS, 4),
+                     "kernel_us_per_launch_by_state": {"recipe_state": round(t_launch * 1e6, 1),
+                                                       "random_state": round(t_rand * 1e6, 1)},
                      "roofline": {"bound": "hbm", "achieved": round(alg / t_launch / 1e9, 1), "peak": PEAK_GBS,
                                   "unit": "GB/s", "frac": round(alg / t_launch / 1e9 / PEAK_GBS, 4),
                                   "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch},

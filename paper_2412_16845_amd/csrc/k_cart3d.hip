@@ -170,9 +170,18 @@ struct March3D {
     // The differences of plane q-1 for the z face below plane q: in fp32 they are read back
     // from the LDS slot this wave wrote them to in the previous step, which keeps them out of
     // the 128 registers of the 16-wave workgroup (with them in registers the double-precision
-    // accumulator spilled: 384^3, 1528 -> 1378 us); fp64 keeps them in registers (3604 us
-    // against 3770 us with the LDS reads).
-    static constexpr bool GP_LDS = sizeof(T) == 4;
+    // accumulator spilled: 384^3, 1528 -> 1378 us); so does the fp64 eight-field kernel, whose
+    // registers spill (20.9 -> 17.0 ms); the fp64 six-field kernel keeps them in registers
+    // (3604 us against 3770 us with the LDS reads).
+    static constexpr bool GP_LDS = sizeof(T) == 4 || NF == 8;
+    // fp64 with eight fields: values that would live across a barrier (the row above, this
+    // plane's differences, the x and y fluxes) are read again from LDS or folded first, which
+    // frees registers in a kernel that spills (384^3: 17.0 -> 15.9 ms; the six-field fp64
+    // kernel, which does not spill, is slower with it: 3.45 -> 3.75 ms)
+    static constexpr bool LEAN = sizeof(T) == 8 && NF == 8;
+    // this plane's differences for the x and y faces, which come after the barrier that
+    // publishes them: LEAN reads them back from this lane's LDS slot
+    __device__ __forceinline__ T gown(const T (&G)[3 * NF], int k) const { return LEAN ? s.g[k][row][lane] : G[k]; }
     __device__ __forceinline__ T gprev(const T (&Gp)[3 * NF], int k) const { return GP_LDS ? s.g[k][row][lane] : Gp[k]; }
 
     // One march step with central plane q: A = q-1, B = q, C = q+1 (loaded), D receives q+2.
@@ -231,10 +240,8 @@ struct March3D {
             T Z[NF];
             // interior planes of interior tiles (the common case): no side is zeroed, so the
             // operator reads the registers directly (384^3 fp64: 4590 -> 4130 us, fp32: 1328 -> 1319
-            // us).  The eight-field fp64 kernel keeps the selects: the second copy of the operator
-            // adds to its register spills (20.9 -> 22.8 ms).
-            constexpr bool DIRECT_Z = !(sizeof(T) == 8 && NF == 8);
-            if (DIRECT_Z && !BXY && !zlu && !zru) {
+            // us; the eight-field fp64 kernel 15.9 -> 15.5 ms)
+            if (!BXY && !zlu && !zru) {
                 T w[8 * NF];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
@@ -303,10 +310,10 @@ struct March3D {
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 w[f] = su[f];
-                w[NF + f] = zr ? T(0) : uy[f];
-                w[2 * NF + f] = G[NF + f];
-                w[3 * NF + f] = G[f];
-                w[4 * NF + f] = G[2 * NF + f];
+                w[NF + f] = zr ? T(0) : (LEAN ? s.u[cu][f][rowp][lane] : uy[f]);
+                w[2 * NF + f] = gown(G, NF + f);
+                w[3 * NF + f] = gown(G, f);
+                w[4 * NF + f] = gown(G, 2 * NF + f);
                 w[5 * NF + f] = s.g[NF + f][rowp][lane];
                 w[6 * NF + f] = s.g[f][rowp][lane];
                 w[7 * NF + f] = s.g[2 * NF + f][rowp][lane];
@@ -324,14 +331,21 @@ struct March3D {
             for (int f = 0; f < NF; ++f) {
                 w[f] = su[f];
                 w[NF + f] = from_right(su[f]);
-                w[2 * NF + f] = G[f];
-                w[3 * NF + f] = G[NF + f];
-                w[4 * NF + f] = G[2 * NF + f];
-                w[5 * NF + f] = from_right(G[f]);
-                w[6 * NF + f] = from_right(G[NF + f]);
-                w[7 * NF + f] = from_right(G[2 * NF + f]);
+                w[2 * NF + f] = gown(G, f);
+                w[3 * NF + f] = gown(G, NF + f);
+                w[4 * NF + f] = gown(G, 2 * NF + f);
+                w[5 * NF + f] = from_right(gown(G, f));
+                w[6 * NF + f] = from_right(gown(G, NF + f));
+                w[7 * NF + f] = from_right(gown(G, 2 * NF + f));
             }
             apply_op<PX_, CH3<T, NF>(), HM>(w, B.mE + from_right(B.mE), HM ? B.mH + from_right(B.mH) : T(2), opx, px);
+        }
+        // LEAN: the x part of the divergence now, so that px need not live across the barrier
+        // (the y fluxes are read back from LDS after it): the same sums in the same order
+        double tx[NF];
+        if (LEAN && outp && need_all) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) tx[f] = (double)px[f] - (double)from_left(px[f]);
         }
         if constexpr (NU == 2) {
             // share the fields of plane q+1 in the other buffer (its last readers, in the
@@ -343,8 +357,11 @@ struct March3D {
         __syncthreads();
         if (outp && need_all) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f)
-                acc[f] += ((double)px[f] - (double)from_left(px[f])) + ((double)py[f] - (double)s.p[f][rowm][lane]);
+            for (int f = 0; f < NF; ++f) {
+                const double dx = LEAN ? tx[f] : (double)px[f] - (double)from_left(px[f]);
+                const T pyf = LEAN ? s.p[f][row][lane] : py[f];
+                acc[f] += dx + ((double)pyf - (double)s.p[f][rowm][lane]);
+            }
         }
     }
 
