@@ -99,22 +99,32 @@ def time_run(torch, s, U, steps, warmup):
 
 
 def time_kernel(torch, s, U, launches=200):
-    """Average duration of one step-kernel launch: a HIP event pair around each launch on the
-    stream the kernel runs on."""
+    """Average duration of one step-kernel launch on the stream the kernel runs on: a HIP event
+    pair around `launches` back-to-back launches, divided by their number (gaps between the
+    launches included).  Also returns the mean over event pairs around single launches (up to 50),
+    which adds the events' own overhead to every launch."""
     A, B = U, torch.empty_like(U)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(launches)]
     for i in range(10):
         s.step(A, B, t=i * s.dt)
         A, B = B, A
     torch.cuda.synchronize()
-    for i, (e0, e1) in enumerate(evs):
-        e0.record(s.stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    for i in range(launches):
         s.step(A, B, t=i * s.dt)
-        e1.record(s.stream)
+        A, B = B, A
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    batch = e0.elapsed_time(e1) / 1e3 / launches
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(min(launches, 50))]
+    for i, (a, b) in enumerate(evs):
+        a.record(s.stream)
+        s.step(A, B, t=i * s.dt)
+        b.record(s.stream)
         A, B = B, A
     torch.cuda.synchronize()
-    d = np.array([e0.elapsed_time(e1) for e0, e1 in evs]) / 1e3
-    return float(np.mean(d)), float(np.median(d))
+    pairs = float(np.mean([a.elapsed_time(b) for a, b in evs])) / 1e3
+    return batch, pairs
 
 
 def kernel_sha():
@@ -792,14 +802,14 @@ def main():
         el, wall = time_run(torch, s, U, args.steps, args.warmup)
         if not torch.isfinite(U).all():
             raise RuntimeError(f"{prec} run produced non-finite values")
-        t_launch, t_med = time_kernel(torch, s, U)
+        t_launch, t_pairs = time_kernel(torch, s, U)
         # the recipe's fields are zero away from the source for most of the run; the same launches
         # on a state of unit normal values in every cell show whether the data changes the time
         g = torch.Generator(device="cuda")
         g.manual_seed(7)
         Ur = torch.randn(U.shape, generator=g, dtype=U.dtype, device=U.device)
         t_rand, _ = time_kernel(torch, s, Ur)
-        res[prec] = {"seconds": el, "wall": wall, "t_launch": t_launch, "t_launch_median": t_med, "dt": s.dt,
+        res[prec] = {"seconds": el, "wall": wall, "t_launch": t_launch, "t_launch_pairs": t_pairs, "dt": s.dt,
                      "t_launch_random": t_rand}
         log(f"[bench] {prec}: {el * 1e3 / args.steps:.4f} ms/step, kernel {t_launch * 1e6:.1f} us/launch "
             f"({t_rand * 1e6:.1f} us from a random state)")
@@ -831,7 +841,9 @@ def main():
                  "roofline": roofline("fp64", f64["t_launch"])},
         "kernel_us_per_launch_by_state": {
             prec: {"recipe_state": round(res[prec]["t_launch"] * 1e6, 2),
-                   "random_state": round(res[prec]["t_launch_random"] * 1e6, 2)} for prec in ("fp32", "fp64")},
+                   "random_state": round(res[prec]["t_launch_random"] * 1e6, 2),
+                   "recipe_state_single_launch_event_pairs": round(res[prec]["t_launch_pairs"] * 1e6, 2)}
+            for prec in ("fp32", "fp64")},
     }
     if not args.no_limited:
         log("[bench] limited 2D step: 4096x4096, minmod slopes, fp32 and fp64")
