@@ -254,6 +254,51 @@ __device__ __forceinline__ void apply_op_transpose(const T (&abar)[NF], T mE, T 
     }
 }
 
+// apply_op_parts and apply_op_transpose in one pass over the coefficients: every coefficient is
+// loaded once and used for both products (phi = K0 w + mE e + mH h with its parts e, h; and
+// wbar += K(mE, mH)^T abar), which halves the scalar loads of a face that needs both.
+template <typename P, int CH = 12, bool HM = true, typename T, int NF, int NIN, typename Op>
+__device__ __forceinline__ void apply_op_both(const T (&w)[NIN], const T (&abar)[NF], T mE, T mH, Op K, T (&phi)[NF],
+                                              T (&e)[NF], T (&h)[NF], T (&wbar)[NIN])
+{
+    T a[NF], ae[NF], ah[NF];
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+        a[r] = e[r] = h[r] = T(0);
+        ae[r] = mE * abar[r];
+        ah[r] = mH * abar[r];
+    }
+#pragma unroll
+    for (int q = 0; q < P::N0; ++q) {
+        if (q % CH == 1 && q + CH - 1 < P::N0) asm volatile("" : "+s"(K) : "v"(a[P::R0[q - 1]]));
+        const T k = K->k0[q];
+        a[P::R0[q]] = fma(k, w[P::C0[q]], a[P::R0[q]]);
+        wbar[P::C0[q]] = fma(k, abar[P::R0[q]], wbar[P::C0[q]]);
+    }
+    asm volatile("" : "+s"(K) : "v"(a[P::R0[P::N0 - 1]]));
+#pragma unroll
+    for (int q = 0; q < P::NE; ++q) {
+        const T k = K->ke[q];
+        e[P::RE[q]] = fma(k, w[P::CE[q]], e[P::RE[q]]);
+        wbar[P::CE[q]] = fma(k, ae[P::RE[q]], wbar[P::CE[q]]);
+    }
+    if constexpr (HM) {
+#pragma unroll
+        for (int q = 0; q < P::NH; ++q) {
+            const T k = K->kh[q];
+            h[P::RH[q]] = fma(k, w[P::CH[q]], h[P::RH[q]]);
+            wbar[P::CH[q]] = fma(k, ah[P::RH[q]], wbar[P::CH[q]]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NF; ++r) {
+        T v = a[r];
+        if ((P::EROWS >> r) & 1u) v = fma(mE, e[r], v);
+        if (HM && ((P::HROWS >> r) & 1u)) v = fma(mH, h[r], v);
+        phi[r] = v;
+    }
+}
+
 // abar . (KE w) and abar . (KH w): derivatives of abar . phi with respect to mE and mH.
 template <typename P, typename T, int NF, int NIN, typename Op>
 __device__ __forceinline__ void material_sens(const T (&abar)[NF], const T (&w)[NIN], Op K, T &dE, T &dH)

@@ -30,11 +30,19 @@
 namespace gks {
 
 constexpr int ADJ_BLOCK = 256;
-// Coefficient chunk of the forward and transposed face operators: small chunks keep fewer
-// scalar registers live and halve the scalar spills of the march (1024^2 x 8 adjoint step:
-// 221.5 -> 208.9 us in fp32 and 482.7 -> 433.1 us in fp64 with 4 instead of 12; 3, 5, 6 and 8
-// are slower).
-constexpr int ADJ_CH = 4;
+// Coefficient chunk of the face operators: small chunks keep fewer scalar registers live and
+// halve the scalar spills of the march (1024^2 x 8 adjoint step with separate forward and
+// transposed passes: 221.5 -> 208.9 us in fp32 and 482.7 -> 433.1 us in fp64 with 4 instead of
+// 12; 3, 5, 6 and 8 were slower).  With the fused pass below fp32 takes chunks of 6 (160.5 ->
+// 157 us).
+template <typename T> constexpr int adj_chunk() { return sizeof(T) == 4 ? 6 : 4; }
+// fp32: the forward and the transposed operator of a face in one pass over its coefficients,
+// each loaded once (163 -> 160.5 us with chunks of 4, 154 instead of 167 VGPRs); fp64 keeps two
+// passes that load them twice (one pass raises its scalar spills from 603 to 722).
+#ifndef GKS_ADJ_FUSED
+#define GKS_ADJ_FUSED 1
+#endif
+template <typename T> constexpr bool adj_fused() { return GKS_ADJ_FUSED != 0 && sizeof(T) == 4; }
 // One wave per workgroup for the march: its waves finish at different times, and a single-wave
 // workgroup lets a freed slot take the next tile at once (4-wave workgroups wait for four free
 // slots on one compute unit).  Measured on 1024^2 x 8: 231 vs 241 us (fp32), 503 vs 552 us (fp64).
@@ -172,12 +180,16 @@ struct AdjStrip {
                                          T (&wbar)[18], T &sE, T &sH) const
     {
         T e[3], h[3];
-        apply_op_parts<P, ADJ_CH, HM>(w, mEs, mHs, K, phi, e, h);
 #pragma unroll
         for (int q = 0; q < 18; ++q) wbar[q] = T(0);
-        // reload the coefficients for the transposed pass rather than keeping them live
-        asm volatile("" : "+s"(K) : "v"(phi[2]));
-        apply_op_transpose<P, ADJ_CH, HM>(ad, mEs, mHs, K, wbar);
+        if constexpr (adj_fused<T>()) {
+            apply_op_both<P, adj_chunk<T>(), HM>(w, ad, mEs, mHs, K, phi, e, h, wbar);
+        } else {
+            apply_op_parts<P, adj_chunk<T>(), HM>(w, mEs, mHs, K, phi, e, h);
+            // reload the coefficients for the transposed pass rather than keeping them live
+            asm volatile("" : "+s"(K) : "v"(phi[2]));
+            apply_op_transpose<P, adj_chunk<T>(), HM>(ad, mEs, mHs, K, wbar);
+        }
         sE = ad[0] * e[0] + ad[1] * e[1] + ad[2] * e[2];
         sH = HM ? ad[0] * h[0] + ad[1] * h[1] + ad[2] * h[2] : T(0);
     }
