@@ -232,12 +232,25 @@ std::vector<int32_t> gks::cart2d_tile_table(int ny, int batch, int precision, in
     // end the band, so the last waves of an XCD are short and the drain of the launch is short.
     // Measured on 4096^2 (fp32, per launch): uniform 14-row tiles 113.4 us; tall 32 / short 8
     // rows with the short rows 0.3 of each band 110.8 us (fp64 203.3 us, as with 16-row tiles).
+    // A later sweep (batch-timed, fp32 / fp64 us): 32/8/0.3 108.3 / 201.4; tall 24, 28, 36, 40:
+    // 108.6, 108.5, 109.0, 113.9 / 202.4, 202.1, 203.9, 206.0; short 6, 10, 12: 108.3, 109.5,
+    // 109.6 / 203.0, 201.9, 202.6; short fraction 0.2, 0.4: 111.0, 108.5 / 200.6, 200.9.
     // A band whose last workgroup also ran the next band's first (tall) tiles cost up to 30%:
     // the padding keeps every band on its own XCD.  Vertically adjacent tiles of a band march in
     // opposite directions, so the halo rows they share are read at about the same time (the
     // second read hits the L2); tiles never straddle two batch items.
-    int tall = 32, shrt = 8;
-    double frac = 0.3;
+#ifndef GKS_TILE_TALL
+#define GKS_TILE_TALL 32
+#endif
+#ifndef GKS_TILE_SHORT
+#define GKS_TILE_SHORT 8
+#endif
+#ifndef GKS_TILE_SHORT_FRAC
+#define GKS_TILE_SHORT_FRAC 0.3
+#endif
+    // (the three macros are build-time overrides for tuning sweeps)
+    int tall = GKS_TILE_TALL, shrt = GKS_TILE_SHORT;
+    double frac = GKS_TILE_SHORT_FRAC;
     (void)precision;
 #ifdef GKS_FORCE_TILE_Y
     tall = shrt = GKS_FORCE_TILE_Y;   // build-time override for tuning sweeps: uniform tiles
