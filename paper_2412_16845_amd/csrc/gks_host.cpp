@@ -426,8 +426,23 @@ template <typename T>
 gks_status upload_tri(gks_ctx *x, const TriGeometry &g)
 {
     const size_t nc = (size_t)g.ncell;
+    // the device layout: vector components side by side (TGP_*), then the |l_k| / |Omega| rows
     std::vector<T> geo(g.geo.size());
-    for (size_t q = 0; q < geo.size(); ++q) geo[q] = (T)g.geo[q];
+    auto pair = [&](int p, int rx, int ry) {
+        for (size_t c = 0; c < nc; ++c) {
+            geo[((size_t)p * nc + c) * 2] = (T)g.geo[(size_t)rx * nc + c];
+            geo[((size_t)p * nc + c) * 2 + 1] = (T)g.geo[(size_t)ry * nc + c];
+        }
+    };
+    for (int k = 0; k < 3; ++k) {
+        pair(TGP_N + k, TG_NX + k, TG_NY + k);
+        pair(TGP_B + k, TG_BX + k, TG_BY + k);
+        pair(TGP_W + k, TG_WX + k, TG_WY + k);
+        for (size_t c = 0; c < nc; ++c)
+            geo[2 * (size_t)TRI_GEO_PAIRS * nc + (size_t)k * nc + c] = (T)g.geo[(size_t)(TG_LW + k) * nc + c];
+    }
+    for (int k = 0; k < 2; ++k) pair(TGP_A + k, TG_AX + k, TG_AY + k);
+    static_assert(2 * TRI_GEO_PAIRS + 3 == TRI_GEO_ROWS, "every geometry row is stored once");
     if (hipMalloc((void **)&x->d_tri_nb, 3 * nc * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&x->d_tri_geo, geo.size() * sizeof(T)) != hipSuccess ||
         hipMalloc((void **)&x->d_area, nc * sizeof(double)) != hipSuccess ||

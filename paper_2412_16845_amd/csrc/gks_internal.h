@@ -106,6 +106,12 @@ struct Cart3DArgs {
 //                          neighbour's centroid or the centroid's mirror image minus x_i)
 constexpr int TG_NX = 0, TG_NY = 3, TG_LW = 6, TG_AX = 9, TG_AY = 11, TG_BX = 13, TG_BY = 16, TG_WX = 19, TG_WY = 22;
 constexpr int TRI_GEO_ROWS = 25;
+// On the device the same values are stored with the x and y components of each vector side by
+// side, so that a lane reads a vector with one 8-byte (16-byte in fp64) load: TRI_GEO_PAIRS
+// arrays [pair][ncell][2] (TGP_N + k: normal of slot k; TGP_A + k: x_s - x_i of slot k = 0, 1;
+// TGP_B + k: x_s - x_nb; TGP_W + k: gradient weight), then the three |l_k| / |Omega| arrays
+// [k][ncell] at element offset 2 TRI_GEO_PAIRS ncell.
+constexpr int TGP_N = 0, TGP_A = 3, TGP_B = 5, TGP_W = 8, TRI_GEO_PAIRS = 11;
 struct TriGeometry {
     int64_t ncell = 0;
     std::vector<int32_t> nb;     // [3][ncell]
@@ -167,7 +173,7 @@ struct TriArgs {
     int32_t ncell, batch;
     int32_t nfields;      // 3: (Ez, Hx, Hy); 4: (Ez, Hx, Hy, psi)
     const int32_t *nb;    // device [3][ncell]
-    const T *geo;         // device [TRI_GEO_ROWS][ncell]
+    const T *geo;         // device: the paired layout above (TRI_GEO_PAIRS pairs, then |l_k| / |Omega|)
     const void *op;       // device: the face operator (face-frame inputs; FaceOpTM<T> or FaceOpTP<T>)
 };
 template <typename T> int launch_tri_step(const TriArgs<T> &a, void *stream);

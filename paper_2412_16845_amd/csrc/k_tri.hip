@@ -58,6 +58,21 @@ __device__ __forceinline__ void load_grad(const T *G, int64_t c, T (&gx)[NF], T 
     }
 }
 
+// Geometry vector p of cell c (x, y) with one load, and the |l_k| / |Omega| of slot k.
+template <typename T>
+__device__ __forceinline__ void geo_vec(const T *geo, int p, int64_t nc, int64_t c, T &x, T &y)
+{
+    using V = typename Pair<T>::type;
+    const V v = reinterpret_cast<const V *>(geo)[(int64_t)p * nc + c];
+    x = v.x;
+    y = v.y;
+}
+template <typename T>
+__device__ __forceinline__ T geo_lw(const T *geo, int k, int64_t nc, int64_t c)
+{
+    return geo[2 * (int64_t)TRI_GEO_PAIRS * nc + (int64_t)k * nc + c];
+}
+
 template <typename T, int NF>
 __device__ __forceinline__ void store_grad(T *G, int64_t c, const T (&gx)[NF], const T (&gy)[NF])
 {
@@ -90,14 +105,16 @@ __global__ __launch_bounds__((tri_block<T, NF>())) void tri_grad_kernel(TriArgs<
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int32_t nb = a.nb[k * nc + i];
-        const T wx = a.geo[(TG_WX + k) * nc + i], wy = a.geo[(TG_WY + k) * nc + i];
+        T wx, wy;
+        geo_vec(a.geo, TGP_W + k, nc, i, wx, wy);
         T d[NF];   // U_k - U_i: the neighbour, or the ghost of a boundary face
         if (nb >= 0) {
 #pragma unroll
             for (int f = 0; f < NF; ++f) d[f] = U[f * nc + nb] - u[f];
         } else if (nb == -(1 + GKS_BC_PEC)) {
             // mirror ghost: Ez and the normal H odd, the tangential H and psi even
-            const T nx = a.geo[(TG_NX + k) * nc + i], ny = a.geo[(TG_NY + k) * nc + i];
+            T nx, ny;
+            geo_vec(a.geo, TGP_N + k, nc, i, nx, ny);
             const T hn = u[1] * nx + u[2] * ny;
             d[0] = T(-2) * u[0];
             d[1] = T(-2) * hn * nx;
@@ -148,13 +165,15 @@ __global__ __launch_bounds__((tri_block<T, NF>())) void tri_step_kernel(TriArgs<
 #pragma unroll
     for (int f = 0; f < NF; ++f) div[f] = 0.0;
     // midpoint offsets of slots 0 and 1; slot 2's is minus their sum
-    const T ax01[2] = {a.geo[(TG_AX + 0) * nc + i], a.geo[(TG_AX + 1) * nc + i]};
-    const T ay01[2] = {a.geo[(TG_AY + 0) * nc + i], a.geo[(TG_AY + 1) * nc + i]};
+    T ax01[2], ay01[2];
+    geo_vec(a.geo, TGP_A + 0, nc, i, ax01[0], ay01[0]);
+    geo_vec(a.geo, TGP_A + 1, nc, i, ax01[1], ay01[1]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int32_t nb = a.nb[k * nc + i];
-        const T nx = a.geo[(TG_NX + k) * nc + i], ny = a.geo[(TG_NY + k) * nc + i];
-        const T lw = a.geo[(TG_LW + k) * nc + i];
+        T nx, ny;
+        geo_vec(a.geo, TGP_N + k, nc, i, nx, ny);
+        const T lw = geo_lw(a.geo, k, nc, i);
         const T ax = k < 2 ? ax01[k < 2 ? k : 0] : -(ax01[0] + ax01[1]);
         const T ay = k < 2 ? ay01[k < 2 ? k : 0] : -(ay01[0] + ay01[1]);
         // The face operator is linear and, for a constant state on both sides, gives that
@@ -187,7 +206,8 @@ __global__ __launch_bounds__((tri_block<T, NF>())) void tri_step_kernel(TriArgs<
         }
         T mEs, mHs;
         if (nb >= 0) {
-            const T bx = a.geo[(TG_BX + k) * nc + i], by = a.geo[(TG_BY + k) * nc + i];
+            T bx, by;
+            geo_vec(a.geo, TGP_B + k, nc, i, bx, by);
             T dr[NF], dn[NF], dt[NF], hxs[NF], hys[NF];
             load_grad<T, NF>(Gr, nb, hxs, hys);
 #pragma unroll
