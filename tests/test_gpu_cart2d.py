@@ -185,6 +185,27 @@ def test_batch_and_long_source_list_fp64(torch):
         assert rel_l2(got[b], ref) <= 1e-12, b
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("nx,ny,batch", [(300, 5, 9), (130, 37, 3), (70, 2, 11), (250, 61, 2)])
+def test_tile_bands_across_batch_items(torch, nx, ny, batch, precision):
+    """The step's tile table cuts the (batch item, row) sequence into eight bands, one per XCD,
+    with tall tiles first and short ones at each band's end, and never lets a tile straddle two
+    batch items.  Shapes whose rows do not divide into the bands (bands that start and end
+    inside batch items, bands shorter than a tile, more bands than rows per item) must give every
+    batch item the oracle's result."""
+    rng = np.random.default_rng(nx * 7 + ny * 13 + batch)
+    U0 = rng.standard_normal((batch, 3, ny, nx))
+    ei = rng.uniform(0.25, 1.0, (batch, ny, nx))
+    bc = (I.NONREFLECT, I.PEC, I.PERIODIC, I.PERIODIC)
+    wl = I.Workload("bands", "cart2d", (nx, ny), (0.0, 0.0), (1.0, 1.0), bc, U0, ei, None, 0.5, 0.01, 6)
+    s, U = setup(torch, wl, precision)
+    s.run(U, wl.nsteps)
+    got = U.cpu().numpy()
+    for b in range(batch):
+        err = rel_l2(got[b], oracle_run(wl, wl.nsteps, s.dt, b=b))
+        assert err <= TOL[precision], (b, err)
+
+
 def test_step_matches_run_and_is_deterministic(torch):
     wl = I.tm_dielectric_nr(nx=128, ny=100, seed=2, nsteps=20, ncircles=8, pulse=1.0)
     s, U = setup(torch, wl, "fp32")
