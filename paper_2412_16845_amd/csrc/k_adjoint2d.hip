@@ -409,18 +409,18 @@ struct Band2D {
     int nx, ny, nrow, ncol;   // band rows (all rows if ny <= 4), band columns of the middle rows
     __host__ __device__ Band2D(int nx_, int ny_) : nx(nx_), ny(ny_), nrow(ny_ <= 4 ? ny_ : 4), ncol(nx_ <= 4 ? nx_ : 4) {}
     __host__ __device__ int64_t count() const { return (int64_t)nrow * nx + (int64_t)(ny > 4 ? ny - 4 : 0) * ncol; }
-    __device__ void cell(int64_t t, int &i, int &j) const
+    // (both branches computed and selected, so that i and j stay in registers)
+    __device__ __forceinline__ void cell(int t, int &i, int &j) const
     {
-        if (t < (int64_t)nrow * nx) {
-            const int r = (int)(t / nx);
-            i = (int)(t % nx);
-            j = (ny <= 4 || r < 2) ? r : ny - 4 + r;
-        } else {
-            const int64_t u = t - (int64_t)nrow * nx;
-            const int c = (int)(u % ncol);
-            j = 2 + (int)(u / ncol);
-            i = (nx <= 4 || c < 2) ? c : nx - 4 + c;
-        }
+        const int top = nrow * nx;
+        const bool inrow = t < top;
+        const int r = t / nx, ci = t - r * nx;   // band rows
+        const int u = inrow ? 0 : t - top;
+        const int v = u / ncol, c = u - v * ncol; // band columns of the middle rows
+        const int jr = (ny <= 4 || r < 2) ? r : ny - 4 + r;
+        const int ic = (nx <= 4 || c < 2) ? c : nx - 4 + c;
+        i = inrow ? ci : ic;
+        j = inrow ? jr : 2 + v;
     }
 };
 
@@ -436,26 +436,37 @@ __global__ __launch_bounds__(ADJ_BLOCK) void adj2d_fold_kernel(Cart2DAdjArgs<T> 
     const int64_t tb = (int64_t)blockIdx.x * ADJ_BLOCK + threadIdx.x;
     if (tb >= band.count()) return;
     int i, j;
-    band.cell(tb, i, j);
+    band.cell((int)tb, i, j);
     const int64_t t = (int64_t)j * a.nx + i;
-    // candidate images along each axis: the cell itself and the ghost indices that map to it
-    int cx[5], cy[5], nxc = 0, nyc = 0;
+    // candidate images along each axis: the ghost indices -2, -1, n, n+1 that map to this cell
+    // (fixed-size, fully unrolled, so that they stay in registers and every gather below is
+    // issued at once)
+    const int gxs[4] = {-2, -1, a.nx, a.nx + 1}, gys[4] = {-2, -1, a.ny, a.ny + 1};
+    bool hx[5], hy[5];
     T sx[5], sy[5];
-    cx[nxc] = i; sx[nxc++] = T(1);
-    for (int g = -2; g <= a.nx + 1; g += (g == -1 ? a.nx + 1 : 1)) {
+    int cx[5], cy[5];
+    hx[0] = hy[0] = true;
+    sx[0] = sy[0] = T(1);
+    cx[0] = i;
+    cy[0] = j;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
         bool m, nr;
-        if (map_axis(g, a.nx, a.bc[0], a.bc[1], m, nr) == i) { cx[nxc] = g; sx[nxc++] = m ? T(-1) : T(1); }
-    }
-    cy[nyc] = j; sy[nyc++] = T(1);
-    for (int g = -2; g <= a.ny + 1; g += (g == -1 ? a.ny + 1 : 1)) {
-        bool m, nr;
-        if (map_axis(g, a.ny, a.bc[2], a.bc[3], m, nr) == j) { cy[nyc] = g; sy[nyc++] = m ? T(-1) : T(1); }
+        hx[q + 1] = map_axis(gxs[q], a.nx, a.bc[0], a.bc[1], m, nr) == i;
+        sx[q + 1] = m ? T(-1) : T(1);
+        cx[q + 1] = gxs[q];
+        hy[q + 1] = map_axis(gys[q], a.ny, a.bc[2], a.bc[3], m, nr) == j;
+        sy[q + 1] = m ? T(-1) : T(1);
+        cy[q + 1] = gys[q];
     }
     T add[3] = {T(0), T(0), T(0)};
     double gE = 0.0, gH = 0.0;
-    for (int u = 0; u < nxc; ++u)
-        for (int v = 0; v < nyc; ++v) {
+#pragma unroll
+    for (int u = 0; u < 5; ++u)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
             if (u == 0 && v == 0) continue;
+            if (!(hx[u] && hy[v])) continue;
             const int64_t p = pd.idx(cx[u], cy[v]);
             // signs: Ez odd in both mirrors, Hx odd in the x mirror, Hy odd in the y mirror
             add[0] += sx[u] * sy[v] * padpsi[((int64_t)b * 3 + 0) * npos + p];
