@@ -50,7 +50,7 @@ typedef enum {
 
 typedef enum { GKS_CART2D = 0, GKS_CART3D = 1, GKS_TRI2D = 2, GKS_TET3D = 3 } gks_mesh_kind;
 /* The perfectly hyperbolic Maxwell (PHM) system (Sec. 2.1) adds the divergence-cleaning
- * potentials phi phi and psi, coupled through chi and gamma (gks_params), to the fields:
+ * potentials phi and psi, coupled through chi and gamma (gks_params), to the fields:
  *   GKS_TM2D_PHM: the TM fields with psi (dpsi/dt + gamma c^2 div H = 0, dH/dt += -gamma
  *   grad psi): (Ez, Hx, Hy, psi).  phi follows div E, which TM fields do not have, so it stays
  *   zero and is not stored.
