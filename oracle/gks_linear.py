@@ -19,8 +19,9 @@ follow the configurations over their full step counts on grids of a few hundred 
 The literal run and this one differ only in rounding order (checked in
 ``tests/test_oracle_linear.py``).
 
-States are (ncells, 6) arrays as in ``gks_oracle``; the map acts on the components ``comps``
-(default: Ez, Hx, Hy in 2D, all six in 3D), field-major: index f * ncells + cell.
+States are (ncells, 6) arrays as in ``gks_oracle`` ((ncells, 8) for the PHM system); the map acts
+on the components ``comps`` (default: Ez, Hx, Hy in 2D, all six in 3D; with PHM also psi in 2D
+and all eight in 3D), field-major: index f * ncells + cell.
 """
 from __future__ import annotations
 
@@ -92,9 +93,18 @@ class LinearStep:
     the literal oracle."""
 
     def __init__(self, mesh, dt, tau, c=1.0, epsinv=None, muinv=None, source=None, comps=None, colors=None,
-                 gradient=O.GRAD_GREEN_GAUSS):
+                 gradient=O.GRAD_GREEN_GAUSS, phm=None):
         self.mesh = mesh
-        self.comps = tuple(comps) if comps is not None else (O.TM if mesh.dim == 2 else ALL)
+        # phm = (chi, gamma): the eight-component PHM state (Sec. 2.1); the TM components then
+        # include psi (column 7), and the 3D ones all eight
+        self.chi, self.gamma = (0.0, 0.0) if phm is None else (float(phm[0]), float(phm[1]))
+        self.width = 6 if phm is None else 8
+        if comps is None:
+            if phm is None:
+                comps = O.TM if mesh.dim == 2 else ALL
+            else:
+                comps = O.TM_PHM if mesh.dim == 2 else tuple(range(8))
+        self.comps = tuple(comps)
         self.dt, self.tau, self.c = dt, tau, c
         self.epsinv, self.muinv, self.gradient = epsinv, muinv, gradient
         self.C = O.coefficients(dt, tau)
@@ -112,7 +122,8 @@ class LinearStep:
             cells, w, J0, tc, sg = source
             J = np.zeros((nc, 3))
             J[np.asarray(cells), 2] = np.asarray(w, dtype=np.float64)   # unit pulse amplitude
-            out = O.step(mesh, np.zeros((nc, 6)), dt, tau, c, epsinv, muinv, J, self.C, gradient)
+            out = O.step(mesh, np.zeros((nc, self.width)), dt, tau, c, epsinv, muinv, J, self.C, gradient,
+                         chi=self.chi, gamma=self.gamma)
             self.b = out[:, list(self.comps)].T.reshape(-1).copy()
 
     def _probe(self, R, colors) -> sp.csr_matrix:
@@ -130,10 +141,10 @@ class LinearStep:
             outside[o] = False
             probe_cells = np.nonzero(colors == col)[0]
             for f, comp in enumerate(comps):
-                U = np.zeros((nc, 6))
+                U = np.zeros((nc, self.width))
                 U[probe_cells, comp] = 1.0
                 out = O.step(mesh, U, self.dt, self.tau, self.c, self.epsinv, self.muinv, None, self.C,
-                             self.gradient)[:, list(comps)]
+                             self.gradient, chi=self.chi, gamma=self.gamma)[:, list(comps)]
                 if np.any(out[outside] != 0.0):
                     raise ValueError("a cell responds to a probe outside its region: the step reaches further "
                                      "than two face hops")
@@ -150,12 +161,12 @@ class LinearStep:
         return np.asarray(U, dtype=np.float64)[:, list(self.comps)].T.reshape(-1).copy()
 
     def unflat(self, v) -> np.ndarray:
-        U = np.zeros((self.mesh.ncells, 6))
+        U = np.zeros((self.mesh.ncells, self.width))
         U[:, list(self.comps)] = np.asarray(v).reshape(len(self.comps), -1).T
         return U
 
     def run(self, U0, nsteps, t0=0.0) -> np.ndarray:
-        """nsteps steps from time t0 (t^n = t0 + n dt) of the state U0 (ncells, 6)."""
+        """nsteps steps from time t0 (t^n = t0 + n dt) of the state U0 (ncells, 6; 8 with PHM)."""
         v = self.flat(U0)
         for n in range(nsteps):
             v = self.A @ v

@@ -79,6 +79,47 @@ def test_map_equals_literal_triangles(gradient):
     assert rel(L.run(U0, 30), ref) <= 1e-13
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_map_equals_literal_phm(dim):
+    """The PHM system (chi, gamma > 0, eight-component state): the map's runs equal the literal
+    runs, in 2D on (Ez, Hx, Hy, psi) and in 3D on all eight components, with a source and a
+    dielectric map."""
+    rng = np.random.default_rng(16 + dim)
+    if dim == 2:
+        mesh = O.cart2d(23, 17, bc=(1, 2, 2, 1))
+        comps, dt, steps = O.TM_PHM, 0.5 / 23, 30
+    else:
+        mesh = O.cart3d(11, 9, 8, bc=(1, 2, 1, 1, 2, 2))
+        comps, dt, steps = tuple(range(8)), (1.0 / 3.0) / 11, 20
+    nc = mesh.ncells
+    U0 = np.zeros((nc, 8))
+    U0[:, list(comps)] = rng.standard_normal((nc, len(comps)))
+    ei = rng.uniform(0.25, 1.0, nc)
+    src = (np.array([nc // 3]), np.array([1.0]), 1.5, 0.02, 0.02)
+    phm = (0.7, 0.9)
+    L = GL.LinearStep(mesh, dt, 0.01 * dt, epsinv=ei, source=src, phm=phm)
+    assert L.comps == tuple(comps)
+    ref = O.run(mesh, U0, steps, dt, 0.01 * dt, epsinv=ei, source=src, chi=phm[0], gamma=phm[1])
+    got = L.run(U0, steps)
+    assert got.shape == (nc, 8)
+    assert rel(got, ref) <= 1e-13
+
+
+def test_map_equals_literal_tetrahedra():
+    """Tetrahedral meshes (greedy colours on the face graph): the map's run equals the literal run
+    on a jittered box around a PEC sphere, with non-reflecting outer faces."""
+    rng = np.random.default_rng(18)
+    wl = I.tet_sphere_workload(n=5, seed=1, nsteps=10)
+    ex = wl.extra
+    mesh = O.tet_mesh(ex["verts"], ex["tets"], ex["face_cells"], ex["face_verts"])
+    nc = mesh.ncells
+    U0 = rng.standard_normal((nc, 6))
+    dt = 2e-3
+    L = GL.LinearStep(mesh, dt, 0.01 * dt)
+    ref = O.run(mesh, U0, 10, dt, 0.01 * dt)
+    assert rel(L.run(U0, 10), ref) <= 1e-13
+
+
 def test_invalid_colouring_is_refused():
     mesh = O.cart2d(10, 9, bc=(1, 1, 1, 1))
     with pytest.raises(ValueError, match="twice"):
