@@ -362,7 +362,8 @@ def phm_leg(torch):
     wl = phm_workload()
     ncell = N * N
     out = {"workload": f"tm_phm_dielectric_nr: PHM TM fields (Ez, Hx, Hy, psi) 4096x4096, the 4096^2 recipe plus "
-                       f"a divergent Hx bump, chi = 0, gamma = 1, {PHM_STEPS} steps, energy every 100", "cells": ncell}
+                       f"a divergent Hx bump, chi = 0, gamma = 1, CFL 0.4, {PHM_STEPS} steps, energy every 100",
+           "cells": ncell}
     for prec in ("fp32", "fp64"):
         s, U, ei = make(torch, wl, prec, energy_every=ENERGY_EVERY)
         el, _ = time_run(torch, s, U, PHM_STEPS, 20)
@@ -474,13 +475,14 @@ C3_PHM_FLOPS_PER_CELL = 2 * 3 * (168 + 72) + 24 + 8 * 4
 
 def cart3d_phm_leg(torch):
     """The 3D workload on the eight PHM fields: 384^3, dielectric blocks, PEC z walls,
-    non-reflecting x/y sides, divergent Ex and Hy bumps, chi = gamma = 1, nu = 1/3."""
+    non-reflecting x/y sides, divergent Ex and Hy bumps, chi = gamma = 1, nu = 0.3 (the 3D PHM step
+    grows above it)."""
     from paper_2412_16845_amd import inputs as I
     from paper_2412_16845_amd.gks import Solver
     wl = I.em_phm_blocks_pec(n=C3_N, seed=0, nsteps=C3_PHM_STEPS)
     ncell = C3_N ** 3
     out = {"workload": f"em_phm_blocks_pec: 3D PHM fields (Ex .. Hz, phi, psi) {C3_N}^3, the 384^3 recipe plus "
-                       f"divergent Ex and Hy bumps, chi = gamma = 1, {C3_PHM_STEPS} steps"}
+                       f"divergent Ex and Hy bumps, chi = gamma = 1, CFL 0.3, {C3_PHM_STEPS} steps"}
     for prec in ("fp32", "fp64"):
         dtype = torch.float64 if prec == "fp64" else torch.float32
         s = Solver("cart3d", n=wl.n, bc=wl.bc, precision=prec, cfl=wl.cfl, tau_over_dt=wl.tau_over_dt,

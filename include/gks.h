@@ -104,7 +104,15 @@ typedef struct {
  *                 (triangles).  c dt / h above the stability limit is rejected (GKS_EINVAL):
  *                 0.5 on 2D grids and triangle meshes, 1/3 on 3D Cartesian grids (the D3Q4
  *                 step grows above it: at 1/2 a Fourier mode gains about 10% per step).
+ *                 With the PHM potentials coupled the Cartesian limits are lower: 0.42 on 2D
+ *                 grids with gamma > 0 (at 0.5 and gamma = 1 a mode gains 11% per step) and
+ *                 0.3 on 3D grids with chi or gamma > 0 (2.6% per step at 1/3).
  *                 Tetrahedral meshes take c dt / (smallest inradius 3|Omega|/surface) <= 0.5.
+ *                 The limits are those of tau -> 0.  On 3D grids tau shrinks the stable range
+ *                 (the free-transport part of the D3Q4 flux has no transverse terms): at
+ *                 tau = 0.01 dt the Maxwell step is stable to 0.32 (at 1/3 a mode gains 2e-5
+ *                 per step, under 1% in 500 steps); at 0.3 a mode gains 1e-4 per step at
+ *                 tau = 0.03 dt and 6e-3 as tau -> infinity.  unstable_growth guards such runs.
  *   tau_over_dt:  collision time tau = tau_over_dt * dt (>= 0; +INFINITY = collisionless).
  *   energy_every: gks_run records the energy every this many steps (0 = never).
  *   unstable_growth: gks_run fails with GKS_EUNSTABLE when a recorded energy exceeds this

@@ -740,12 +740,19 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
         x->dt = (p->dt > 0) ? p->dt : p->cfl * hmin / p->c;
         if (!(x->dt > 0) || !std::isfinite(x->dt)) return bail(fail(x, GKS_EINVAL, "dt must be positive (set dt or cfl)"));
         const double nu = p->c * x->dt / hmin;
-        // 2D: 0.5 is the stability limit of the D2Q4 step.  3D: the D3Q4 step grows above 1/3
-        // (the amplification factor of a Fourier mode exceeds 1 at 0.4 and 0.5 for small tau)
-        const double numax = (nd == 2) ? 0.5 : 1.0 / 3.0;
+        // Largest Courant numbers at which the amplification factor of every Fourier mode
+        // stays <= 1 (tau <= 0.01 dt).  2D: 0.5 for the D2Q4 step; with the psi coupling the
+        // limit falls with gamma (0.49, 0.47, 0.44, 0.42 at gamma = 1/4 .. 1; at 0.5 and
+        // gamma = 1 a mode gains 11% per step).  3D: the D3Q4 step grows above 1/3 (about 10%
+        // per step at 1/2); with the potentials coupled (chi = gamma = 1) above 0.30 (2.6%
+        // per step at 1/3).
+        const bool cleaning = (m->model == GKS_TM2D_PHM && p->gamma > 0.0) ||
+                              (m->model == GKS_EM3D_PHM && (p->chi > 0.0 || p->gamma > 0.0));
+        const double numax = (nd == 2) ? (cleaning ? 0.42 : 0.5) : (cleaning ? 0.3 : 1.0 / 3.0);
+        const char *lim = (nd == 2) ? (cleaning ? "0.42" : "0.5") : (cleaning ? "0.3" : "1/3");
         if (nu > numax * (1 + 1e-12))
-            return bail(fail(x, GKS_EINVAL, "Courant number c dt / h = %g exceeds the stability limit %s of the %dD step",
-                             nu, nd == 2 ? "0.5" : "1/3", nd));
+            return bail(fail(x, GKS_EINVAL, "Courant number c dt / h = %g exceeds the stability limit %s of the %dD %sstep",
+                             nu, lim, nd, cleaning ? "PHM " : ""));
     } else if (m->kind == GKS_TRI2D) {
         if (m->model != GKS_TM2D && m->model != GKS_TM2D_PHM)
             return bail(fail(x, GKS_EINVAL, "triangle meshes carry TM2D or TM2D_PHM fields"));

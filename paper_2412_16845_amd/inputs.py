@@ -138,12 +138,13 @@ def tm_dielectric_nr(nx=4096, ny=None, seed=0, nsteps=1000, cfl=0.5, tau_over_dt
                     (1.0 / eps)[None], None, cfl, tau_over_dt, nsteps, source=src)
 
 
-def tm_phm_dielectric_nr(nx=4096, ny=None, seed=0, nsteps=1000, cfl=0.5, tau_over_dt=0.01, ncircles=64,
+def tm_phm_dielectric_nr(nx=4096, ny=None, seed=0, nsteps=1000, cfl=0.4, tau_over_dt=0.01, ncircles=64,
                          chi=0.0, gamma=1.0, hbump=0.5, pulse: Optional[float] = 1.0, bc=(NONREFLECT,) * 4) -> Workload:
     """The dielectric workload of tm_dielectric_nr carried by the PHM fields (Ez, Hx, Hy, psi):
     the same inclusions, point source and initial Ez pulse, plus a divergence error to clean,
     an Hx Gaussian bump of amplitude hbump (w = 0.05 at (0.65, 0.35)), and psi = 0.  The PHM
-    couplings (chi, gamma) travel in extra["phm"]."""
+    couplings (chi, gamma) travel in extra["phm"].  CFL 0.4: with the psi coupling the 2D step
+    is stable up to 0.42 only (at 0.5 and gamma = 1 a Fourier mode gains 11% per step)."""
     base = tm_dielectric_nr(nx, ny, seed, nsteps, cfl, tau_over_dt, ncircles, pulse, bc)
     ny = base.n[1]
     x, y = centres_2d(nx, ny)
@@ -172,12 +173,13 @@ def em_blocks_pec(n=384, seed=0, nsteps=500, cfl=1.0 / 3.0, tau_over_dt=0.01, nb
                     (1.0 / eps)[None], None, cfl, tau_over_dt, nsteps)
 
 
-def em_phm_blocks_pec(n=384, seed=0, nsteps=500, cfl=1.0 / 3.0, tau_over_dt=0.01, nboxes=32, w=0.05, chi=1.0,
+def em_phm_blocks_pec(n=384, seed=0, nsteps=500, cfl=0.3, tau_over_dt=0.01, nboxes=32, w=0.05, chi=1.0,
                       gamma=1.0, bump=0.5, bc=None) -> Workload:
     """The 3D workload of em_blocks_pec carried by the PHM fields (Ex, Ey, Ez, Hx, Hy, Hz, phi,
     psi), plus divergence errors to clean: an Ex and an Hy Gaussian bump of amplitude `bump`
     (w = 0.05 at (0.3, 0.6, 0.5) and (0.65, 0.35, 0.4)); phi = psi = 0.  The couplings travel in
-    extra["phm"]."""
+    extra["phm"].  CFL 0.3: with the potentials coupled the 3D step is stable up to 0.30 only
+    (at 1/3 and chi = gamma = 1 a Fourier mode gains 2.6% per step)."""
     base = em_blocks_pec(n, seed, nsteps, cfl, tau_over_dt, nboxes, w)
     nx, ny, nz = base.n
     x, y, z = np.meshgrid(*((np.arange(m) + 0.5) / m for m in (nx, ny, nz)), indexing="ij")

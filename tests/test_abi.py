@@ -90,6 +90,11 @@ def _init(gks, **over):
     ({"model": 1, "kind": 1, "n": (8, 8, 8), "cfl": 0.34}, "1/3"),
     ({"model": 3, "kind": 1, "n": (8, 8, 8), "cfl": 0.4}, "1/3"),
     ({"model": 1, "kind": 1, "n": (8, 8, 8), "dt": 0.05}, "1/3"),   # c dt / h = 0.4
+    # with the PHM potentials coupled the limits fall: 0.42 in 2D (gamma > 0), 0.3 in 3D
+    ({"model": 2, "gamma": 1.0, "cfl": 0.5}, "0.42"),
+    ({"model": 2, "gamma": 0.1, "cfl": 0.43}, "0.42"),
+    ({"model": 3, "kind": 1, "n": (8, 8, 8), "chi": 1.0, "cfl": 1.0 / 3.0}, "0.3"),
+    ({"model": 3, "kind": 1, "n": (8, 8, 8), "gamma": 0.2, "cfl": 0.31}, "0.3"),
 ])
 def test_init_rejects_bad_arguments(gks, over, needle):
     st, msg = _init(gks, **over)
@@ -104,6 +109,17 @@ def test_init_accepts_3d_courant_one_third(gks):
     device query."""
     st, msg = _init(gks, model=1, kind=1, n=(8, 8, 8), cfl=1.0 / 3.0)
     assert "1/3" not in msg and "Courant" not in msg, msg
+
+
+@pytest.mark.parametrize("over", [
+    {"model": 2, "gamma": 1.0, "cfl": 0.42},                            # the 2D PHM limit itself
+    {"model": 2, "chi": 1.0, "cfl": 0.5},                               # chi alone leaves TM fields alone
+    {"model": 3, "kind": 1, "n": (8, 8, 8), "chi": 1.0, "gamma": 1.0, "cfl": 0.3},
+    {"model": 3, "kind": 1, "n": (8, 8, 8), "cfl": 1.0 / 3.0},          # chi = gamma = 0: the Maxwell step
+])
+def test_init_accepts_phm_courant_limits(gks, over):
+    st, msg = _init(gks, **over)
+    assert "Courant" not in msg, msg
 
 
 def test_null_arguments(gks):

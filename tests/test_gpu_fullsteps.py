@@ -196,3 +196,86 @@ def test_differentiable_batch_800_steps(torch, c5, precision):
     check("64^2 x 8 probe energy after 800 steps", loss.detach().cpu().numpy(), loss_ref, precision)
     check("64^2 x 8 gradient wrt 1/eps (checkpoints every 50)", E.grad.cpu().numpy(), gE_ref, precision)
     check("64^2 x 8 gradient wrt the initial fields", U0.grad.cpu().numpy(), gU_ref, precision)
+
+
+# ------------------------------------------------------------------ PHM recipes and tetrahedra
+# The PHM workloads (Sec. 2.1 divergence cleaning) over the step counts the bench runs them
+# for, and the tetrahedral workload over its 300 steps, against the probed linear map (with the
+# PHM couplings, pinned to the literal step in test_oracle_linear.py).
+@pytest.fixture(scope="module")
+def phm2d():
+    """The 2D PHM recipe (the dielectric box plus a divergent Hx bump, chi = 0, gamma = 1, CFL 0.4)
+    on 256 x 256 cells, 300 steps."""
+    wl = I.tm_phm_dielectric_nr(nx=256, seed=0, nsteps=300, gamma=1.0)
+    dt = cart_dt(wl)
+    L = GL.LinearStep(oracle_mesh(wl), dt, wl.tau_over_dt * dt, epsinv=wl.epsinv[0].reshape(-1),
+                      source=oracle_source(wl), phm=wl.extra["phm"])
+    ref = L.run(O.from_soa(wl.U0[0].reshape(4, -1), "tm2d_phm"), wl.nsteps)
+    assert np.abs(ref).max() < 4 * np.abs(wl.U0).max()     # a stable run: no mode has grown
+    return wl, dt, O.to_soa(ref, "tm2d_phm").reshape(wl.U0.shape[1:])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_phm_dielectric_box_300_steps(torch, phm2d, precision):
+    wl, dt, ref = phm2d
+    s = solver_for(torch, wl, precision, phm=wl.extra["phm"])
+    assert abs(s.dt - dt) <= 1e-15 * dt
+    s.set_material(dev(torch, wl.epsinv, precision))
+    U = dev(torch, wl.U0, precision)
+    s.run(U, wl.nsteps)
+    check("256^2 PHM dielectric box, 300 steps", U[0].cpu().numpy(), ref, precision)
+
+
+@pytest.fixture(scope="module")
+def phm3d():
+    """The 3D PHM recipe (the PEC blocks plus divergent Ex and Hy bumps, chi = gamma = 1, CFL 0.3)
+    on 32^3 cells, 60 steps."""
+    wl = I.em_phm_blocks_pec(n=32, seed=0, nsteps=60)
+    dt = cart_dt(wl)
+    L = GL.LinearStep(oracle_mesh(wl), dt, wl.tau_over_dt * dt, epsinv=wl.epsinv[0].reshape(-1),
+                      phm=wl.extra["phm"])
+    ref = L.run(O.from_soa(wl.U0[0].reshape(8, -1), "em3d_phm"), wl.nsteps)
+    assert np.abs(ref).max() < 4 * np.abs(wl.U0).max()
+    return wl, dt, O.to_soa(ref, "em3d_phm").reshape(wl.U0.shape[1:])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_phm_pec_blocks_60_steps(torch, phm3d, precision):
+    wl, dt, ref = phm3d
+    s = solver_for(torch, wl, precision, phm=wl.extra["phm"])
+    assert abs(s.dt - dt) <= 1e-15 * dt
+    s.set_material(dev(torch, wl.epsinv, precision))
+    U = dev(torch, wl.U0, precision)
+    s.run(U, wl.nsteps)
+    check("32^3 PHM PEC blocks, 60 steps", U[0].cpu().numpy(), ref, precision)
+
+
+@pytest.fixture(scope="module")
+def tet():
+    """The tetrahedral recipe (jittered cubes of six tetrahedra around a PEC sphere, non-reflecting
+    box, Ez pulse, CFL 0.5 on the smallest inradius) at n = 12, 300 steps; dt = 0.5 x the smallest
+    inradius 3|Omega| / surface."""
+    wl = I.tet_sphere_workload(n=12, seed=0, nsteps=300)
+    ex = wl.extra
+    mesh = O.tet_mesh(ex["verts"], ex["tets"], ex["face_cells"], ex["face_verts"])
+    surf = np.zeros(mesh.ncells)
+    np.add.at(surf, mesh.face_L, mesh.area)
+    inner = mesh.face_R >= 0
+    np.add.at(surf, mesh.face_R[inner], mesh.area[inner])
+    dt = wl.cfl * float(np.min(3.0 * mesh.vol / surf))
+    L = GL.LinearStep(mesh, dt, wl.tau_over_dt * dt)
+    ref = L.run(O.from_soa(wl.U0[0], "em3d"), wl.nsteps)
+    return wl, dt, O.to_soa(ref, "em3d")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tet_sphere_300_steps(torch, tet, precision):
+    from paper_2412_16845_amd.gks import Solver
+    wl, dt, ref = tet
+    ex = wl.extra
+    s = Solver("tet3d", tet=(ex["verts"], ex["tets"], ex["face_cells"], ex["face_verts"]), precision=precision,
+               cfl=wl.cfl, tau_over_dt=wl.tau_over_dt)
+    assert abs(s.dt - dt) <= 1e-14 * dt
+    U = dev(torch, wl.U0, precision)
+    s.run(U, wl.nsteps)
+    check(f"{wl.n[0]} tetrahedra, 300 steps", U[0].cpu().numpy(), ref, precision)

@@ -70,7 +70,7 @@ def test_phm_mixed_boundaries_and_materials(torch, bc, precision):
     x, y = I.centres_2d(nx, ny)
     epsinv = (1.0 / (1.5 + 0.5 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)))[None]
     muinv = (1.0 / (1.2 + 0.3 * np.cos(2 * np.pi * x)))[None]
-    wl = I.Workload("phm_mixed", "cart2d", (nx, ny), (0.0, 0.0), (1.0, 1.0), bc, U0, epsinv, muinv, 0.45, 0.05, 60,
+    wl = I.Workload("phm_mixed", "cart2d", (nx, ny), (0.0, 0.0), (1.0, 1.0), bc, U0, epsinv, muinv, 0.4, 0.05, 60,
                     extra={"phm": (0.3, 0.8)})
     s, U = setup(torch, wl, precision)
     s.run(U, wl.nsteps)
@@ -89,7 +89,7 @@ def test_phm_minimum_and_thin_grids(torch, n, bc, precision):
     U0 = rng.standard_normal((2, 4, ny, nx))
     ei = rng.uniform(0.25, 1.0, (2, ny, nx))
     mi = rng.uniform(0.5, 1.0, (2, ny, nx))
-    wl = I.Workload("phm_thin", "cart2d", (nx, ny), (0.0, 0.0), (1.0, 1.0), bc, U0, ei, mi, 0.5, 0.01, 12,
+    wl = I.Workload("phm_thin", "cart2d", (nx, ny), (0.0, 0.0), (1.0, 1.0), bc, U0, ei, mi, 0.42, 0.01, 12,
                     extra={"phm": (0.5, 1.0)})
     s, U = setup(torch, wl, precision)
     s.run(U, wl.nsteps)
@@ -174,7 +174,7 @@ def random3(n, bc, seed, batch=1, mu=False, tau_hat=0.01, nsteps=6, phm=(0.7, 0.
     U = rng.standard_normal((batch, 8, nz, ny, nx))
     ei = rng.uniform(0.25, 1.0, (batch, nz, ny, nx))
     mi = rng.uniform(0.5, 1.0, (batch, nz, ny, nx)) if mu else None
-    return I.Workload("phm3d", "cart3d", tuple(n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), tuple(bc), U, ei, mi, 1.0 / 3.0,
+    return I.Workload("phm3d", "cart3d", tuple(n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), tuple(bc), U, ei, mi, 0.3,
                       tau_hat, nsteps, source=source, extra={"phm": phm})
 
 

@@ -55,7 +55,8 @@ def _cartesian_case(seed):
     phm = None if (limiter or rng.random() < 0.5) else (float(rng.uniform(0, 1)), float(rng.uniform(0, 1)))
     nf = (4 if phm else 3) if nd == 2 else (8 if phm else 6)
     tau_hat = [0.0, 0.01, 0.3, np.inf][rng.integers(4)]
-    cfl = 0.5 if nd == 2 else 1.0 / 3.0
+    # the stability limits: lower with the PHM potentials coupled (both couplings drawn > 0)
+    cfl = (0.42 if phm else 0.5) if nd == 2 else (0.3 if phm else 1.0 / 3.0)
     grid = (n[1], n[0]) if nd == 2 else (n[2], n[1], n[0])
     U0 = rng.standard_normal((batch, nf) + grid)
     ei = rng.uniform(0.25, 1.0, (batch,) + grid) if rng.random() < 0.7 else None
