@@ -459,26 +459,49 @@ __global__ __launch_bounds__(ADJ_BLOCK) void adj2d_fold_kernel(Cart2DAdjArgs<T> 
         sy[q + 1] = m ? T(-1) : T(1);
         cy[q + 1] = gys[q];
     }
+    // the cell's own values first, so that their loads overlap the gathers
+    T own[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) own[f] = a.lam_out[((int64_t)b * 3 + f) * ncell + t];
+    const double oE = a.g_epsinv ? a.g_epsinv[(int64_t)b * ncell + t] : 0.0;
+    const double oH = a.g_muinv ? a.g_muinv[(int64_t)b * ncell + t] : 0.0;
     T add[3] = {T(0), T(0), T(0)};
     double gE = 0.0, gH = 0.0;
+    // The 24 ghost candidates (u, v) != (0, 0), in two halves of 12.  A half's gathers are all
+    // issued before any is used (a candidate that does not image this cell reads position 0 and
+    // adds a selected zero; a select rather than a branch, so that the loads are not moved into
+    // branches), so the kernel waits on memory twice rather than once per ghost that images the
+    // cell; the sums keep the (u, v) order.
 #pragma unroll
-    for (int u = 0; u < 5; ++u)
+    for (int half = 0; half < 2; ++half) {
+        T vp[12][3];
+        double vg[12][2];
+        bool ok[12];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            if (u == 0 && v == 0) continue;
-            if (!(hx[u] && hy[v])) continue;
-            const int64_t p = pd.idx(cx[u], cy[v]);
-            // signs: Ez odd in both mirrors, Hx odd in the x mirror, Hy odd in the y mirror
-            add[0] += sx[u] * sy[v] * padpsi[((int64_t)b * 3 + 0) * npos + p];
-            add[1] += sx[u] * padpsi[((int64_t)b * 3 + 1) * npos + p];
-            add[2] += sy[v] * padpsi[((int64_t)b * 3 + 2) * npos + p];
-            gE += padg[((int64_t)b * 2 + 0) * npos + p];
-            gH += padg[((int64_t)b * 2 + 1) * npos + p];
+        for (int m = 0; m < 12; ++m) {
+            const int k = 1 + 12 * half + m, u = k / 5, v = k % 5;
+            ok[m] = hx[u] && hy[v];
+            const int64_t p = ok[m] ? pd.idx(cx[u], cy[v]) : 0;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) vp[m][f] = padpsi[((int64_t)b * 3 + f) * npos + p];
+            vg[m][0] = padg[((int64_t)b * 2 + 0) * npos + p];
+            vg[m][1] = padg[((int64_t)b * 2 + 1) * npos + p];
         }
 #pragma unroll
-    for (int f = 0; f < 3; ++f) a.lam_out[((int64_t)b * 3 + f) * ncell + t] += add[f];
-    if (a.g_epsinv) a.g_epsinv[(int64_t)b * ncell + t] += gE;
-    if (a.g_muinv) a.g_muinv[(int64_t)b * ncell + t] += gH;
+        for (int m = 0; m < 12; ++m) {
+            const int k = 1 + 12 * half + m, u = k / 5, v = k % 5;
+            // signs: Ez odd in both mirrors, Hx odd in the x mirror, Hy odd in the y mirror
+            add[0] += ok[m] ? sx[u] * sy[v] * vp[m][0] : T(0);
+            add[1] += ok[m] ? sx[u] * vp[m][1] : T(0);
+            add[2] += ok[m] ? sy[v] * vp[m][2] : T(0);
+            gE += ok[m] ? vg[m][0] : 0.0;
+            gH += ok[m] ? vg[m][1] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) a.lam_out[((int64_t)b * 3 + f) * ncell + t] = own[f] + add[f];
+    if (a.g_epsinv) a.g_epsinv[(int64_t)b * ncell + t] = oE + gE;
+    if (a.g_muinv) a.g_muinv[(int64_t)b * ncell + t] = oH + gH;
 }
 
 // Material gradient of the explicit source: U'_Ez += (1/eps) A, A = dt S_z, so
