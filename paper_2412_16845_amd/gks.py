@@ -120,6 +120,10 @@ class Solver:
     phm: None, or (chi, gamma) for the perfectly hyperbolic Maxwell system: the fields become
     (Ez, Hx, Hy, psi) in 2D (Cartesian or triangles) and (Ex, Ey, Ez, Hx, Hy, Hz, phi, psi) in
     3D, with divergence errors of E and H carried off at chi c and gamma c.
+    cfl: c dt / h (h the smallest cell width, or the smallest inradius on unstructured meshes),
+    used when dt is 0.  The library refuses values above the step's stability limit: 0.5 on 2D
+    grids and unstructured meshes, 1/3 on 3D grids, and with the PHM couplings nonzero 0.42 on
+    2D grids and 0.3 on 3D grids.
     """
 
     def __init__(self, kind: str = "cart2d", n: Sequence[int] = (64, 64), lo=None, hi=None,
