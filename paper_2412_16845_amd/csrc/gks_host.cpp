@@ -38,6 +38,8 @@ struct gks_ctx {
     int32_t ntile_rows = 0;         // Cartesian 2D: tile rows of the step (entries of d_tiles)
     int32_t tiles_per_band = 0;     // Cartesian 2D: entries per band (one band per XCD)
     int32_t *d_tiles = nullptr;     // Cartesian 2D: [ntile_rows][4] tile rows in dispatch order
+    int32_t pair_tiles_per_band = 0;  // Cartesian 2D TM: the paired (two-step) kernel's table,
+    int32_t *d_pair_tiles = nullptr;  // null where that kernel does not apply
     int32_t tile_z = 64;            // planes per workgroup tile (Cartesian 3D)
     const void *epsinv = nullptr, *muinv = nullptr;
 
@@ -293,6 +295,65 @@ std::vector<int32_t> gks::cart2d_tile_table(int ny, int batch, int precision, in
     return out;
 }
 
+std::vector<int32_t> gks::cart2d_pair_tile_table(int ny, int batch, int ntx, int32_t &tiles_per_band)
+{
+    // The single-step table's bands and tile heights, with two constraints of the paired
+    // kernel: a tile reads the intermediate state two rows beyond each end, so a cut between
+    // tiles never falls one row from a side (it moves one row on), and a tile that touches the
+    // lower side marches down, one that touches the upper side up (no tile may touch both).
+    const int tall = GKS_TILE_TALL, shrt = GKS_TILE_SHORT;
+    const double frac = GKS_TILE_SHORT_FRAC;
+    tiles_per_band = 0;
+    if (ny < 8) return {};
+    const int64_t total = (int64_t)ny * batch;
+    auto fix = [&](int64_t r) {   // a cut at row 1 or ny - 1 of an item moves one row on
+        const int64_t y = r % ny;
+        return (y == 1 || y == ny - 1) ? r + 1 : r;
+    };
+    std::vector<int64_t> cut(NBANDS + 1);
+    for (int band = 0; band <= NBANDS; ++band) cut[band] = std::min(fix(total * band / NBANDS), total);
+    std::vector<std::vector<int32_t>> bands(NBANDS);
+    size_t most = 0;
+    for (int band = 0; band < NBANDS; ++band) {
+        const int64_t r0 = cut[band], r1 = cut[band + 1];
+        const int64_t split = r1 - (int64_t)(frac * (double)(r1 - r0) + 0.5);
+        std::vector<int32_t> &tab = bands[band];
+        int64_t r = r0;
+        int k = 0;
+        while (r < r1) {
+            const int64_t b = r / ny, y = r % ny;
+            const int64_t h = r < split ? tall : shrt;
+            const int64_t lim = std::min(r1, (b + 1) * ny);
+            int64_t e = std::min(r + h, lim);
+            if (e < lim) e = std::min(fix(e), lim);
+            const int64_t ye = y + (e - r);
+            int dn = k++ & 1;
+            if (y == 0) dn = 1;
+            if (ye == ny) dn = 0;
+            if (y == 0 && ye == ny) return {};
+            if ((y != 0 && y < 2) || (ye != ny && ye > ny - 2)) return {};
+            tab.push_back((int32_t)b);
+            tab.push_back((int32_t)y);
+            tab.push_back((int32_t)ye);
+            tab.push_back(dn);
+            r = e;
+        }
+        most = std::max(most, tab.size() / 4);
+    }
+    size_t per = most;
+    while ((per * (size_t)ntx) % CART2D_WAVES_PER_BLOCK) ++per;
+    std::vector<int32_t> out;
+    for (auto &tab : bands) {
+        out.insert(out.end(), tab.begin(), tab.end());
+        for (size_t q = tab.size() / 4; q < per; ++q) {
+            const int32_t pad[4] = {-1, 0, 0, 0};
+            out.insert(out.end(), pad, pad + 4);
+        }
+    }
+    tiles_per_band = (int32_t)per;
+    return out;
+}
+
 int gks::cart3d_pick_tile_z(int nx, int ny, int nz, int batch, int ncu, int precision, int nfields)
 {
     // One workgroup per compute unit at a time (its LDS tile takes most of the unit): the step
@@ -357,6 +418,40 @@ gks_status step_cart2d(gks_ctx *x, const void *Uin, void *Uout, double tn)
                                      (int32_t)x->batch, 0, x->d_src_cells, x->d_src_w, amp, (int32_t)ns, x->stream);
         if (e) return hip_fail(x, e, "source launch");
     }
+    return GKS_OK;
+}
+
+// The steps at tn and tn1 in one launch of the paired kernel (gks_run, where d_pair_tiles is set
+// and at most one source cell is given): the same results as two calls of step_cart2d, bit for
+// bit.
+template <typename T>
+gks_status step2_cart2d(gks_ctx *x, const void *Uin, void *Uout, double tn, double tn1)
+{
+    Cart2DArgs<T> a;
+    std::memset(&a, 0, sizeof a);
+    a.U = (const T *)Uin;
+    a.Unew = (T *)Uout;
+    a.epsinv = (const T *)x->epsinv;
+    a.muinv = (const T *)x->muinv;
+    a.nx = (int32_t)x->n[0];
+    a.ny = (int32_t)x->n[1];
+    a.batch = (int32_t)x->batch;
+    for (int i = 0; i < 4; ++i) a.bc[i] = x->bc[i];
+    a.ntx = (a.nx + cart2d_pair_tile_x(x->prec) - 1) / cart2d_pair_tile_x(x->prec);
+    a.nty = x->pair_tiles_per_band;
+    a.tiles = x->d_pair_tiles;
+    a.nfields = x->nfields;
+    a.ops = x->d_ops;
+    a.limiter = x->limiter;
+    a.src_row = -1;
+    if (x->src_cells.size() == 1) {   // times formed as gks_run forms them for single steps
+        a.src_row = (int32_t)(x->src_cells[0] / x->n[0]);
+        a.src_col = (int32_t)(x->src_cells[0] % x->n[0]);
+        a.src_amp = -x->dt * source_pulse(x, tn) * x->src_w[0];
+        a.src_amp2 = -x->dt * source_pulse(x, tn1) * x->src_w[0];
+    }
+    const int e = launch_cart2d_pair<T>(a, x->stream);
+    if (e) return hip_fail(x, e, "GKS paired step launch");
     return GKS_OK;
 }
 
@@ -822,6 +917,21 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
             return bail(fail(x, GKS_ENOMEM, "cannot allocate the tile table"));
         const int e = hipMemcpy(x->d_tiles, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice);
         if (e) return bail(hip_fail(x, e, "tile table upload"));
+        // the paired kernel: TM fields, no limiter, no periodic side
+        bool periodic = false;
+        for (int i = 0; i < 4; ++i) periodic = periodic || x->bc[i] == GKS_BC_PERIODIC;
+        if (x->model == GKS_TM2D && x->limiter == GKS_LIMITER_NONE && !periodic) {
+            const int ntx2 = (int)((x->n[0] + cart2d_pair_tile_x(x->prec) - 1) / cart2d_pair_tile_x(x->prec));
+            const std::vector<int32_t> tab2 =
+                cart2d_pair_tile_table((int)x->n[1], (int)x->batch, ntx2, x->pair_tiles_per_band);
+            if (!tab2.empty()) {
+                if (hipMalloc((void **)&x->d_pair_tiles, tab2.size() * sizeof(int32_t)) != hipSuccess)
+                    return bail(fail(x, GKS_ENOMEM, "cannot allocate the paired tile table"));
+                const int e2 = hipMemcpy(x->d_pair_tiles, tab2.data(), tab2.size() * sizeof(int32_t),
+                                         hipMemcpyHostToDevice);
+                if (e2) return bail(hip_fail(x, e2, "paired tile table upload"));
+            }
+        }
     }
     if (x->kind == GKS_CART2D && x->model == GKS_TM2D) {
         // the device address of the allocation-free adjoint's static scratch (once per device)
@@ -855,6 +965,7 @@ extern "C" gks_status gks_destroy(gks_ctx *ctx)
     if (!ctx) return GKS_OK;
     if (ctx->d_ops) hipFree(ctx->d_ops);
     if (ctx->d_tiles) hipFree(ctx->d_tiles);
+    if (ctx->d_pair_tiles) hipFree(ctx->d_pair_tiles);
     if (ctx->pingpong) hipFree(ctx->pingpong);
     if (ctx->d_partial) hipFree(ctx->d_partial);
     if (ctx->d_out) hipFree(ctx->d_out);
@@ -998,11 +1109,20 @@ extern "C" gks_status gks_run(gks_ctx *ctx, void *U, int64_t nsteps, double t0, 
     int64_t nenq = 0, nchecked = 0;   // records enqueued / checked
     gks_status bad = GKS_OK;
     int e = 0;
-    for (int64_t k = 0; k < nsteps && bad == GKS_OK; ++k) {
-        st = do_step(ctx, cur, nxt, t0 + (double)k * ctx->dt);
+    // Two steps per launch where the paired kernel applies, except across an energy record.
+    const bool pair = ctx->kind == GKS_CART2D && ctx->d_pair_tiles && ctx->src_cells.size() <= 1;
+    for (int64_t k = 0; k < nsteps && bad == GKS_OK;) {
+        const bool two = pair && k + 1 < nsteps && !(every && (k + 1) % every == 0);
+        const double tk = t0 + (double)k * ctx->dt, tk1 = t0 + (double)(k + 1) * ctx->dt;
+        if (two)
+            st = ctx->prec == GKS_FP64 ? step2_cart2d<double>(ctx, cur, nxt, tk, tk1)
+                                       : step2_cart2d<float>(ctx, cur, nxt, tk, tk1);
+        else
+            st = do_step(ctx, cur, nxt, tk);
         if (st) return st;
         std::swap(cur, nxt);
-        if (every && (k + 1) % every == 0) {
+        k += two ? 2 : 1;
+        if (every && k % every == 0) {
             const int64_t r = nenq++;
             double *dst = ctx->d_out + r * ctx->batch;
             st = launch_energy_into(ctx, cur, dst);

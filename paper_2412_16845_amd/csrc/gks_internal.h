@@ -72,6 +72,7 @@ struct Cart2DArgs {
     int32_t src_row, src_col; // one point source applied inside the step (src_row < 0: none)
     double src_amp;           // its dt * S_z = -dt * J_z(t^n) (before the 1/eps factor)
     int32_t limiter;          // 0: central differences, 1: minmod-limited slopes
+    double src_amp2;          // the paired kernel: the source amplitude of its second step
 };
 
 // Arguments of the Cartesian 3D (six-field) step kernel.
@@ -196,6 +197,9 @@ struct Cart2DAdjArgs {
 
 // Launchers (defined in the .hip files).  Return a hipError_t as int.
 template <typename T> int launch_cart2d_step(const Cart2DArgs<T> &a, void *stream);
+// Two steps in one launch (TM fields, no limiter, no periodic side, at most one source cell;
+// a.tiles from cart2d_pair_tile_table, a.ntx from cart2d_pair_tile_x).
+template <typename T> int launch_cart2d_pair(const Cart2DArgs<T> &a, void *stream);
 // Adjoint of one 2D step.  Scratch (device), over the npos = adjoint_ring_positions(nx, ny)
 // ghost positions around the grid: padpsi [batch][3][npos] of T and padg [batch][2][npos]
 // doubles; every entry is written by the step's first kernel before its second reads it, so
@@ -228,6 +232,11 @@ int cart2d_tile_x(int precision);
 constexpr int NBANDS = 8;
 constexpr int CART2D_WAVES_PER_BLOCK = 4;
 std::vector<int32_t> cart2d_tile_table(int ny, int batch, int precision, int ntx, int32_t &tiles_per_band);
+// Output columns per strip of the paired kernel, and its tile table (same layout as above): the
+// first tile row of every batch item marches down and the last up, and every tile keeps two
+// rows away from a side it does not touch.  Empty when the grid is too small for it.
+int cart2d_pair_tile_x(int precision);
+std::vector<int32_t> cart2d_pair_tile_table(int ny, int batch, int ntx, int32_t &tiles_per_band);
 
 // Energy: partial sums per (batch, block) then a fixed-order final sum; all FP64.
 // Fields [0, nE) are E (weight eps), [nE, nE + nH) are H (weight mu), the rest potentials (1).

@@ -339,6 +339,364 @@ struct Strip2D {
     }
 };
 
+// ------------------------------------------------------------------ two steps per launch
+// The paired kernel runs two consecutive steps of the TM fields in one march, so that the
+// fields are read and written once per two steps.  Stage 1 is the march above over a strip with
+// four halo columns and a tile widened by two rows on each side.  Every row it finishes (the
+// state after the first step, rounded to the storage type as a stored state would be) enters
+// stage 2, a second march of the same form that takes its rows from registers instead of
+// memory and writes the state after the second step.  Both stages do the single-step kernel's
+// arithmetic in its order, so the two kernels give the same results bit for bit.
+// Ghost values of the intermediate state are formed from its own cells, as the loads form them
+// for a stored state: along x from the boundary column held by another lane of the same wave,
+// along y from the last two rows stage 1 finished (so a tile that touches the lower side marches
+// down and one that touches the upper side marches up).  Periodic sides would need
+// intermediate values from other waves: those grids take the single-step kernel.
+constexpr int PAIR_HALO = 4;
+template <typename T>
+constexpr int pair_out_cols() { return WAVE * cols_per_lane<T>() - 2 * PAIR_HALO; }
+
+// v of the lane whose byte address (4 x lane) is given; all lanes take part (the asm keeps
+// the move out of any branch, where lanes switched off would read as zero)
+__device__ __forceinline__ float lane_fetch(float v, int addr)
+{
+    int r = __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v));
+    asm volatile("" : "+v"(r));
+    return __builtin_bit_cast(float, r);
+}
+__device__ __forceinline__ double lane_fetch(double v, int addr)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffll));
+    int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+    asm volatile("" : "+v"(lo), "+v"(hi));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T, int NC, bool HAS_EPS, bool HAS_MU, bool BND>
+struct Pair2D {
+    static constexpr int NF = 3;
+    using S = Strip2D<T, NC, NF, HAS_EPS, HAS_MU, BND, false>;
+    using Row = Row2D<T, NC, NF>;
+    using OpT = FaceOpTM<T>;
+    static constexpr int CH2 = S::CH2;
+    static constexpr bool HM = S::HM;
+    static constexpr int OPS0 = S::OPS0;
+    S s;              // the strip: buffer resources, column maps, stage 1's loads, stage 2's writers
+    int ylo, yhi;     // the rows stage 1 reads (its loads are clamped to them)
+    int gaddr[NC];    // boundary strips: the lane (byte address) holding each ghost column's image
+    int gk[NC];       // ... and the column of that lane
+    bool gcol[NC];    // a ghost column whose intermediate value stage 2 reads
+
+    // One row step of a march whose window holds rows Rs = q-2s, Rc = q-s, Rn = q: the
+    // differences of Rc, the horizontal face between Rs and Rc, and from the third step on the
+    // vertical faces of Rs and its new values nv.  Returns whether nv was formed.
+    template <bool DN>
+    __device__ __forceinline__ bool stage(int i, int q, double amp, const Row &Rs, const Row &Rc, const Row &Rn,
+                                          T (&Ds)[NC][2 * NF], T (&Dc)[NC][2 * NF], T (&fyP)[NC][NF],
+                                          T (&fyN)[NC][NF], T (&nv)[NC][NF]) const
+    {
+        constexpr int sd = DN ? -1 : 1;
+        const Cart2DArgs<T> &a = s.a;
+        const OpT *ops = (const OpT *)a.ops;
+        const auto opy = scalar_ptr_after(ops + OPS0 + 1, fyP[0][0]);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const T rnext = from_right(Rc.u[0][f]);
+            const T lprev = from_left(Rc.u[NC - 1][f]);
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                const T right = (k + 1 < NC) ? Rc.u[k + 1 < NC ? k + 1 : 0][f] : rnext;
+                const T left = (k > 0) ? Rc.u[k > 0 ? k - 1 : 0][f] : lprev;
+                Dc[k][f] = right - left;
+                Dc[k][NF + f] = DN ? Rs.u[k][f] - Rn.u[k][f] : Rn.u[k][f] - Rs.u[k][f];
+            }
+        }
+        if (i < 1) return false;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const Row &RL = DN ? Rc : Rs;
+            const Row &RR = DN ? Rs : Rc;
+            const T(&DL)[NC][2 * NF] = DN ? Dc : Ds;
+            const T(&DR)[NC][2 * NF] = DN ? Ds : Dc;
+            const bool zl = BND && RL.nr[k], zr = BND && RR.nr[k];
+            T w[6 * NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                w[f] = zl ? T(0) : RL.u[k][f];
+                w[NF + f] = zr ? T(0) : RR.u[k][f];
+                w[2 * NF + f] = zl ? T(0) : DL[k][NF + f];
+                w[3 * NF + f] = zl ? T(0) : DL[k][f];
+                w[4 * NF + f] = zr ? T(0) : DR[k][NF + f];
+                w[5 * NF + f] = zr ? T(0) : DR[k][f];
+            }
+            apply_op<PatTMy, CH2, HM>(w, RL.mE[k] + RR.mE[k], HM ? RL.mH[k] + RR.mH[k] : T(2), opy, fyN[k]);
+        }
+        if (i < 2) return false;
+        const auto opx = scalar_ptr_after(ops + OPS0, fyN[NC - 1][2]);
+        T ul[NC][NF], dl[NC][2 * NF];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const bool z = BND && Rs.nr[k];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) ul[k][f] = z ? T(0) : Rs.u[k][f];
+#pragma unroll
+            for (int f = 0; f < 2 * NF; ++f) dl[k][f] = z ? T(0) : Ds[k][f];
+        }
+        T fx[NC][NF];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            constexpr int last = NC - 1;
+            const int kr = (k + 1 < NC) ? k + 1 : 0;
+            T v[6 * NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                v[f] = ul[k][f];
+                v[NF + f] = (k < last) ? ul[kr][f] : from_right(ul[0][f]);
+                v[2 * NF + f] = dl[k][f];
+                v[3 * NF + f] = dl[k][NF + f];
+                v[4 * NF + f] = (k < last) ? dl[kr][f] : from_right(dl[0][f]);
+                v[5 * NF + f] = (k < last) ? dl[kr][NF + f] : from_right(dl[0][NF + f]);
+            }
+            const T mEr = (k < last) ? Rs.mE[kr] : from_right(Rs.mE[0]);
+            const T mHr = !HM ? T(1) : (k < last) ? Rs.mH[kr] : from_right(Rs.mH[0]);
+            apply_op<PatTMx, CH2, HM>(v, Rs.mE[k] + mEr, Rs.mH[k] + mHr, opx, fx[k]);
+        }
+        const int row = q - 2 * sd;
+        double src[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) src[k] = (row == a.src_row && s.gx0 + k == a.src_col) ? amp : 0.0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const double fr = (double)fx[k][f];
+                const double fl = (double)((k > 0) ? fx[k > 0 ? k - 1 : 0][f] : from_left(fx[NC - 1][f]));
+                const double fu = (double)(DN ? fyP[k][f] : fyN[k][f]);
+                const double fd = (double)(DN ? fyN[k][f] : fyP[k][f]);
+                const double div = (fr - fl) + (fu - fd);
+                const double m = (f == 0) ? (double)Rs.mE[k] : (double)Rs.mH[k];
+                const double add = (f == 0) ? src[k] : 0.0;
+                nv[k][f] = (T)fma(m, add - div, (double)Rs.u[k][f]);
+            }
+        }
+        return true;
+    }
+
+    __device__ __forceinline__ void store(int row, const T (&nv)[NC][NF]) const
+    {
+        const Cart2DArgs<T> &a = s.a;
+        const uint32_t rowc = (uint32_t)row * (uint32_t)a.nx;
+        if constexpr (!BND) {
+            if (s.writer[0]) {
+                const uint32_t so = (rowc + (uint32_t)s.x0) * (uint32_t)sizeof(T);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    if constexpr (NC == 2) buf_store_f2(make_float2(nv[0][f], nv[1][f]), s.rO, s.vlane, so + f * s.fbytes);
+                    else buf_store(nv[0][f], s.rO, s.vlane, so + f * s.fbytes);
+                }
+            }
+        } else {
+            const uint32_t so = rowc * (uint32_t)sizeof(T);
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+                if (s.writer[k]) {
+                    const uint32_t vo = (uint32_t)(s.gx0 + k) * (uint32_t)sizeof(T);
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) buf_store(nv[k][f], s.rO, vo, so + f * s.fbytes);
+                }
+        }
+    }
+
+    // Stage-1 step i (window head q = qs + s i) and, from i = 4 on, stage-2 step i - 4, whose
+    // window (Bs, Bc, Bn) holds the intermediate rows formed at steps i - 2, i - 1 and i.
+    // h0 and h1 hold the last two real intermediate rows (h0 the later one, row hrow).
+    template <bool DN>
+    __device__ __forceinline__ void pstep(int i, int qs, Row &Rs, Row &Rc, Row &Rn, Row &Rp, T (&Ds)[NC][2 * NF],
+                                          T (&Dc)[NC][2 * NF], T (&fyP)[NC][NF], T (&fyN)[NC][NF], Row &Bs,
+                                          Row &Bc, Row &Bn, T (&Es)[NC][2 * NF], T (&Ec)[NC][2 * NF],
+                                          T (&gP)[NC][NF], T (&gN)[NC][NF], T (&h0)[NC][NF], T (&h1)[NC][NF],
+                                          int &hrow) const
+    {
+        constexpr int sd = DN ? -1 : 1;
+        const Cart2DArgs<T> &a = s.a;
+        const int q = qs + sd * i;
+        s.load(min(max(q + sd * PF, ylo), yhi), Rp);
+        T nv[NC][NF];
+        if (!stage<DN>(i, q, a.src_amp, Rs, Rc, Rn, Ds, Dc, fyP, fyN, nv)) return;
+        const int r = q - 2 * sd;   // the intermediate row just formed
+        if constexpr (BND) {
+            // ghost columns: the (mirror) image of a column of the same row; x mirror: Ez and Hx odd
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                T got[NC];
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    T from[NC];
+#pragma unroll
+                    for (int kk = 0; kk < NC; ++kk) from[kk] = lane_fetch(nv[kk][f], gaddr[k]);
+                    T v = from[0];
+#pragma unroll
+                    for (int kk = 1; kk < NC; ++kk) v = (gk[k] == kk) ? from[kk] : v;
+                    got[k] = (f < 2) ? v * s.sgx[k] : v;
+                }
+#pragma unroll
+                for (int k = 0; k < NC; ++k) nv[k][f] = gcol[k] ? got[k] : nv[k][f];
+            }
+            if (r < 0 || r >= a.ny) {
+                // a ghost row: the (mirror) image of one of the last two real rows; y mirror: Ez and
+                // Hy odd
+                bool mir, nry;
+                const int m = map_axis(r, a.ny, a.bc[2], a.bc[3], mir, nry);
+                const bool last = m == hrow;
+                const T sg = mir ? T(-1) : T(1);
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    nv[k][0] = (last ? h0[k][0] : h1[k][0]) * sg;
+                    nv[k][1] = last ? h0[k][1] : h1[k][1];
+                    nv[k][2] = (last ? h0[k][2] : h1[k][2]) * sg;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < NC; ++k)
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+                        h1[k][f] = h0[k][f];
+                        h0[k][f] = nv[k][f];
+                    }
+                hrow = r;
+            }
+        }
+        // the row enters stage 2 with the materials and ghost flags of its cells
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) Bn.u[k][f] = nv[k][f];
+            Bn.mE[k] = Rs.mE[k];
+            Bn.mH[k] = Rs.mH[k];
+            Bn.nr[k] = Rs.nr[k];
+        }
+        if (i < 4) return;
+        T nv2[NC][NF];
+        if (!stage<DN>(i - 4, r, a.src_amp2, Bs, Bc, Bn, Es, Ec, gP, gN, nv2)) return;
+        store(r - 2 * sd, nv2);
+    }
+
+    // March the tile (rows y0 .. y1-1 written): stage 1 forms the intermediate rows y0-2 ..
+    // y1+1, upwards (DN false) or downwards.
+    template <bool DN>
+    __device__ __forceinline__ void run() const
+    {
+        constexpr int sd = DN ? -1 : 1;
+        const int y0 = s.y0, y1 = s.y1;
+        Row R0, R1, R2, R3, R4, R5, B0, B1, B2;
+        T D0[NC][2 * NF], D1[NC][2 * NF], E0[NC][2 * NF], E1[NC][2 * NF];
+        T F0[NC][NF], F1[NC][NF], G0[NC][NF], G1[NC][NF], H0[NC][NF], H1[NC][NF];
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+#pragma unroll
+            for (int f = 0; f < NF; ++f) F0[k][f] = F1[k][f] = G0[k][f] = G1[k][f] = H0[k][f] = H1[k][f] = T(0);
+        int hrow = -1000;
+        const int Y0 = y0 - 2, Y1 = y1 + 2;          // intermediate rows formed: [Y0, Y1)
+        const int qs = DN ? Y1 - 1 : Y0;
+        auto ld = [&](int y, Row &R) { s.load(min(max(y, ylo), yhi), R); };
+        ld(qs - 2 * sd, R0);
+        ld(qs - sd, R1);
+        ld(qs, R2);
+        ld(qs + sd, R3);
+        ld(qs + 2 * sd, R4);
+        const int n = Y1 - Y0 + 2;
+        for (int i = 0; i < n; i += 6) {
+            pstep<DN>(i, qs, R0, R1, R2, R5, D0, D1, F0, F1, B1, B2, B0, E0, E1, G0, G1, H0, H1, hrow);
+            if (i + 1 >= n) break;
+            pstep<DN>(i + 1, qs, R1, R2, R3, R0, D1, D0, F1, F0, B2, B0, B1, E1, E0, G1, G0, H0, H1, hrow);
+            if (i + 2 >= n) break;
+            pstep<DN>(i + 2, qs, R2, R3, R4, R1, D0, D1, F0, F1, B0, B1, B2, E0, E1, G0, G1, H0, H1, hrow);
+            if (i + 3 >= n) break;
+            pstep<DN>(i + 3, qs, R3, R4, R5, R2, D1, D0, F1, F0, B1, B2, B0, E1, E0, G1, G0, H0, H1, hrow);
+            if (i + 4 >= n) break;
+            pstep<DN>(i + 4, qs, R4, R5, R0, R3, D0, D1, F0, F1, B2, B0, B1, E0, E1, G0, G1, H0, H1, hrow);
+            if (i + 5 >= n) break;
+            pstep<DN>(i + 5, qs, R5, R0, R1, R4, D1, D0, F1, F0, B0, B1, B2, E1, E0, G1, G0, H0, H1, hrow);
+        }
+    }
+};
+
+template <typename T, bool HAS_EPS, bool HAS_MU>
+__global__ __launch_bounds__(STEP2D_BLOCK, 2) void cart2d_pair_kernel(Cart2DArgs<T> a)
+{
+    constexpr int NC = cols_per_lane<T>();
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int band = blockIdx.x % NBANDS;
+    const int wave = (blockIdx.x / NBANDS) * (STEP2D_BLOCK / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int tl = wave / a.ntx;
+    if (tl >= a.nty) return;
+    const int tx = wave - tl * a.ntx;
+    const int t = band * a.nty + tl;
+    const int b = __builtin_amdgcn_readfirstlane(a.tiles[4 * t]);
+    if (b < 0) return;
+    const int y0 = __builtin_amdgcn_readfirstlane(a.tiles[4 * t + 1]);
+    const int y1 = __builtin_amdgcn_readfirstlane(a.tiles[4 * t + 2]);
+    const bool down = __builtin_amdgcn_readfirstlane(a.tiles[4 * t + 3]) != 0;
+
+    const int64_t ncell = (int64_t)a.nx * a.ny;
+    const uint32_t fbytes = (uint32_t)(ncell * (int64_t)sizeof(T));
+    const Rsrc rU = make_rsrc(a.U + (int64_t)b * 3 * ncell, 3ull * fbytes);
+    const Rsrc rO = make_rsrc(a.Unew + (int64_t)b * 3 * ncell, 3ull * fbytes);
+    const Rsrc rE = make_rsrc(HAS_EPS ? a.epsinv + (int64_t)b * ncell : a.U, fbytes);
+    const Rsrc rM = make_rsrc(HAS_MU ? a.muinv + (int64_t)b * ncell : a.U, fbytes);
+
+    const int x0 = tx * pair_out_cols<T>() - PAIR_HALO;
+    const int gx0 = x0 + NC * lane;
+    const uint32_t vlane = (uint32_t)(NC * lane) * (uint32_t)sizeof(T);
+    const int ylo = max(y0 - 4, -2), yhi = min(y1 + 3, a.ny + 1);
+
+    const bool interior = x0 >= 0 && x0 + WAVE * NC - 1 <= a.nx - 1 && y0 - 4 >= 0 && y1 + 3 <= a.ny - 1;
+    if (interior) {
+        Pair2D<T, NC, HAS_EPS, HAS_MU, false> p{{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0}};
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            p.s.vx[k] = 0;
+            p.s.sgx[k] = T(1);
+            p.s.nrx[k] = false;
+            p.s.writer[k] = NC * lane + k >= PAIR_HALO && NC * lane + k < WAVE * NC - PAIR_HALO;
+            p.gaddr[k] = 0;
+            p.gk[k] = 0;
+            p.gcol[k] = false;
+        }
+        p.s.y0 = y0;
+        p.s.y1 = y1;
+        p.ylo = ylo;
+        p.yhi = yhi;
+        if (down) p.template run<true>();
+        else p.template run<false>();
+    } else {
+        Pair2D<T, NC, HAS_EPS, HAS_MU, true> p{{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0}};
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int g = gx0 + k;
+            // columns beyond the two ghost layers feed only halo values that stage 2 never reads
+            const int gc = min(max(g, -2), a.nx + 1);
+            bool mirx, nrx;
+            const int sx = map_axis(gc, a.nx, a.bc[0], a.bc[1], mirx, nrx);
+            p.s.vx[k] = (uint32_t)sx * (uint32_t)sizeof(T);
+            p.s.sgx[k] = mirx ? T(-1) : T(1);
+            p.s.nrx[k] = nrx;
+            p.s.writer[k] = NC * lane + k >= PAIR_HALO && NC * lane + k < WAVE * NC - PAIR_HALO && g >= 0 && g < a.nx;
+            p.gcol[k] = (g == -2 || g == -1 || g == a.nx || g == a.nx + 1) && g == gc;
+            const int src = min(max(sx - x0, 0), WAVE * NC - 1);   // the image's place in the strip
+            p.gaddr[k] = (src / NC) * 4;
+            p.gk[k] = src % NC;
+        }
+        p.s.y0 = y0;
+        p.s.y1 = y1;
+        p.ylo = ylo;
+        p.yhi = yhi;
+        if (down) p.template run<true>();
+        else p.template run<false>();
+    }
+}
+
 // The fp32 four-field (PHM) kernel is held to three waves per SIMD: left alone the compiler
 // takes 172 VGPRs, two waves fit, and the 4096^2 step takes 183 us; held to 168 it takes 155
 // VGPRs and 165 us, with fewer scalar spills.
@@ -437,6 +795,25 @@ int launch_cart2d_step(const Cart2DArgs<T> &a, void *stream)
 template int launch_cart2d_step<float>(const Cart2DArgs<float> &, void *);
 template int launch_cart2d_step<double>(const Cart2DArgs<double> &, void *);
 
+template <typename T>
+int launch_cart2d_pair(const Cart2DArgs<T> &a, void *stream)
+{
+    if (a.nfields != 3 || a.limiter) return (int)hipErrorInvalidValue;
+    const int waves = a.ntx * a.nty;
+    const int wpb = STEP2D_BLOCK / WAVE;
+    dim3 grid(NBANDS * ((waves + wpb - 1) / wpb)), block(STEP2D_BLOCK);
+    hipStream_t s = (hipStream_t)stream;
+    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, true, true>), grid, block, 0, s, a);
+    else if (a.epsinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, true, false>), grid, block, 0, s, a);
+    else if (a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, false, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((cart2d_pair_kernel<T, false, false>), grid, block, 0, s, a);
+    return (int)hipGetLastError();
+}
+
+template int launch_cart2d_pair<float>(const Cart2DArgs<float> &, void *);
+template int launch_cart2d_pair<double>(const Cart2DArgs<double> &, void *);
+
 int cart2d_tile_x(int precision) { return precision == GKS_FP64 ? out_cols<double>() : out_cols<float>(); }
+int cart2d_pair_tile_x(int precision) { return precision == GKS_FP64 ? pair_out_cols<double>() : pair_out_cols<float>(); }
 
 }  // namespace gks

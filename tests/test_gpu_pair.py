@@ -1,0 +1,68 @@
+"""The paired 2D kernel (two steps per launch) against single steps.
+
+gks_run advances 2D TM grids without a periodic side two steps per launch; its intermediate
+state is the one a single step would store, and both stages do the single step's arithmetic in
+its order.  So a run must equal the same number of gks_step calls bit for bit, on every side
+mix, with materials, a point source, odd step counts and energy records that fall between two
+steps (where the run takes single steps).  The oracle comparisons of the full-step tests run
+through the same path.
+"""
+import numpy as np
+import pytest
+
+NR, PEC, PER = "nonreflecting", "pec", "periodic"
+
+CASES = {
+    # name: (nx, ny, bc, batch, eps, mu, source, nsteps, energy_every)
+    "nr_box_source": ((300, 130), (NR,) * 4, 1, True, False, True, 7, 0),
+    "mixed_mu_batch": ((257, 64), (PEC, NR, NR, PEC), 2, True, True, True, 10, 0),
+    "pec_box_vacuum": ((131, 9), (PEC,) * 4, 1, False, False, False, 5, 0),
+    "records_between": ((64, 300), (NR, PEC, PEC, NR), 3, True, False, True, 9, 3),
+    "narrow": ((5, 40), (PEC, NR, PEC, NR), 2, True, True, False, 6, 0),
+    "two_columns": ((2, 8), (NR,) * 4, 1, True, False, False, 4, 0),
+    "strip_edges": ((245, 77), (NR, PEC, NR, PEC), 1, False, True, True, 8, 0),
+    "periodic_fallback": ((70, 50), (PER, PER, NR, NR), 1, True, False, True, 6, 0),
+}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a GPU"
+    return _t
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_run_equals_single_steps(torch, case, precision):
+    from paper_2412_16845_amd.gks import Solver
+    (nx, ny), bc, batch, eps, mu, source, nsteps, every = CASES[case]
+    rng = np.random.default_rng(list(CASES).index(case) + 100 * (precision == "fp32"))
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    s = Solver("cart2d", n=(nx, ny), bc=bc, precision=precision, batch=batch, cfl=0.5, tau_over_dt=0.01,
+               energy_every=every)
+    ei = torch.tensor(rng.uniform(0.25, 1.0, (batch, ny, nx)), dtype=dtype, device="cuda") if eps else None
+    mi = torch.tensor(rng.uniform(0.5, 1.0, (batch, ny, nx)), dtype=dtype, device="cuda") if mu else None
+    s.set_material(ei, mi)
+    if source:
+        s.set_point_source([(ny // 3) * nx + nx // 2], [1.3], 1.0, 0.01, 0.004)
+    U0 = torch.tensor(rng.standard_normal((batch, 3, ny, nx)), dtype=dtype, device="cuda")
+    t0 = 0.0037
+    A = U0.clone()
+    rec = s.run(A, nsteps, t0, energy=every > 0)
+    B = U0.clone()
+    for k in range(nsteps):
+        B = s.step(B, t=t0 + k * s.dt)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(A, B))
+    diff = float((A - B).abs().max())
+    print(f"{case} {precision}: run vs single steps, max |diff| = {diff:.3e}")
+    assert same
+    if every:
+        # the records are those of the single steps' states
+        C = U0.clone()
+        for k in range(nsteps):
+            C = s.step(C, t=t0 + k * s.dt)
+            if (k + 1) % every == 0:
+                assert np.array_equal(rec[(k + 1) // every - 1], s.energy(C))
