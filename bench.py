@@ -12,9 +12,12 @@ Inputs are resident in HBM before timing starts.
 One JSON line on stdout:
   value          FP32-mode cell-updates/s (FP32 storage, flux and update)
   fp64           the same run in FP64
-  roofline       achieved algorithmic HBM bandwidth of the step kernel (HIP events around each
-                 launch) against the 8 TB/s peak; traffic = HBM bytes per launch from the
-                 committed rocprofv3 counter summary (null when the kernel source changed since)
+  roofline       achieved algorithmic HBM bandwidth of the kernel the timed run uses, the paired
+                 kernel (two steps per launch: twice the single step's algorithmic bytes per
+                 launch), HIP events around its launches, against the 8 TB/s peak; traffic = HBM
+                 bytes per launch from the committed rocprofv3 counter summary (null when the
+                 kernel source changed since); single_step_roofline: the same for the single-step
+                 kernel (gks_step)
   cpu_baseline   the FP64 oracle on the host cores, on a bounded sample of the same workload
   cart3d         the 3D six-field 384^3 workload (FP32 and FP64): throughput and roofline
   tri2d          the ~4M-triangle workload (FP32 and FP64): throughput and roofline
@@ -28,6 +31,7 @@ One JSON line on stdout:
   tet3d          the tetrahedral workload (1.5M cells around a PEC sphere), FP32 and FP64
 
 Helper modes for the profiles: --profile-kernel PREC runs only step kernels (for rocprofv3);
+--profile-pair PREC 20 launches of the paired kernel (gks_run of 40 steps);
 --profile-tri PREC runs 20 steps of the triangle workload, --profile-3d PREC 10 steps of the 384^3
 workload, --profile-adjoint 10 adjoint steps of the 1024^2 x 8 workload, --profile-phm PREC 20 steps of
 the 4096^2 PHM workload, --profile-phm3d PREC 5 steps of the 384^3 PHM workload, --profile-tet PREC 20
@@ -127,13 +131,30 @@ def time_kernel(torch, s, U, launches=200):
     return batch, pairs
 
 
+def time_pair(torch, s, U, launches=200):
+    """Average duration of one launch of the paired kernel (two steps per launch, the kernel
+    gks_run takes on this grid): a HIP event pair on the solver's stream around gks_run of
+    2 x `launches` steps without the energy diagnostic (an even number of launches, so the state
+    ends where it began and no copy follows), divided by `launches`."""
+    assert launches % 2 == 0
+    s.run(U, 20)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.run(U, 2 * launches)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / launches
+
+
 def kernel_sha():
     with open(KERNEL_SRC, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic(precision):
-    """HBM bytes per launch from the committed counter summary, if it matches this kernel."""
+def read_traffic(precision, kind="step"):
+    """HBM bytes per launch from the committed counter summary, if it matches this kernel
+    (kind "step": the single-step kernel, "pair": the paired kernel)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -145,7 +166,7 @@ def read_traffic(precision):
         kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256_16") != kernel_sha():
         return None
-    key = f"traffic_bytes_per_launch_{precision}"
+    key = f"traffic_bytes_per_launch_{precision}" if kind == "step" else f"traffic_bytes_per_launch_pair_{precision}"
     return float(kv[key]) if key in kv else None
 
 
@@ -155,6 +176,20 @@ def roofline(precision, t_launch):
     achieved = alg / t_launch / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_GBS, 4), "traffic": read_traffic(precision),
+            "kernel": "cart2d_step_kernel", "steps_per_launch": 1,
+            "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch}
+
+
+def roofline_pair(precision, t_launch):
+    """The paired kernel: two cell-updates per cell and launch, so its algorithmic bytes are twice
+    the single step's; `traffic` is what the counters measured per launch (about one step's
+    bytes: the fields are read and written once for both steps)."""
+    ncell = N * N
+    alg = 2 * BYTES_PER_CELL[precision] * ncell
+    achieved = alg / t_launch / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_GBS, 4), "traffic": read_traffic(precision, "pair"),
+            "kernel": "cart2d_pair_kernel", "steps_per_launch": 2,
             "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch}
 
 
@@ -340,11 +375,15 @@ def limited_leg(torch, wl):
         t_launch, _ = time_kernel(torch, s, U, launches=100)
         if not torch.isfinite(U).all():
             raise RuntimeError(f"limited {prec} run produced non-finite values")
+        t_pair = time_pair(torch, s, U, launches=50)
         alg = BYTES_PER_CELL[prec] * ncell
         out[prec] = {"cell_updates_per_s": round(ncell / t_launch, 1),
                      "roofline": {"bound": "hbm", "achieved": round(alg / t_launch / 1e9, 1), "peak": PEAK_GBS,
                                   "unit": "GB/s", "frac": round(alg / t_launch / 1e9 / PEAK_GBS, 4),
-                                  "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch}}
+                                  "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch},
+                     "paired_kernel": {"cell_updates_per_s": round(2 * ncell / t_pair, 1),
+                                       "kernel_seconds_per_launch": t_pair, "steps_per_launch": 2,
+                                       "frac": round(2 * alg / t_pair / 1e9 / PEAK_GBS, 4)}}
         del s, U, ei
         torch.cuda.empty_cache()
     return out
@@ -392,18 +431,22 @@ def oversized_leg(torch):
     wl = I.tm_dielectric_nr(nx=N_OVERSIZED, seed=0, nsteps=100)
     ncell = N_OVERSIZED * N_OVERSIZED
     out = {"workload": f"tm_dielectric_nr: 2D TM {N_OVERSIZED}x{N_OVERSIZED}, the 4096^2 recipe on a finer grid "
-                       f"(step kernel only, 100 timed launches)", "cells": ncell}
+                       f"(step kernel only, 100 timed launches; the paired kernel, 50 launches)", "cells": ncell}
     for prec in ("fp32", "fp64"):
         s, U, ei = make(torch, wl, prec)
         s.run(U, 10)
         t_launch, _ = time_kernel(torch, s, U, launches=100)
         if not torch.isfinite(U).all():
             raise RuntimeError(f"oversized {prec} run produced non-finite values")
+        t_pair = time_pair(torch, s, U, launches=50)
         alg = BYTES_PER_CELL[prec] * ncell
         out[prec] = {"cell_updates_per_s": round(ncell / t_launch, 1),
                      "roofline": {"bound": "hbm", "achieved": round(alg / t_launch / 1e9, 1), "peak": PEAK_GBS,
                                   "unit": "GB/s", "frac": round(alg / t_launch / 1e9 / PEAK_GBS, 4),
-                                  "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch}}
+                                  "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch},
+                     "paired_kernel": {"cell_updates_per_s": round(2 * ncell / t_pair, 1),
+                                       "kernel_seconds_per_launch": t_pair, "steps_per_launch": 2,
+                                       "frac": round(2 * alg / t_pair / 1e9 / PEAK_GBS, 4)}}
         del s, U, ei
         torch.cuda.empty_cache()
     return out
@@ -684,6 +727,7 @@ def main():
     ap.add_argument("--profile-phm3d", choices=["fp32", "fp64"])
     ap.add_argument("--profile-tet", choices=["fp32", "fp64"])
     ap.add_argument("--profile-kernel", choices=["fp32", "fp64"])
+    ap.add_argument("--profile-pair", choices=["fp32", "fp64"])
     ap.add_argument("--profile-tri", choices=["fp32", "fp64"])
     ap.add_argument("--profile-3d", choices=["fp32", "fp64"])
     ap.add_argument("--profile-adjoint", action="store_true")
@@ -787,6 +831,12 @@ def main():
         return
 
     wl = workload()
+    if args.profile_pair:
+        s, U, _ = make(torch, wl, args.profile_pair)
+        s.run(U, 40)   # 20 launches of the paired kernel
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled": "pair " + args.profile_pair, "launches": 20}))
+        return
     if args.profile_kernel:
         s, U, _ = make(torch, wl, args.profile_kernel)
         B = torch.empty_like(U)
@@ -804,16 +854,19 @@ def main():
         el, wall = time_run(torch, s, U, args.steps, args.warmup)
         if not torch.isfinite(U).all():
             raise RuntimeError(f"{prec} run produced non-finite values")
+        t_pair = time_pair(torch, s, U)
         t_launch, t_pairs = time_kernel(torch, s, U)
         # the recipe's fields are zero away from the source for most of the run; the same launches
         # on a state of unit normal values in every cell show whether the data changes the time
         g = torch.Generator(device="cuda")
         g.manual_seed(7)
         Ur = torch.randn(U.shape, generator=g, dtype=U.dtype, device=U.device)
+        t_pair_rand = time_pair(torch, s, Ur.clone())
         t_rand, _ = time_kernel(torch, s, Ur)
         res[prec] = {"seconds": el, "wall": wall, "t_launch": t_launch, "t_launch_pairs": t_pairs, "dt": s.dt,
-                     "t_launch_random": t_rand}
-        log(f"[bench] {prec}: {el * 1e3 / args.steps:.4f} ms/step, kernel {t_launch * 1e6:.1f} us/launch "
+                     "t_launch_random": t_rand, "t_pair": t_pair, "t_pair_random": t_pair_rand}
+        log(f"[bench] {prec}: {el * 1e3 / args.steps:.4f} ms/step; paired kernel {t_pair * 1e6:.1f} us/launch "
+            f"({t_pair_rand * 1e6:.1f} us from a random state); single-step kernel {t_launch * 1e6:.1f} us/launch "
             f"({t_rand * 1e6:.1f} us from a random state)")
         del Ur
         del s, U, ei
@@ -837,14 +890,18 @@ def main():
         "config": {"workload": "tm_dielectric_nr: 2D TM 4096x4096, non-reflecting sides, 64 dielectric discs "
                                "(eps in [1,4]), Gaussian point source, CFL 0.5, tau = 0.01 dt, energy every 100 steps",
                    "cells": ncell, "precision": "fp32"},
-        "roofline": roofline("fp32", f32["t_launch"]),
+        "roofline": roofline_pair("fp32", f32["t_pair"]),
+        "single_step_roofline": roofline("fp32", f32["t_launch"]),
         "fp64": {"value": round(ncell * args.steps / f64["seconds"], 1), "unit": "cell-updates/s",
                  "ms_per_step": round(f64["seconds"] * 1e3 / args.steps, 5), "dtype": "f64",
-                 "roofline": roofline("fp64", f64["t_launch"])},
+                 "roofline": roofline_pair("fp64", f64["t_pair"]),
+                 "single_step_roofline": roofline("fp64", f64["t_launch"])},
         "kernel_us_per_launch_by_state": {
-            prec: {"recipe_state": round(res[prec]["t_launch"] * 1e6, 2),
-                   "random_state": round(res[prec]["t_launch_random"] * 1e6, 2),
-                   "recipe_state_single_launch_event_pairs": round(res[prec]["t_launch_pairs"] * 1e6, 2)}
+            prec: {"paired_recipe_state": round(res[prec]["t_pair"] * 1e6, 2),
+                   "paired_random_state": round(res[prec]["t_pair_random"] * 1e6, 2),
+                   "single_step_recipe_state": round(res[prec]["t_launch"] * 1e6, 2),
+                   "single_step_random_state": round(res[prec]["t_launch_random"] * 1e6, 2),
+                   "single_step_recipe_state_single_launch_event_pairs": round(res[prec]["t_launch_pairs"] * 1e6, 2)}
             for prec in ("fp32", "fp64")},
     }
     if not args.no_limited:

@@ -301,7 +301,16 @@ std::vector<int32_t> gks::cart2d_pair_tile_table(int ny, int batch, int ntx, int
     // kernel: a tile reads the intermediate state two rows beyond each end, so a cut between
     // tiles never falls one row from a side (it moves one row on), and a tile that touches the
     // lower side marches down, one that touches the upper side up (no tile may touch both).
-    const int tall = GKS_TILE_TALL, shrt = GKS_TILE_SHORT;
+    // A tile's stage 1 forms four rows more than it writes, so the paired kernel takes taller
+    // tiles: on 4096^2 (fp32 / fp64 us per launch) tall 32 153.7 / 238.0, 48 150.4 / 232.3,
+    // 64 150.3 / 230.5, 96 163.3 / 246.0, 128 174.8 / 234.7; tall 64 with short 16 150.0 / 226.3.
+#ifndef GKS_PAIR_TILE_TALL
+#define GKS_PAIR_TILE_TALL 64
+#endif
+#ifndef GKS_PAIR_TILE_SHORT
+#define GKS_PAIR_TILE_SHORT 16
+#endif
+    const int tall = GKS_PAIR_TILE_TALL, shrt = GKS_PAIR_TILE_SHORT;
     const double frac = GKS_TILE_SHORT_FRAC;
     tiles_per_band = 0;
     if (ny < 8) return {};

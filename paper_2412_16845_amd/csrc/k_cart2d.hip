@@ -353,8 +353,16 @@ struct Strip2D {
 // down and one that touches the upper side marches up).  Periodic sides would need
 // intermediate values from other waves: those grids take the single-step kernel.
 constexpr int PAIR_HALO = 4;
+// One column per lane in both precisions: the paired fp32 kernel with two columns per lane
+// needs all 256 VGPRs (and spills); with one it takes 150.0 against 173.6 us per launch on the
+// 4096^2 workload, for the wider halo (8 of 64 columns).
+#ifndef GKS_PAIR_FP32_COLS
+#define GKS_PAIR_FP32_COLS 1
+#endif
 template <typename T>
-constexpr int pair_out_cols() { return WAVE * cols_per_lane<T>() - 2 * PAIR_HALO; }
+constexpr int pair_cols_per_lane() { return sizeof(T) == 4 ? GKS_PAIR_FP32_COLS : 1; }
+template <typename T>
+constexpr int pair_out_cols() { return WAVE * pair_cols_per_lane<T>() - 2 * PAIR_HALO; }
 
 // v of the lane whose byte address (4 x lane) is given; all lanes take part (the asm keeps
 // the move out of any branch, where lanes switched off would read as zero)
@@ -622,10 +630,14 @@ struct Pair2D {
     }
 };
 
+// Four waves per SIMD in fp32 (at most 128 VGPRs; the 1/eps kernel then spills 5 values): 143.7
+// against 150.0 us per launch on the 4096^2 workload at the compiler's 134 VGPRs and three waves.
+// The kernel with both material maps would spill 42 values and keeps three; fp64 needs two.
 template <typename T, bool HAS_EPS, bool HAS_MU>
-__global__ __launch_bounds__(STEP2D_BLOCK, 2) void cart2d_pair_kernel(Cart2DArgs<T> a)
+__global__ __launch_bounds__(STEP2D_BLOCK, sizeof(T) == 8 ? 2 : (HAS_EPS && HAS_MU) ? 3 : 4) void cart2d_pair_kernel(
+    Cart2DArgs<T> a)
 {
-    constexpr int NC = cols_per_lane<T>();
+    constexpr int NC = pair_cols_per_lane<T>();
     const int lane = threadIdx.x & (WAVE - 1);
     const int band = blockIdx.x % NBANDS;
     const int wave = (blockIdx.x / NBANDS) * (STEP2D_BLOCK / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
