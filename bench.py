@@ -180,17 +180,28 @@ def roofline(precision, t_launch):
             "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch}
 
 
+# arithmetic per 2D cell-update: two flops per multiply-add of the two face operators a cell owns
+# (24 + 6 structural non-zeros each with vacuum 1/mu), six differences, and per field the four
+# face fluxes and the update
+C2_FLOPS_PER_CELL = 2 * 2 * (24 + 6) + 6 + 3 * 6
+
+
 def roofline_pair(precision, t_launch):
     """The paired kernel: two cell-updates per cell and launch, so its algorithmic bytes are twice
     the single step's; `traffic` is what the counters measured per launch (about one step's
-    bytes: the fields are read and written once for both steps)."""
+    bytes: the fields are read and written once for both steps).  Its arithmetic is given beside
+    it against the non-packed vector peak (the profile summary has its VALU issue fraction)."""
     ncell = N * N
     alg = 2 * BYTES_PER_CELL[precision] * ncell
     achieved = alg / t_launch / 1e9
+    tflops = 2 * C2_FLOPS_PER_CELL * ncell / t_launch / 1e12
+    peak_alu = 78.6
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_GBS, 4), "traffic": read_traffic(precision, "pair"),
             "kernel": "cart2d_pair_kernel", "steps_per_launch": 2,
-            "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch}
+            "algorithmic_bytes_per_launch": alg, "kernel_seconds_per_launch": t_launch,
+            "vector_alu": {"flops_per_cell_update": C2_FLOPS_PER_CELL, "achieved_tflops": round(tflops, 2),
+                           "peak_tflops_non_packed": peak_alu, "frac": round(tflops / peak_alu, 4)}}
 
 
 def cpu_model() -> str:
@@ -321,6 +332,14 @@ def adjoint_leg(torch):
         s, E, U = solver(prec)
         s.run(U, 50)
         plain[prec] = timed(s, lambda: s.run(U, ADJ_STEPS)) / ADJ_STEPS
+
+        def single_steps():
+            A, B = U, torch.empty_like(U)
+            for i in range(ADJ_STEPS):
+                s.step(A, B, t=i * s.dt)
+                A, B = B, A
+
+        plain[prec + "_single"] = timed(s, single_steps) / ADJ_STEPS
         del s, E, U
     s, E, U0 = solver("fp32")
     E.requires_grad_(True)
@@ -358,6 +377,9 @@ def adjoint_leg(torch):
             "plain_fp64_ms_per_step": round(plain["fp64"] * 1e3, 5),
             "plain_fp32_ms_per_step": round(plain["fp32"] * 1e3, 5),
             "fwd_adj_over_fp64_step": round(t_fb / ADJ_STEPS / plain["fp64"], 3),
+            "plain_fp64_single_step_ms": round(plain["fp64_single"] * 1e3, 5),
+            "plain_fp32_single_step_ms": round(plain["fp32_single"] * 1e3, 5),
+            "fwd_adj_over_fp64_single_step": round(t_fb / ADJ_STEPS / plain["fp64_single"], 3),
             "adjoint_step_us_per_launch": round(t_adj * 1e6, 2),
             "adjoint_roofline": {"bound": "hbm", "achieved": round(alg / t_adj / 1e9, 1), "peak": PEAK_GBS,
                                  "unit": "GB/s", "frac": round(alg / t_adj / 1e9 / PEAK_GBS, 4),
