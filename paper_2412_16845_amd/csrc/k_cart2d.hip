@@ -340,9 +340,9 @@ struct Strip2D {
 };
 
 // ------------------------------------------------------------------ two steps per launch
-// The paired kernel runs two consecutive steps of the TM fields in one march, so that the
-// fields are read and written once per two steps.  Stage 1 is the march above over a strip with
-// four halo columns and a tile widened by two rows on each side.  Every row it finishes (the
+// The paired kernel runs two consecutive steps of the TM fields (with or without psi) in one
+// march, so that the fields are read and written once per two steps.  Stage 1 is the march
+// above over a strip with four halo columns and a tile widened by two rows on each side.  Every row it finishes (the
 // state after the first step, rounded to the storage type as a stored state would be) enters
 // stage 2, a second march of the same form that takes its rows from registers instead of
 // memory and writes the state after the second step.  Both stages do the single-step kernel's
@@ -381,12 +381,12 @@ __device__ __forceinline__ double lane_fetch(double v, int addr)
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename T, int NC, bool HAS_EPS, bool HAS_MU, bool BND>
+template <typename T, int NC, int NF, bool HAS_EPS, bool HAS_MU, bool BND>
 struct Pair2D {
-    static constexpr int NF = 3;
     using S = Strip2D<T, NC, NF, HAS_EPS, HAS_MU, BND, false>;
     using Row = Row2D<T, NC, NF>;
-    using OpT = FaceOpTM<T>;
+    using FS = Fields2D<NF>;
+    using OpT = typename FS::template Op<T>;
     static constexpr int CH2 = S::CH2;
     static constexpr bool HM = S::HM;
     static constexpr int OPS0 = S::OPS0;
@@ -438,7 +438,7 @@ struct Pair2D {
                 w[4 * NF + f] = zr ? T(0) : DR[k][NF + f];
                 w[5 * NF + f] = zr ? T(0) : DR[k][f];
             }
-            apply_op<PatTMy, CH2, HM>(w, RL.mE[k] + RR.mE[k], HM ? RL.mH[k] + RR.mH[k] : T(2), opy, fyN[k]);
+            apply_op<typename FS::PY, CH2, HM>(w, RL.mE[k] + RR.mE[k], HM ? RL.mH[k] + RR.mH[k] : T(2), opy, fyN[k]);
         }
         if (i < 2) return false;
         const auto opx = scalar_ptr_after(ops + OPS0, fyN[NC - 1][2]);
@@ -468,7 +468,7 @@ struct Pair2D {
             }
             const T mEr = (k < last) ? Rs.mE[kr] : from_right(Rs.mE[0]);
             const T mHr = !HM ? T(1) : (k < last) ? Rs.mH[kr] : from_right(Rs.mH[0]);
-            apply_op<PatTMx, CH2, HM>(v, Rs.mE[k] + mEr, Rs.mH[k] + mHr, opx, fx[k]);
+            apply_op<typename FS::PX, CH2, HM>(v, Rs.mE[k] + mEr, Rs.mH[k] + mHr, opx, fx[k]);
         }
         const int row = q - 2 * sd;
         double src[NC];
@@ -483,7 +483,8 @@ struct Pair2D {
                 const double fu = (double)(DN ? fyP[k][f] : fyN[k][f]);
                 const double fd = (double)(DN ? fyN[k][f] : fyP[k][f]);
                 const double div = (fr - fl) + (fu - fd);
-                const double m = (f == 0) ? (double)Rs.mE[k] : (double)Rs.mH[k];
+                // 1/eps scales Ez, 1/mu scales H; psi carries no material factor
+                const double m = (f == 0) ? (double)Rs.mE[k] : (f < 3) ? (double)Rs.mH[k] : 1.0;
                 const double add = (f == 0) ? src[k] : 0.0;
                 nv[k][f] = (T)fma(m, add - div, (double)Rs.u[k][f]);
             }
@@ -534,7 +535,8 @@ struct Pair2D {
         if (!stage<DN>(i, q, a.src_amp, Rs, Rc, Rn, Ds, Dc, fyP, fyN, nv)) return;
         const int r = q - 2 * sd;   // the intermediate row just formed
         if constexpr (BND) {
-            // ghost columns: the (mirror) image of a column of the same row; x mirror: Ez and Hx odd
+            // ghost columns: the (mirror) image of a column of the same row; x mirror: Ez and Hx
+            // odd, Hy and psi even
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 T got[NC];
@@ -553,17 +555,18 @@ struct Pair2D {
             }
             if (r < 0 || r >= a.ny) {
                 // a ghost row: the (mirror) image of one of the last two real rows; y mirror: Ez and
-                // Hy odd
+                // Hy odd, Hx and psi even
                 bool mir, nry;
                 const int m = map_axis(r, a.ny, a.bc[2], a.bc[3], mir, nry);
                 const bool last = m == hrow;
                 const T sg = mir ? T(-1) : T(1);
 #pragma unroll
-                for (int k = 0; k < NC; ++k) {
-                    nv[k][0] = (last ? h0[k][0] : h1[k][0]) * sg;
-                    nv[k][1] = last ? h0[k][1] : h1[k][1];
-                    nv[k][2] = (last ? h0[k][2] : h1[k][2]) * sg;
-                }
+                for (int k = 0; k < NC; ++k)
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+                        const T v = last ? h0[k][f] : h1[k][f];
+                        nv[k][f] = (f == 0 || f == 2) ? v * sg : v;
+                    }
             } else {
 #pragma unroll
                 for (int k = 0; k < NC; ++k)
@@ -632,10 +635,11 @@ struct Pair2D {
 
 // Four waves per SIMD in fp32 (at most 128 VGPRs; the 1/eps kernel then spills 5 values): 143.7
 // against 150.0 us per launch on the 4096^2 workload at the compiler's 134 VGPRs and three waves.
-// The kernel with both material maps would spill 42 values and keeps three; fp64 needs two.
-template <typename T, bool HAS_EPS, bool HAS_MU>
-__global__ __launch_bounds__(STEP2D_BLOCK, sizeof(T) == 8 ? 2 : (HAS_EPS && HAS_MU) ? 3 : 4) void cart2d_pair_kernel(
-    Cart2DArgs<T> a)
+// The kernel with both material maps would spill 42 values and keeps three, as do the PHM fields
+// (four per cell); fp64 needs two.
+template <typename T, int NF, bool HAS_EPS, bool HAS_MU>
+__global__ __launch_bounds__(STEP2D_BLOCK, sizeof(T) == 8 ? 2 : (NF == 4 || (HAS_EPS && HAS_MU)) ? 3 : 4) void
+cart2d_pair_kernel(Cart2DArgs<T> a)
 {
     constexpr int NC = pair_cols_per_lane<T>();
     const int lane = threadIdx.x & (WAVE - 1);
@@ -653,8 +657,8 @@ __global__ __launch_bounds__(STEP2D_BLOCK, sizeof(T) == 8 ? 2 : (HAS_EPS && HAS_
 
     const int64_t ncell = (int64_t)a.nx * a.ny;
     const uint32_t fbytes = (uint32_t)(ncell * (int64_t)sizeof(T));
-    const Rsrc rU = make_rsrc(a.U + (int64_t)b * 3 * ncell, 3ull * fbytes);
-    const Rsrc rO = make_rsrc(a.Unew + (int64_t)b * 3 * ncell, 3ull * fbytes);
+    const Rsrc rU = make_rsrc(a.U + (int64_t)b * NF * ncell, (uint64_t)NF * fbytes);
+    const Rsrc rO = make_rsrc(a.Unew + (int64_t)b * NF * ncell, (uint64_t)NF * fbytes);
     const Rsrc rE = make_rsrc(HAS_EPS ? a.epsinv + (int64_t)b * ncell : a.U, fbytes);
     const Rsrc rM = make_rsrc(HAS_MU ? a.muinv + (int64_t)b * ncell : a.U, fbytes);
 
@@ -665,7 +669,7 @@ __global__ __launch_bounds__(STEP2D_BLOCK, sizeof(T) == 8 ? 2 : (HAS_EPS && HAS_
 
     const bool interior = x0 >= 0 && x0 + WAVE * NC - 1 <= a.nx - 1 && y0 - 4 >= 0 && y1 + 3 <= a.ny - 1;
     if (interior) {
-        Pair2D<T, NC, HAS_EPS, HAS_MU, false> p{{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0}};
+        Pair2D<T, NC, NF, HAS_EPS, HAS_MU, false> p{{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0}};
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             p.s.vx[k] = 0;
@@ -683,7 +687,7 @@ __global__ __launch_bounds__(STEP2D_BLOCK, sizeof(T) == 8 ? 2 : (HAS_EPS && HAS_
         if (down) p.template run<true>();
         else p.template run<false>();
     } else {
-        Pair2D<T, NC, HAS_EPS, HAS_MU, true> p{{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0}};
+        Pair2D<T, NC, NF, HAS_EPS, HAS_MU, true> p{{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0}};
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int g = gx0 + k;
@@ -810,15 +814,22 @@ template int launch_cart2d_step<double>(const Cart2DArgs<double> &, void *);
 template <typename T>
 int launch_cart2d_pair(const Cart2DArgs<T> &a, void *stream)
 {
-    if (a.nfields != 3 || a.limiter) return (int)hipErrorInvalidValue;
+    if ((a.nfields != 3 && a.nfields != 4) || a.limiter) return (int)hipErrorInvalidValue;
     const int waves = a.ntx * a.nty;
     const int wpb = STEP2D_BLOCK / WAVE;
     dim3 grid(NBANDS * ((waves + wpb - 1) / wpb)), block(STEP2D_BLOCK);
     hipStream_t s = (hipStream_t)stream;
-    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, true, true>), grid, block, 0, s, a);
-    else if (a.epsinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, true, false>), grid, block, 0, s, a);
-    else if (a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, false, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((cart2d_pair_kernel<T, false, false>), grid, block, 0, s, a);
+    if (a.nfields == 4) {
+        if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, true, true>), grid, block, 0, s, a);
+        else if (a.epsinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, true, false>), grid, block, 0, s, a);
+        else if (a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, false, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, false, false>), grid, block, 0, s, a);
+        return (int)hipGetLastError();
+    }
+    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, true, true>), grid, block, 0, s, a);
+    else if (a.epsinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, true, false>), grid, block, 0, s, a);
+    else if (a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, false, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, false, false>), grid, block, 0, s, a);
     return (int)hipGetLastError();
 }
 
