@@ -347,11 +347,12 @@ struct Strip2D {
 // stage 2, a second march of the same form that takes its rows from registers instead of
 // memory and writes the state after the second step.  Both stages do the single-step kernel's
 // arithmetic in its order, so the two kernels give the same results bit for bit.
-// Ghost values of the intermediate state are formed from its own cells, as the loads form them
-// for a stored state: along x from the boundary column held by another lane of the same wave,
-// along y from the last two rows stage 1 finished (so a tile that touches the lower side marches
-// down and one that touches the upper side marches up).  Periodic sides would need
-// intermediate values from other waves: those grids take the single-step kernel.
+// Ghost values of the intermediate state behind a non-reflecting or PEC side are formed from its
+// own cells, as the loads form them for a stored state: along x from the boundary column held
+// by another lane of the same wave, along y from the last two rows stage 1 finished (so a tile
+// that touches the lower side marches down and one that touches the upper side marches up).
+// Behind a periodic side stage 1 forms them itself, as the step of the cells they image (its
+// inputs wrap, and the step is the same at every position).
 constexpr int PAIR_HALO = 4;
 // One column per lane in both precisions: the paired fp32 kernel with two columns per lane
 // needs all 256 VGPRs (and spills); with one it takes 150.0 against 173.6 us per launch on the
@@ -392,9 +393,21 @@ struct Pair2D {
     static constexpr int OPS0 = S::OPS0;
     S s;              // the strip: buffer resources, column maps, stage 1's loads, stage 2's writers
     int ylo, yhi;     // the rows stage 1 reads (its loads are clamped to them)
+    bool yper;        // periodic y sides: rows beyond them wrap, and ghost rows are formed by stage 1
+    int scol[NC];     // the column each lane's cells are (a periodic ghost: its image), for the source
     int gaddr[NC];    // boundary strips: the lane (byte address) holding each ghost column's image
     int gk[NC];       // ... and the column of that lane
     bool gcol[NC];    // a ghost column whose intermediate value stage 2 reads
+
+    // the row a periodic y side wraps a row to (other rows unchanged)
+    __device__ __forceinline__ int wrap_row(int y) const
+    {
+        if (!BND || !yper) return y;
+        const int ny = s.a.ny;
+        return ((y % ny) + ny) % ny;
+    }
+    // the row stage 1 loads for march row y: clamped to the rows it reads, wrapped on periodic sides
+    __device__ __forceinline__ int stage1_row(int y) const { return wrap_row(min(max(y, ylo), yhi)); }
 
     // One row step of a march whose window holds rows Rs = q-2s, Rc = q-s, Rn = q: the
     // differences of Rc, the horizontal face between Rs and Rc, and from the third step on the
@@ -473,7 +486,7 @@ struct Pair2D {
         const int row = q - 2 * sd;
         double src[NC];
 #pragma unroll
-        for (int k = 0; k < NC; ++k) src[k] = (row == a.src_row && s.gx0 + k == a.src_col) ? amp : 0.0;
+        for (int k = 0; k < NC; ++k) src[k] = (wrap_row(row) == a.src_row && scol[k] == a.src_col) ? amp : 0.0;
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
 #pragma unroll
@@ -530,7 +543,7 @@ struct Pair2D {
         constexpr int sd = DN ? -1 : 1;
         const Cart2DArgs<T> &a = s.a;
         const int q = qs + sd * i;
-        s.load(min(max(q + sd * PF, ylo), yhi), Rp);
+        s.load(stage1_row(q + sd * PF), Rp);
         T nv[NC][NF];
         if (!stage<DN>(i, q, a.src_amp, Rs, Rc, Rn, Ds, Dc, fyP, fyN, nv)) return;
         const int r = q - 2 * sd;   // the intermediate row just formed
@@ -553,7 +566,7 @@ struct Pair2D {
 #pragma unroll
                 for (int k = 0; k < NC; ++k) nv[k][f] = gcol[k] ? got[k] : nv[k][f];
             }
-            if (r < 0 || r >= a.ny) {
+            if (!yper && (r < 0 || r >= a.ny)) {
                 // a ghost row: the (mirror) image of one of the last two real rows; y mirror: Ez and
                 // Hy odd, Hx and psi even
                 bool mir, nry;
@@ -610,7 +623,7 @@ struct Pair2D {
         int hrow = -1000;
         const int Y0 = y0 - 2, Y1 = y1 + 2;          // intermediate rows formed: [Y0, Y1)
         const int qs = DN ? Y1 - 1 : Y0;
-        auto ld = [&](int y, Row &R) { s.load(min(max(y, ylo), yhi), R); };
+        auto ld = [&](int y, Row &R) { s.load(stage1_row(y), R); };
         ld(qs - 2 * sd, R0);
         ld(qs - sd, R1);
         ld(qs, R2);
@@ -665,7 +678,10 @@ cart2d_pair_kernel(Cart2DArgs<T> a)
     const int x0 = tx * pair_out_cols<T>() - PAIR_HALO;
     const int gx0 = x0 + NC * lane;
     const uint32_t vlane = (uint32_t)(NC * lane) * (uint32_t)sizeof(T);
-    const int ylo = max(y0 - 4, -2), yhi = min(y1 + 3, a.ny + 1);
+    // periodic y sides: rows beyond them wrap (stage 1 forms the intermediate ghost rows as the
+    // step of the rows they image); other sides: the two ghost rows a load can form
+    const bool yper = a.bc[2] == GKS_BC_PERIODIC;
+    const int ylo = yper ? y0 - 4 : max(y0 - 4, -2), yhi = yper ? y1 + 3 : min(y1 + 3, a.ny + 1);
 
     const bool interior = x0 >= 0 && x0 + WAVE * NC - 1 <= a.nx - 1 && y0 - 4 >= 0 && y1 + 3 <= a.ny - 1;
     if (interior) {
@@ -679,7 +695,9 @@ cart2d_pair_kernel(Cart2DArgs<T> a)
             p.gaddr[k] = 0;
             p.gk[k] = 0;
             p.gcol[k] = false;
+            p.scol[k] = gx0 + k;
         }
+        p.yper = yper;
         p.s.y0 = y0;
         p.s.y1 = y1;
         p.ylo = ylo;
@@ -691,15 +709,19 @@ cart2d_pair_kernel(Cart2DArgs<T> a)
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int g = gx0 + k;
-            // columns beyond the two ghost layers feed only halo values that stage 2 never reads
-            const int gc = min(max(g, -2), a.nx + 1);
+            // periodic x sides: every column wraps (stage 1 forms the intermediate ghost columns as
+            // the step of the columns they image); other sides: columns beyond the two ghost layers
+            // feed only halo values that stage 2 never reads
+            const bool xper = a.bc[0] == GKS_BC_PERIODIC;
+            const int gc = xper ? ((g % a.nx) + a.nx) % a.nx : min(max(g, -2), a.nx + 1);
             bool mirx, nrx;
             const int sx = map_axis(gc, a.nx, a.bc[0], a.bc[1], mirx, nrx);
             p.s.vx[k] = (uint32_t)sx * (uint32_t)sizeof(T);
             p.s.sgx[k] = mirx ? T(-1) : T(1);
             p.s.nrx[k] = nrx;
             p.s.writer[k] = NC * lane + k >= PAIR_HALO && NC * lane + k < WAVE * NC - PAIR_HALO && g >= 0 && g < a.nx;
-            p.gcol[k] = (g == -2 || g == -1 || g == a.nx || g == a.nx + 1) && g == gc;
+            p.gcol[k] = !xper && (g == -2 || g == -1 || g == a.nx || g == a.nx + 1);
+            p.scol[k] = xper ? sx : g;
             const int src = min(max(sx - x0, 0), WAVE * NC - 1);   // the image's place in the strip
             p.gaddr[k] = (src / NC) * 4;
             p.gk[k] = src % NC;
@@ -708,6 +730,7 @@ cart2d_pair_kernel(Cart2DArgs<T> a)
         p.s.y1 = y1;
         p.ylo = ylo;
         p.yhi = yhi;
+        p.yper = yper;
         if (down) p.template run<true>();
         else p.template run<false>();
     }

@@ -1,10 +1,11 @@
 """The paired 2D kernel (two steps per launch) against single steps.
 
-gks_run advances 2D TM grids without a periodic side two steps per launch; its intermediate
-state is the one a single step would store, and both stages do the single step's arithmetic in
-its order.  So a run must equal the same number of gks_step calls bit for bit, on every side
-mix, with materials, a point source, odd step counts and energy records that fall between two
-steps (where the run takes single steps).  The oracle comparisons of the full-step tests run
+gks_run advances 2D TM grids (with or without psi) two steps per launch; its intermediate state
+is the one a single step would store, and both stages do the single step's arithmetic in its
+order.  So a run must equal the same number of gks_step calls bit for bit, on every side mix
+(periodic sides included, with a source in the cell their ghosts image), with materials, a
+point source, odd step counts and energy records that fall between two steps (where the run
+takes single steps).  The oracle comparisons of the full-step tests run
 through the same path.
 """
 import numpy as np
@@ -21,7 +22,10 @@ CASES = {
     "narrow": ((5, 40), (PEC, NR, PEC, NR), 2, True, True, False, 6, 0),
     "two_columns": ((2, 8), (NR,) * 4, 1, True, False, False, 4, 0),
     "strip_edges": ((245, 77), (NR, PEC, NR, PEC), 1, False, True, True, 8, 0),
-    "periodic_fallback": ((70, 50), (PER, PER, NR, NR), 1, True, False, True, 6, 0),
+    "periodic_x": ((70, 50), (PER, PER, NR, NR), 1, True, False, True, 6, 0),
+    "periodic_y_pec_x": ((90, 33), (PEC, PEC, PER, PER), 2, True, True, True, 7, 0),
+    "periodic_both_small": ((3, 9), (PER,) * 4, 1, True, False, True, 5, 0),
+    "periodic_source_at_wrap": ((61, 40), (PER,) * 4, 1, True, False, "wrap", 6, 0),
 }
 # the PHM fields (Ez, Hx, Hy, psi): name -> grid, sides, batch, eps, mu, source, steps, couplings
 PHM_CASES = {
@@ -50,7 +54,9 @@ def test_run_equals_single_steps(torch, case, precision):
     ei = torch.tensor(rng.uniform(0.25, 1.0, (batch, ny, nx)), dtype=dtype, device="cuda") if eps else None
     mi = torch.tensor(rng.uniform(0.5, 1.0, (batch, ny, nx)), dtype=dtype, device="cuda") if mu else None
     s.set_material(ei, mi)
-    if source:
+    if source == "wrap":   # the corner cell, which periodic ghosts of the other sides image
+        s.set_point_source([(ny - 1) * nx + nx - 1], [1.3], 1.0, 0.01, 0.004)
+    elif source:
         s.set_point_source([(ny // 3) * nx + nx // 2], [1.3], 1.0, 0.01, 0.004)
     U0 = torch.tensor(rng.standard_normal((batch, 3, ny, nx)), dtype=dtype, device="cuda")
     t0 = 0.0037
