@@ -382,7 +382,7 @@ __device__ __forceinline__ double lane_fetch(double v, int addr)
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename T, int NC, int NF, bool HAS_EPS, bool HAS_MU, bool BND>
+template <typename T, int NC, int NF, bool HAS_EPS, bool HAS_MU, bool BND, bool PER>
 struct Pair2D {
     using S = Strip2D<T, NC, NF, HAS_EPS, HAS_MU, BND, false>;
     using Row = Row2D<T, NC, NF>;
@@ -402,12 +402,16 @@ struct Pair2D {
     // the row a periodic y side wraps a row to (other rows unchanged)
     __device__ __forceinline__ int wrap_row(int y) const
     {
-        if (!BND || !yper) return y;
+        if (!BND || !PER || !yper) return y;
         const int ny = s.a.ny;
         return ((y % ny) + ny) % ny;
     }
     // the row stage 1 loads for march row y: clamped to the rows it reads, wrapped on periodic sides
-    __device__ __forceinline__ int stage1_row(int y) const { return wrap_row(min(max(y, ylo), yhi)); }
+    __device__ __forceinline__ int stage1_row(int y) const
+    {
+        if constexpr (BND && PER) return wrap_row(min(max(y, ylo), yhi));
+        else return min(max(y, ylo), yhi);
+    }
 
     // One row step of a march whose window holds rows Rs = q-2s, Rc = q-s, Rn = q: the
     // differences of Rc, the horizontal face between Rs and Rc, and from the third step on the
@@ -486,7 +490,11 @@ struct Pair2D {
         const int row = q - 2 * sd;
         double src[NC];
 #pragma unroll
-        for (int k = 0; k < NC; ++k) src[k] = (wrap_row(row) == a.src_row && scol[k] == a.src_col) ? amp : 0.0;
+        for (int k = 0; k < NC; ++k) {
+            // boundary strips: a periodic ghost takes the source of the cell it images
+            if constexpr (BND && PER) src[k] = (wrap_row(row) == a.src_row && scol[k] == a.src_col) ? amp : 0.0;
+            else src[k] = (row == a.src_row && s.gx0 + k == a.src_col) ? amp : 0.0;
+        }
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
 #pragma unroll
@@ -566,7 +574,7 @@ struct Pair2D {
 #pragma unroll
                 for (int k = 0; k < NC; ++k) nv[k][f] = gcol[k] ? got[k] : nv[k][f];
             }
-            if (!yper && (r < 0 || r >= a.ny)) {
+            if (!(PER && yper) && (r < 0 || r >= a.ny)) {
                 // a ghost row: the (mirror) image of one of the last two real rows; y mirror: Ez and
                 // Hy odd, Hx and psi even
                 bool mir, nry;
@@ -650,7 +658,9 @@ struct Pair2D {
 // against 150.0 us per launch on the 4096^2 workload at the compiler's 134 VGPRs and three waves.
 // The kernel with both material maps would spill 42 values and keeps three, as do the PHM fields
 // (four per cell); fp64 needs two.
-template <typename T, int NF, bool HAS_EPS, bool HAS_MU>
+// PER: the grid has a periodic side (a separate instantiation keeps that bookkeeping out of the
+// others: with it the 4096^2 non-reflecting launch took 164.3 against 144.1 us in fp32).
+template <typename T, int NF, bool HAS_EPS, bool HAS_MU, bool PER>
 __global__ __launch_bounds__(STEP2D_BLOCK, sizeof(T) == 8 ? 2 : (NF == 4 || (HAS_EPS && HAS_MU)) ? 3 : 4) void
 cart2d_pair_kernel(Cart2DArgs<T> a)
 {
@@ -680,12 +690,12 @@ cart2d_pair_kernel(Cart2DArgs<T> a)
     const uint32_t vlane = (uint32_t)(NC * lane) * (uint32_t)sizeof(T);
     // periodic y sides: rows beyond them wrap (stage 1 forms the intermediate ghost rows as the
     // step of the rows they image); other sides: the two ghost rows a load can form
-    const bool yper = a.bc[2] == GKS_BC_PERIODIC;
+    const bool yper = PER && a.bc[2] == GKS_BC_PERIODIC;
     const int ylo = yper ? y0 - 4 : max(y0 - 4, -2), yhi = yper ? y1 + 3 : min(y1 + 3, a.ny + 1);
 
     const bool interior = x0 >= 0 && x0 + WAVE * NC - 1 <= a.nx - 1 && y0 - 4 >= 0 && y1 + 3 <= a.ny - 1;
     if (interior) {
-        Pair2D<T, NC, NF, HAS_EPS, HAS_MU, false> p{{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0}};
+        Pair2D<T, NC, NF, HAS_EPS, HAS_MU, false, PER> p{{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0}};
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             p.s.vx[k] = 0;
@@ -697,7 +707,7 @@ cart2d_pair_kernel(Cart2DArgs<T> a)
             p.gcol[k] = false;
             p.scol[k] = gx0 + k;
         }
-        p.yper = yper;
+        p.yper = false;   // interior tiles never reach a side
         p.s.y0 = y0;
         p.s.y1 = y1;
         p.ylo = ylo;
@@ -705,14 +715,14 @@ cart2d_pair_kernel(Cart2DArgs<T> a)
         if (down) p.template run<true>();
         else p.template run<false>();
     } else {
-        Pair2D<T, NC, NF, HAS_EPS, HAS_MU, true> p{{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0}};
+        Pair2D<T, NC, NF, HAS_EPS, HAS_MU, true, PER> p{{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0}};
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int g = gx0 + k;
             // periodic x sides: every column wraps (stage 1 forms the intermediate ghost columns as
             // the step of the columns they image); other sides: columns beyond the two ghost layers
             // feed only halo values that stage 2 never reads
-            const bool xper = a.bc[0] == GKS_BC_PERIODIC;
+            const bool xper = PER && a.bc[0] == GKS_BC_PERIODIC;
             const int gc = xper ? ((g % a.nx) + a.nx) % a.nx : min(max(g, -2), a.nx + 1);
             bool mirx, nrx;
             const int sx = map_axis(gc, a.nx, a.bc[0], a.bc[1], mirx, nrx);
@@ -834,6 +844,22 @@ int launch_cart2d_step(const Cart2DArgs<T> &a, void *stream)
 template int launch_cart2d_step<float>(const Cart2DArgs<float> &, void *);
 template int launch_cart2d_step<double>(const Cart2DArgs<double> &, void *);
 
+template <typename T, bool PER>
+static void launch_pair(const Cart2DArgs<T> &a, dim3 grid, dim3 block, hipStream_t s)
+{
+    if (a.nfields == 4) {
+        if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, true, true, PER>), grid, block, 0, s, a);
+        else if (a.epsinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, true, false, PER>), grid, block, 0, s, a);
+        else if (a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, false, true, PER>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, false, false, PER>), grid, block, 0, s, a);
+        return;
+    }
+    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, true, true, PER>), grid, block, 0, s, a);
+    else if (a.epsinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, true, false, PER>), grid, block, 0, s, a);
+    else if (a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, false, true, PER>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, false, false, PER>), grid, block, 0, s, a);
+}
+
 template <typename T>
 int launch_cart2d_pair(const Cart2DArgs<T> &a, void *stream)
 {
@@ -842,17 +868,10 @@ int launch_cart2d_pair(const Cart2DArgs<T> &a, void *stream)
     const int wpb = STEP2D_BLOCK / WAVE;
     dim3 grid(NBANDS * ((waves + wpb - 1) / wpb)), block(STEP2D_BLOCK);
     hipStream_t s = (hipStream_t)stream;
-    if (a.nfields == 4) {
-        if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, true, true>), grid, block, 0, s, a);
-        else if (a.epsinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, true, false>), grid, block, 0, s, a);
-        else if (a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, false, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, false, false>), grid, block, 0, s, a);
-        return (int)hipGetLastError();
-    }
-    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, true, true>), grid, block, 0, s, a);
-    else if (a.epsinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, true, false>), grid, block, 0, s, a);
-    else if (a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, false, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, false, false>), grid, block, 0, s, a);
+    bool per = false;
+    for (int i = 0; i < 4; ++i) per = per || a.bc[i] == GKS_BC_PERIODIC;
+    if (per) launch_pair<T, true>(a, grid, block, s);
+    else launch_pair<T, false>(a, grid, block, s);
     return (int)hipGetLastError();
 }
 
