@@ -388,8 +388,9 @@ def adjoint_leg(torch):
 
 def limited_leg(torch, wl):
     """The 4096^2 workload with minmod-limited slopes (the step for discontinuous data): per-launch
-    time of the limited step kernel against the same algorithmic bytes."""
-    out = {"workload": "tm_dielectric_nr 4096x4096 with limiter = minmod (step kernel only, 100 timed launches)"}
+    times of the limited single-step and paired kernels against the same algorithmic bytes."""
+    out = {"workload": "tm_dielectric_nr 4096x4096 with limiter = minmod (single-step kernel, 100 timed launches; "
+                       "the paired kernel, 50 launches)"}
     ncell = N * N
     for prec in ("fp32", "fp64"):
         s, U, ei = make(torch, wl, prec, limiter="minmod")

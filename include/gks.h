@@ -203,10 +203,10 @@ gks_status gks_step(gks_ctx *ctx, const void *U_in, void *U_out, double t_n);
  * the failing one (at most energy_every steps past it), the records up to that one are written
  * and the later entries of energy_host are left untouched; the error text names the batch item
  * and the step of the failing record.
- * On 2D Cartesian grids with TM fields (GKS_TM2D or GKS_TM2D_PHM), no limiter and at most one
- * source cell, gks_run advances two steps per kernel launch (the fields are read and written
- * once for both); the result equals that of nsteps gks_step calls at the same times, bit for
- * bit.
+ * On 2D Cartesian grids (GKS_TM2D, with or without the limiter, or GKS_TM2D_PHM) with at most
+ * one source cell, gks_run advances two steps per kernel launch (the fields are read and
+ * written once for both); the result equals that of nsteps gks_step calls at the same times,
+ * bit for bit.
  */
 gks_status gks_run(gks_ctx *ctx, void *U, int64_t nsteps, double t0, double *energy_host);
 

@@ -926,8 +926,8 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
             return bail(fail(x, GKS_ENOMEM, "cannot allocate the tile table"));
         const int e = hipMemcpy(x->d_tiles, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice);
         if (e) return bail(hip_fail(x, e, "tile table upload"));
-        // the paired kernel: TM fields (with or without psi), no limiter
-        if ((x->model == GKS_TM2D || x->model == GKS_TM2D_PHM) && x->limiter == GKS_LIMITER_NONE) {
+        // the paired kernel: TM fields (with or without psi; the limiter, TM only)
+        if (x->model == GKS_TM2D || x->model == GKS_TM2D_PHM) {
             const int ntx2 = (int)((x->n[0] + cart2d_pair_tile_x(x->prec) - 1) / cart2d_pair_tile_x(x->prec));
             const std::vector<int32_t> tab2 =
                 cart2d_pair_tile_table((int)x->n[1], (int)x->batch, ntx2, x->pair_tiles_per_band);

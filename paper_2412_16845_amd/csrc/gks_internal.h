@@ -197,7 +197,7 @@ struct Cart2DAdjArgs {
 
 // Launchers (defined in the .hip files).  Return a hipError_t as int.
 template <typename T> int launch_cart2d_step(const Cart2DArgs<T> &a, void *stream);
-// Two steps in one launch (TM fields with or without psi, no limiter, at most one source cell;
+// Two steps in one launch (TM fields with or without psi or the limiter, at most one source cell;
 // a.tiles from cart2d_pair_tile_table, a.ntx from cart2d_pair_tile_x).
 template <typename T> int launch_cart2d_pair(const Cart2DArgs<T> &a, void *stream);
 // Adjoint of one 2D step.  Scratch (device), over the npos = adjoint_ring_positions(nx, ny)

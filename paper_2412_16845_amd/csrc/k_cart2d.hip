@@ -340,13 +340,14 @@ struct Strip2D {
 };
 
 // ------------------------------------------------------------------ two steps per launch
-// The paired kernel runs two consecutive steps of the TM fields (with or without psi) in one
-// march, so that the fields are read and written once per two steps.  Stage 1 is the march
-// above over a strip with four halo columns and a tile widened by two rows on each side.  Every row it finishes (the
-// state after the first step, rounded to the storage type as a stored state would be) enters
-// stage 2, a second march of the same form that takes its rows from registers instead of
-// memory and writes the state after the second step.  Both stages do the single-step kernel's
-// arithmetic in its order, so the two kernels give the same results bit for bit.
+// The paired kernel runs two consecutive steps of the TM fields (with or without psi, with or
+// without the limiter) in one march, so that the fields are read and written once per two steps.
+// Stage 1 is the march above over a strip with four halo columns and a tile widened by two rows
+// on each side.  Every row it finishes (the state after the first step, rounded to the storage
+// type as a stored state would be) enters stage 2, a second march of the same form that takes
+// its rows from registers instead of memory and writes the state after the second step.  Both
+// stages do the single-step kernel's arithmetic in its order, so the two kernels give the same
+// results bit for bit.
 // Ghost values of the intermediate state behind a non-reflecting or PEC side are formed from its
 // own cells, as the loads form them for a stored state: along x from the boundary column held
 // by another lane of the same wave, along y from the last two rows stage 1 finished (so a tile
@@ -382,9 +383,9 @@ __device__ __forceinline__ double lane_fetch(double v, int addr)
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename T, int NC, int NF, bool HAS_EPS, bool HAS_MU, bool BND, bool PER>
+template <typename T, int NC, int NF, bool HAS_EPS, bool HAS_MU, bool BND, bool PER, bool LIM>
 struct Pair2D {
-    using S = Strip2D<T, NC, NF, HAS_EPS, HAS_MU, BND, false>;
+    using S = Strip2D<T, NC, NF, HAS_EPS, HAS_MU, BND, LIM>;
     using Row = Row2D<T, NC, NF>;
     using FS = Fields2D<NF>;
     using OpT = typename FS::template Op<T>;
@@ -425,16 +426,31 @@ struct Pair2D {
         const Cart2DArgs<T> &a = s.a;
         const OpT *ops = (const OpT *)a.ops;
         const auto opy = scalar_ptr_after(ops + OPS0 + 1, fyP[0][0]);
+        T right[NC][NF], left[NC][NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const T rnext = from_right(Rc.u[0][f]);
             const T lprev = from_left(Rc.u[NC - 1][f]);
 #pragma unroll
             for (int k = 0; k < NC; ++k) {
-                const T right = (k + 1 < NC) ? Rc.u[k + 1 < NC ? k + 1 : 0][f] : rnext;
-                const T left = (k > 0) ? Rc.u[k > 0 ? k - 1 : 0][f] : lprev;
-                Dc[k][f] = right - left;
+                right[k][f] = (k + 1 < NC) ? Rc.u[k + 1 < NC ? k + 1 : 0][f] : rnext;
+                left[k][f] = (k > 0) ? Rc.u[k > 0 ? k - 1 : 0][f] : lprev;
+                Dc[k][f] = right[k][f] - left[k][f];
                 Dc[k][NF + f] = DN ? Rs.u[k][f] - Rn.u[k][f] : Rn.u[k][f] - Rs.u[k][f];
+            }
+        }
+        if constexpr (LIM) {
+            // limited slopes, as in the single-step kernel
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                const T(&c)[NF] = Rc.u[k];
+                const T(&up)[NF] = DN ? Rs.u[k] : Rn.u[k];
+                const T(&dn)[NF] = DN ? Rn.u[k] : Rs.u[k];
+                limit_pair(right[k][0] - c[0], right[k][2] - c[2], c[0] - left[k][0], c[2] - left[k][2], Dc[k][0],
+                           Dc[k][2]);
+                Dc[k][1] = T(2) * minmod(right[k][1] - c[1], c[1] - left[k][1]);
+                limit_pair(up[0] - c[0], up[1] - c[1], c[0] - dn[0], c[1] - dn[1], Dc[k][NF + 0], Dc[k][NF + 1]);
+                Dc[k][NF + 2] = T(2) * minmod(up[2] - c[2], c[2] - dn[2]);
             }
         }
         if (i < 1) return false;
@@ -659,9 +675,10 @@ struct Pair2D {
 // The kernel with both material maps would spill 42 values and keeps three, as do the PHM fields
 // (four per cell); fp64 needs two.
 // PER: the grid has a periodic side (a separate instantiation keeps that bookkeeping out of the
-// others: with it the 4096^2 non-reflecting launch took 164.3 against 144.1 us in fp32).
-template <typename T, int NF, bool HAS_EPS, bool HAS_MU, bool PER>
-__global__ __launch_bounds__(STEP2D_BLOCK, sizeof(T) == 8 ? 2 : (NF == 4 || (HAS_EPS && HAS_MU)) ? 3 : 4) void
+// others: with it the 4096^2 non-reflecting launch took 164.3 against 144.1 us in fp32).  LIM:
+// minmod-limited slopes (TM fields only).
+template <typename T, int NF, bool HAS_EPS, bool HAS_MU, bool PER, bool LIM>
+__global__ __launch_bounds__(STEP2D_BLOCK, sizeof(T) == 8 ? 2 : (NF == 4 || LIM || (HAS_EPS && HAS_MU)) ? 3 : 4) void
 cart2d_pair_kernel(Cart2DArgs<T> a)
 {
     constexpr int NC = pair_cols_per_lane<T>();
@@ -695,7 +712,7 @@ cart2d_pair_kernel(Cart2DArgs<T> a)
 
     const bool interior = x0 >= 0 && x0 + WAVE * NC - 1 <= a.nx - 1 && y0 - 4 >= 0 && y1 + 3 <= a.ny - 1;
     if (interior) {
-        Pair2D<T, NC, NF, HAS_EPS, HAS_MU, false, PER> p{{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0}};
+        Pair2D<T, NC, NF, HAS_EPS, HAS_MU, false, PER, LIM> p{{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0}};
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             p.s.vx[k] = 0;
@@ -715,7 +732,7 @@ cart2d_pair_kernel(Cart2DArgs<T> a)
         if (down) p.template run<true>();
         else p.template run<false>();
     } else {
-        Pair2D<T, NC, NF, HAS_EPS, HAS_MU, true, PER> p{{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0}};
+        Pair2D<T, NC, NF, HAS_EPS, HAS_MU, true, PER, LIM> p{{a, rU, rE, rM, rO, fbytes, vlane, x0, gx0}};
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int g = gx0 + k;
@@ -844,34 +861,42 @@ int launch_cart2d_step(const Cart2DArgs<T> &a, void *stream)
 template int launch_cart2d_step<float>(const Cart2DArgs<float> &, void *);
 template int launch_cart2d_step<double>(const Cart2DArgs<double> &, void *);
 
-template <typename T, bool PER>
+template <typename T, bool PER, bool LIM>
 static void launch_pair(const Cart2DArgs<T> &a, dim3 grid, dim3 block, hipStream_t s)
 {
-    if (a.nfields == 4) {
-        if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, true, true, PER>), grid, block, 0, s, a);
-        else if (a.epsinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, true, false, PER>), grid, block, 0, s, a);
-        else if (a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, false, true, PER>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, false, false, PER>), grid, block, 0, s, a);
-        return;
+    if constexpr (!LIM) {
+        if (a.nfields == 4) {
+            if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, true, true, PER, false>), grid, block, 0, s, a);
+            else if (a.epsinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, true, false, PER, false>), grid, block, 0, s, a);
+            else if (a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, false, true, PER, false>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((cart2d_pair_kernel<T, 4, false, false, PER, false>), grid, block, 0, s, a);
+            return;
+        }
     }
-    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, true, true, PER>), grid, block, 0, s, a);
-    else if (a.epsinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, true, false, PER>), grid, block, 0, s, a);
-    else if (a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, false, true, PER>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, false, false, PER>), grid, block, 0, s, a);
+    if (a.epsinv && a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, true, true, PER, LIM>), grid, block, 0, s, a);
+    else if (a.epsinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, true, false, PER, LIM>), grid, block, 0, s, a);
+    else if (a.muinv) hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, false, true, PER, LIM>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((cart2d_pair_kernel<T, 3, false, false, PER, LIM>), grid, block, 0, s, a);
 }
 
 template <typename T>
 int launch_cart2d_pair(const Cart2DArgs<T> &a, void *stream)
 {
-    if ((a.nfields != 3 && a.nfields != 4) || a.limiter) return (int)hipErrorInvalidValue;
+    if (a.nfields != 3 && a.nfields != 4) return (int)hipErrorInvalidValue;
+    if (a.limiter && a.nfields != 3) return (int)hipErrorInvalidValue;   // the host refuses PHM + limiter
     const int waves = a.ntx * a.nty;
     const int wpb = STEP2D_BLOCK / WAVE;
     dim3 grid(NBANDS * ((waves + wpb - 1) / wpb)), block(STEP2D_BLOCK);
     hipStream_t s = (hipStream_t)stream;
     bool per = false;
     for (int i = 0; i < 4; ++i) per = per || a.bc[i] == GKS_BC_PERIODIC;
-    if (per) launch_pair<T, true>(a, grid, block, s);
-    else launch_pair<T, false>(a, grid, block, s);
+    if (a.limiter) {
+        if (per) launch_pair<T, true, true>(a, grid, block, s);
+        else launch_pair<T, false, true>(a, grid, block, s);
+    } else {
+        if (per) launch_pair<T, true, false>(a, grid, block, s);
+        else launch_pair<T, false, false>(a, grid, block, s);
+    }
     return (int)hipGetLastError();
 }
 

@@ -102,3 +102,36 @@ def test_phm_run_equals_single_steps(torch, case, precision):
     torch.cuda.synchronize()
     print(f"{case} {precision}: run vs single steps, max |diff| = {float((A - B).abs().max()):.3e}")
     assert bool(torch.equal(A, B))
+
+
+# minmod-limited slopes: name -> grid, sides, batch, eps, source, steps
+LIM_CASES = {
+    "lim_nr_source": ((150, 60), (NR,) * 4, 1, True, True, 7),
+    "lim_pec_periodic": ((64, 45), (PEC, PEC, PER, PER), 2, True, False, 6),
+}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", list(LIM_CASES))
+def test_limited_run_equals_single_steps(torch, case, precision):
+    from paper_2412_16845_amd.gks import Solver
+    (nx, ny), bc, batch, eps, source, nsteps = LIM_CASES[case]
+    rng = np.random.default_rng(70 + list(LIM_CASES).index(case) + 100 * (precision == "fp32"))
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    s = Solver("cart2d", n=(nx, ny), bc=bc, precision=precision, batch=batch, cfl=0.5, tau_over_dt=0.01,
+               limiter="minmod")
+    ei = torch.tensor(rng.uniform(0.25, 1.0, (batch, ny, nx)), dtype=dtype, device="cuda") if eps else None
+    s.set_material(ei, None)
+    if source:
+        s.set_point_source([(ny // 2) * nx + nx // 4], [1.1], 1.0, 0.01, 0.004)
+    # discontinuous data, where the limiter acts
+    U0 = torch.tensor(np.sign(rng.standard_normal((batch, 3, ny, nx))), dtype=dtype, device="cuda")
+    A = U0.clone()
+    s.run(A, nsteps, 0.001)
+    B = U0.clone()
+    for k in range(nsteps):
+        B = s.step(B, t=0.001 + k * s.dt)
+    torch.cuda.synchronize()
+    print(f"{case} {precision}: run vs single steps, max |diff| = {float((A - B).abs().max()):.3e}")
+    assert bool(torch.equal(A, B))
