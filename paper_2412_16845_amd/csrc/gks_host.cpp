@@ -295,7 +295,7 @@ std::vector<int32_t> gks::cart2d_tile_table(int ny, int batch, int precision, in
     return out;
 }
 
-std::vector<int32_t> gks::cart2d_pair_tile_table(int ny, int batch, int ntx, int32_t &tiles_per_band)
+std::vector<int32_t> gks::cart2d_pair_tile_table(int ny, int batch, int precision, int ntx, int32_t &tiles_per_band)
 {
     // The single-step table's bands and tile heights, with two constraints of the paired
     // kernel: a tile reads the intermediate state two rows beyond each end, so a cut between
@@ -304,8 +304,10 @@ std::vector<int32_t> gks::cart2d_pair_tile_table(int ny, int batch, int ntx, int
     // A tile's stage 1 forms four rows more than it writes, so the paired kernel takes taller
     // tiles: on 4096^2 (fp32 / fp64 us per launch) tall 32 153.7 / 238.0, 48 150.4 / 232.3,
     // 64 150.3 / 230.5, 96 163.3 / 246.0, 128 174.8 / 234.7; tall 64 with short 16 150.0 / 226.3.
+    // A later sweep (short 16): tall 56, 64, 72: 147.7, 143.8, 140.3 / 222.8, 226.4, 225.3; short
+    // 24, 32: 143.8, 149.9 / 225.8, 232.0; short fraction 0.2, 0.4: 164.9, 142.7 / 246.3, 230.2.
 #ifndef GKS_PAIR_TILE_TALL
-#define GKS_PAIR_TILE_TALL 64
+#define GKS_PAIR_TILE_TALL ((precision == GKS_FP64) ? 56 : 72)
 #endif
 #ifndef GKS_PAIR_TILE_SHORT
 #define GKS_PAIR_TILE_SHORT 16
@@ -930,7 +932,7 @@ extern "C" gks_status gks_init_mesh(const gks_mesh_desc *m, const gks_params *p,
         if (x->model == GKS_TM2D || x->model == GKS_TM2D_PHM) {
             const int ntx2 = (int)((x->n[0] + cart2d_pair_tile_x(x->prec) - 1) / cart2d_pair_tile_x(x->prec));
             const std::vector<int32_t> tab2 =
-                cart2d_pair_tile_table((int)x->n[1], (int)x->batch, ntx2, x->pair_tiles_per_band);
+                cart2d_pair_tile_table((int)x->n[1], (int)x->batch, x->prec, ntx2, x->pair_tiles_per_band);
             if (!tab2.empty()) {
                 if (hipMalloc((void **)&x->d_pair_tiles, tab2.size() * sizeof(int32_t)) != hipSuccess)
                     return bail(fail(x, GKS_ENOMEM, "cannot allocate the paired tile table"));

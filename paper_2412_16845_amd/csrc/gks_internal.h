@@ -236,7 +236,7 @@ std::vector<int32_t> cart2d_tile_table(int ny, int batch, int precision, int ntx
 // first tile row of every batch item marches down and the last up, and every tile keeps two
 // rows away from a side it does not touch.  Empty when the grid is too small for it.
 int cart2d_pair_tile_x(int precision);
-std::vector<int32_t> cart2d_pair_tile_table(int ny, int batch, int ntx, int32_t &tiles_per_band);
+std::vector<int32_t> cart2d_pair_tile_table(int ny, int batch, int precision, int ntx, int32_t &tiles_per_band);
 
 // Energy: partial sums per (batch, block) then a fixed-order final sum; all FP64.
 // Fields [0, nE) are E (weight eps), [nE, nE + nH) are H (weight mu), the rest potentials (1).
