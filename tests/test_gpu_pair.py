@@ -26,6 +26,9 @@ CASES = {
     "periodic_y_pec_x": ((90, 33), (PEC, PEC, PER, PER), 2, True, True, True, 7, 0),
     "periodic_both_small": ((3, 9), (PER,) * 4, 1, True, False, True, 5, 0),
     "periodic_source_at_wrap": ((61, 40), (PER,) * 4, 1, True, False, "wrap", 6, 0),
+    # short items in a batch: band cuts land one row from a side and move
+    "short_items_batch": ((33, 11), (NR, PEC, PEC, NR), 3, True, False, True, 5, 0),
+    "rows_9_pec": ((120, 9), (PEC,) * 4, 2, False, True, False, 4, 0),
 }
 # the PHM fields (Ez, Hx, Hy, psi): name -> grid, sides, batch, eps, mu, source, steps, couplings
 PHM_CASES = {
